@@ -1,0 +1,233 @@
+/*
+ * cc.h -- exact connected-component labelling of undirected int32 edge lists on
+ * AMD Instinct MI355X (gfx950).  C ABI of libccmi.so.
+ *
+ * Problem (Section III-A.1, Notations): given an undirected graph G = (V, E)
+ * with n = |V| vertices and m = |E| edges, label every vertex with its
+ * connected component; two vertices share a component iff a path joins them
+ * (Section I).  The label written for a vertex is the smallest vertex id of its
+ * component (the canonical partition id of Fig. 1(b)), so the output is unique
+ * and independent of the route, the thread schedule and the edge order.
+ *
+ * Method: the hybrid of Algorithm 2 (Section III-B).  An optional BFS from one
+ * seed labels the dominant component and removes its edges; the
+ * Shiloach-Vishkin style iteration of Section III-A (hook each partition to its
+ * minimum neighbour, pointer-jump, drop finished work) labels the rest.  The
+ * BFS step runs only when the degree distribution is classed as scale-free
+ * (power-law fit, K-S statistic below tau = 0.05, Section V) or when a learned
+ * router picks it.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named as device pointers must be device memory of the current
+ *    HIP device (e.g. torch tensor storage).  Host pointers are marked "host".
+ *  - The caller owns every array it passes; inputs are never modified; outputs
+ *    are written only on success (on CC_ERANGE the labels are undefined).
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All device
+ *    work is enqueued on it.  Calls return after their results are complete
+ *    (they read small device counters to drive their loops), i.e. they are
+ *    host-synchronous with respect to `stream`.
+ *  - Scratch memory is taken from a per-device workspace that the library
+ *    grows on demand with hipMalloc and keeps until cc_release_workspace() or
+ *    process exit.  Calls that overlap on one device from several host threads
+ *    are serialised by an internal lock.
+ *  - Return value: CC_OK (0) or a negative CC_E* code; cc_last_error() then
+ *    returns a message (thread-local).  Nothing is thrown across the ABI.
+ */
+#ifndef CCMI_CC_H
+#define CCMI_CC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CC_VERSION 10000 /* 1.0.0 */
+
+/* ------------------------------------------------------------ status codes */
+#define CC_OK 0
+#define CC_EINVAL (-1)     /* bad argument: negative size, NULL with non-zero size, bad offsets/options */
+#define CC_ERANGE (-2)     /* an edge endpoint lies outside [0, n) (detected on the device) */
+#define CC_ENOMEM (-3)     /* device or pinned-host allocation failed */
+#define CC_EHIP (-4)       /* a HIP runtime call failed; message has hipGetErrorString */
+#define CC_EINTERNAL (-5)  /* pass cap reached (cc_options.max_passes) or an internal invariant failed */
+#define CC_ENOROUTER (-6)  /* CC_ROUTE_ROUTER requested but no router weights are loaded */
+
+/* ------------------------------------------------------------------ routes */
+#define CC_ROUTE_AUTO 0       /* router if weights are loaded, else the degree heuristic */
+#define CC_ROUTE_HEURISTIC 1  /* Algorithm 2: K-S statistic < tau -> BFS + SV, else SV */
+#define CC_ROUTE_ROUTER 2     /* argmax of the MLP router's three logits */
+#define CC_ROUTE_SV 3         /* force R1: plain SV, compaction after every pass */
+#define CC_ROUTE_BFS_SV 4     /* force R0: BFS from the max-degree vertex, then SV on the rest */
+#define CC_ROUTE_SV_THETA 5   /* force R2: SV with threshold-gated compaction */
+
+/* route ids reported in cc_stats.route and used as router classes */
+#define CC_R0_BFS_SV 0
+#define CC_R1_SV 1
+#define CC_R2_SV_THETA 2
+
+typedef struct cc_options {
+    int32_t route;       /* CC_ROUTE_* */
+    int32_t max_passes;  /* 0: no cap; else CC_EINTERNAL once this many SV passes ran without converging */
+    double tau;          /* K-S threshold; <= 0 selects 0.05 (Section V, Table "tab:ks_stat") */
+    double theta;        /* R2: compact after a pass only if >= theta of its edges were finished; <= 0 selects 0.25 */
+    int32_t reserved[8]; /* must be zero */
+} cc_options;
+
+typedef struct cc_stats {
+    int32_t route;                /* route taken: CC_R0_BFS_SV, CC_R1_SV or CC_R2_SV_THETA */
+    int32_t sv_passes;            /* SV passes over active edges */
+    int32_t bfs_levels;           /* BFS levels expanded (R0) */
+    int32_t bfs_bottom_up_levels; /* of which bottom-up */
+    int32_t bfs_seed;             /* BFS seed (max degree, smallest id on ties), -1 if none */
+    int32_t bfs_label;            /* minimum id of the BFS component, -1 if none */
+    int64_t bfs_visited;          /* vertices reached by the BFS */
+    int64_t bfs_edges_examined;   /* adjacency entries read by the BFS */
+    int64_t edges_after_filter;   /* edges left for SV after the BFS step */
+    int64_t max_degree;           /* when the degree pass ran, else -1 */
+    double ks_statistic;          /* K-S statistic when computed, else NaN */
+    double ks_alpha;              /* fitted power-law exponent, else NaN */
+    int64_t ks_dmin;              /* fitted lower cutoff, else 0 */
+    float router_logits[3];       /* when the router ran, else 0 */
+    int32_t reserved0;
+    int64_t active_edges[64];     /* active edges entering SV pass i (first 64 passes) */
+    int64_t hooks_total;          /* successful hooks over all passes */
+    double ms_predict;            /* degree pass + histograms + decision */
+    double ms_csr;                /* CSR build (R0) */
+    double ms_bfs;                /* BFS levels (R0) */
+    double ms_filter;             /* BFS label + edge filter (R0) */
+    double ms_sv;                 /* SV passes, shortcuts and finalize */
+    double ms_total;              /* whole call, device time between first and last event */
+    double algorithmic_bytes;     /* bytes the method must move (cost model, see DESIGN) */
+} cc_stats;
+
+/* Fills *opt with the defaults (route AUTO, no cap, tau 0.05, theta 0.25). */
+void cc_default_options(cc_options* opt);
+
+int cc_version(void);
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char* cc_last_error(void);
+
+/* Label the components of one graph.
+ *  u, v       device, int32[m]: edge i joins u[i] and v[i]; ids in [0, n).
+ *             Self-loops and repeated edges are allowed (they change nothing).
+ *  m          number of edges, >= 0.
+ *  n          number of vertices, >= 0; vertices in no edge get label x.
+ *  labels     device, int32[n], written: labels[x] = min id of x's component.
+ *  stream     hipStream_t or NULL.
+ * Errors: CC_EINVAL (m < 0, n < 0, m > 0 with n == 0, NULL with non-zero size),
+ * CC_ERANGE, CC_ENOMEM, CC_EHIP. */
+int cc_label(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream);
+
+/* cc_label with options (NULL = defaults) and statistics (NULL = not wanted). */
+int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream,
+                const cc_options* opt, cc_stats* stats);
+
+/* Label G independent graphs in one call (one persistent launch for the
+ * SV iteration over all of them).
+ *  u, v       device, int32: graph g owns edges [edge_off[g], edge_off[g+1]);
+ *             ids are graph-local, in [0, n_g) with n_g = vert_off[g+1] - vert_off[g].
+ *  edge_off   device, int64[G+1], edge_off[0] = 0, non-decreasing.
+ *  vert_off   device, int64[G+1], vert_off[0] = 0, non-decreasing, total < 2^31.
+ *  labels     device, int32[vert_off[G]]: graph-local labels (min local id).
+ * Errors: CC_EINVAL (G < 0, bad offsets: checked on the device), CC_ERANGE,
+ * CC_ENOMEM, CC_EHIP. */
+int cc_label_batched(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
+                     int32_t G, int32_t* labels, void* stream);
+
+/* Batched statistics: passes of the persistent loop and tile size used. */
+typedef struct cc_batch_stats {
+    int32_t passes;
+    int32_t tile_edges;
+    int32_t blocks;
+    int32_t reserved0;
+    int64_t total_edges;
+    int64_t total_vertices;
+    double ms_total;
+} cc_batch_stats;
+
+/* cc_label_batched with a tile size (0 = autotuned/default) and statistics (may be NULL). */
+int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
+                        int32_t G, int32_t* labels, void* stream, int32_t tile_edges, cc_batch_stats* stats);
+
+/* ------------------------------------------------------------------ router */
+/* Number of float32 parameters of the 66 -> 64 -> 64 -> 3 MLP: W1[64][66], b1[64],
+ * W2[64][64], b2[64], W3[3][64], b3[3], in that order, row-major [out][in]. */
+#define CC_ROUTER_NPARAMS (64 * 66 + 64 + 64 * 64 + 64 + 3 * 64 + 3)
+#define CC_ROUTER_NFEATURES 66
+
+/* Load router weights from a text file: CC_ROUTER_NPARAMS decimal floats
+ * separated by white space (lines starting with '#' are comments).  Returns
+ * CC_EINVAL if the file cannot be read or has the wrong count. */
+int cc_router_load(const char* path);
+/* Set router weights from host memory (float32[CC_ROUTER_NPARAMS]); NULL unloads. */
+int cc_router_set(const float* host_params);
+int cc_router_loaded(void);
+
+/* ---------------------------------------------------------- step entry points
+ * The individual steps of the path, exposed so each can be checked on its own.
+ * All pointers are device pointers unless marked "host". */
+
+/* Degree (Section III-B, Degree_Distribution): deg[x] = number of edge endpoints
+ * equal to x (each undirected edge counts for both ends, a self-loop twice).
+ * deg: int32[n], written.  Returns CC_ERANGE if an id is outside [0, n). */
+int cc_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* deg, void* stream);
+
+/* Degree histograms: hist64[64] (half-octave log bins: bin 0 = degree 0, degree
+ * d >= 1 with k = floor(log2 d) goes to 1 + 2k, plus 1 if k >= 1 and bit k-1 of
+ * d is set), histx[4096] (exact counts for d < 4096), tail[] (every degree
+ * >= 4096, unordered, at most tail_cap written), *tail_count (host, total
+ * number of such vertices) and *argmax (host: vertex of maximum degree,
+ * smallest id on ties; -1 if n == 0).  hist64/histx are int64 device arrays. */
+int cc_degree_histograms(const int32_t* deg, int32_t n, int64_t* hist64, int64_t* histx, int32_t* tail,
+                         int64_t tail_cap, int64_t* tail_count, int32_t* argmax, void* stream);
+
+/* Discrete power-law fit and K-S statistic of a degree distribution given as
+ * host arrays histx[4096] (counts of degrees below 4096) and tail[ntail] (the
+ * degrees >= 4096).  Clauset-Shalizi-Newman: for each candidate cutoff d_min
+ * (distinct degree with >= 50 vertices and >= 2 distinct values at or above
+ * it) alpha is the maximum-likelihood exponent on (1, 10] and D the largest
+ * CDF gap; the result is the smallest D.  out[0] = D (+inf if no candidate),
+ * out[1] = alpha, out[2] = d_min, out[3] = tail size, out[4] = candidates.
+ * Host-only, no device work. */
+int cc_powerlaw_ks(const int64_t* histx, const int32_t* tail, int64_t ntail, double* out);
+
+/* CSR of the undirected graph (both directions of every edge, self-loops
+ * twice): off: int64[n+1] = exclusive scan of deg; adj: int32[2m] neighbour
+ * lists, each vertex's entries in an unspecified order. */
+int cc_csr(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const int32_t* deg, int64_t* off,
+           int32_t* adj, void* stream);
+
+/* Direction-optimising BFS from seed over a CSR (off, adj) with n vertices.
+ * visited: uint32[(n+31)/32] bitmap, written (bit x%32 of word x/32).
+ * *levels and *bottom_up (host, may be NULL) receive level counts. */
+int cc_bfs(const int64_t* off, const int32_t* adj, int32_t n, int64_t nadj, int32_t seed, uint32_t* visited,
+           int32_t* levels, int32_t* bottom_up, void* stream);
+
+/* BFS component label and edge filter (Algorithm 2, filter step): labels[x] =
+ * min visited id for visited x, x otherwise; (fu, fv) = the edges whose first
+ * endpoint is not visited, in an unspecified order; *m_kept and *label (host)
+ * receive their count and the component label (-1 if nothing is visited). */
+int cc_bfs_filter(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const uint32_t* visited,
+                  int32_t* labels, int32_t* fu, int32_t* fv, int64_t* m_kept, int32_t* label, void* stream);
+
+/* Router network on the device: logits[batch][3] for features x[batch][66]
+ * (params as in CC_ROUTER_NPARAMS, device float32). */
+int cc_mlp_forward(const float* params, const float* x, int32_t batch, float* logits, void* stream);
+
+/* One SGD step of the router on a batch: mean softmax cross-entropy over
+ * (x[batch][66], y[batch] in {0,1,2}); params updated in place with step lr;
+ * grads (device float32[CC_ROUTER_NPARAMS], may be NULL) receives the gradient;
+ * *loss (host, may be NULL) the batch loss before the step. */
+int cc_mlp_sgd_step(float* params, const float* x, const int32_t* y, int32_t batch, float lr, float* grads,
+                    float* loss, void* stream);
+
+/* Free the calling device's workspace. */
+int cc_release_workspace(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCMI_CC_H */

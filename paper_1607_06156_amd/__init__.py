@@ -1,0 +1,297 @@
+"""Exact connected-component labelling on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over ``libccmi.so`` (C ABI declared in ``include/cc.h``).
+This module only marshals arguments: torch tensors provide device memory and
+the current HIP stream; every step of the computation runs in the library's
+HIP kernels.  If the library is not built the calls raise -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccmi.so")
+
+ROUTE_AUTO, ROUTE_HEURISTIC, ROUTE_ROUTER, ROUTE_SV, ROUTE_BFS_SV, ROUTE_SV_THETA = range(6)
+R0_BFS_SV, R1_SV, R2_SV_THETA = 0, 1, 2
+ROUTE_NAMES = {R0_BFS_SV: "bfs+sv", R1_SV: "sv", R2_SV_THETA: "sv-theta"}
+_ROUTE_ARG = {None: ROUTE_AUTO, "auto": ROUTE_AUTO, "heuristic": ROUTE_HEURISTIC, "router": ROUTE_ROUTER,
+              "sv": ROUTE_SV, "bfs+sv": ROUTE_BFS_SV, "bfs": ROUTE_BFS_SV, "sv-theta": ROUTE_SV_THETA}
+
+ROUTER_NPARAMS = 64 * 66 + 64 + 64 * 64 + 64 + 3 * 64 + 3
+ROUTER_NFEATURES = 66
+
+CC_OK, CC_EINVAL, CC_ERANGE, CC_ENOMEM, CC_EHIP, CC_EINTERNAL, CC_ENOROUTER = 0, -1, -2, -3, -4, -5, -6
+_ERRNAMES = {-1: "CC_EINVAL", -2: "CC_ERANGE", -3: "CC_ENOMEM", -4: "CC_EHIP", -5: "CC_EINTERNAL",
+             -6: "CC_ENOROUTER"}
+
+
+class CCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("route", ctypes.c_int32), ("max_passes", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("theta", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("route", ctypes.c_int32), ("sv_passes", ctypes.c_int32), ("bfs_levels", ctypes.c_int32),
+                ("bfs_bottom_up_levels", ctypes.c_int32), ("bfs_seed", ctypes.c_int32),
+                ("bfs_label", ctypes.c_int32), ("bfs_visited", ctypes.c_int64),
+                ("bfs_edges_examined", ctypes.c_int64), ("edges_after_filter", ctypes.c_int64),
+                ("max_degree", ctypes.c_int64), ("ks_statistic", ctypes.c_double), ("ks_alpha", ctypes.c_double),
+                ("ks_dmin", ctypes.c_int64), ("router_logits", ctypes.c_float * 3), ("reserved0", ctypes.c_int32),
+                ("active_edges", ctypes.c_int64 * 64), ("hooks_total", ctypes.c_int64),
+                ("ms_predict", ctypes.c_double), ("ms_csr", ctypes.c_double), ("ms_bfs", ctypes.c_double),
+                ("ms_filter", ctypes.c_double), ("ms_sv", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("algorithmic_bytes", ctypes.c_double)]
+
+    def to_dict(self) -> dict:
+        d = {}
+        for name, _ in self._fields_:
+            if name.startswith("reserved"):
+                continue
+            val = getattr(self, name)
+            if name == "active_edges":
+                val = [int(x) for x in val][: max(0, min(self.sv_passes, 64))]
+            elif name == "router_logits":
+                val = [float(x) for x in val]
+            d[name] = val
+        d["route_name"] = ROUTE_NAMES.get(self.route, "none")
+        return d
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("tile_edges", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("total_edges", ctypes.c_int64),
+                ("total_vertices", ctypes.c_int64), ("ms_total", ctypes.c_double)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def lib():
+    """Load libccmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build()); no fallback exists")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "cc_version": (ctypes.c_int, []),
+            "cc_last_error": (ctypes.c_char_p, []),
+            "cc_default_options": (None, [ctypes.POINTER(Options)]),
+            "cc_label": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP]),
+            "cc_label_ex": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP,
+                                           ctypes.POINTER(Options), ctypes.POINTER(Stats)]),
+            "cc_label_batched": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP]),
+            "cc_label_batched_ex": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
+                                                   ctypes.POINTER(BatchStats)]),
+            "cc_router_load": (ctypes.c_int, [ctypes.c_char_p]),
+            "cc_router_set": (ctypes.c_int, [_VP]),
+            "cc_router_loaded": (ctypes.c_int, []),
+            "cc_degree": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP]),
+            "cc_degree_histograms": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_int64,
+                                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                                    _VP]),
+            "cc_powerlaw_ks": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP]),
+            "cc_csr": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP, _VP, _VP]),
+            "cc_bfs": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _VP,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _VP]),
+            "cc_bfs_filter": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP, _VP, _VP,
+                                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), _VP]),
+            "cc_mlp_forward": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
+            "cc_mlp_sgd_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_float, _VP,
+                                               ctypes.POINTER(ctypes.c_float), _VP]),
+            "cc_release_workspace": (ctypes.c_int, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != CC_OK:
+        raise CCError(rc, lib().cc_last_error().decode(errors="replace"))
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return _VP(t.data_ptr() if t.numel() else 0)
+
+
+def _stream():
+    return _VP(torch.cuda.current_stream().cuda_stream)
+
+
+def version() -> int:
+    return lib().cc_version()
+
+
+def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tensor | None = None,
+          stats: bool = False, max_passes: int = 0, tau: float = 0.05, theta: float = 0.25):
+    """labels[x] = min vertex id of x's component; (u[i], v[i]) are undirected edges."""
+    m = int(u.numel())
+    if int(v.numel()) != m:
+        raise ValueError("u and v differ in length")
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=u.device if u.is_cuda else "cuda")
+    opt = Options()
+    lib().cc_default_options(ctypes.byref(opt))
+    opt.route = _ROUTE_ARG[route] if not isinstance(route, int) else route
+    opt.max_passes = max_passes
+    opt.tau = tau
+    opt.theta = theta
+    st = Stats()
+    rc = lib().cc_label_ex(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n,
+                           _dev(out, torch.int32, "labels"), _stream(), ctypes.byref(opt),
+                           ctypes.byref(st) if stats else None)
+    _check(rc)
+    return (out, st.to_dict()) if stats else out
+
+
+def label_batched(u, v, edge_off, vert_off, out=None, tile_edges: int = 0, stats: bool = False):
+    """Graph-local labels of G graphs (see cc_label_batched)."""
+    G = int(edge_off.numel()) - 1
+    if out is None:
+        total = int(vert_off[-1].item()) if G >= 0 else 0
+        out = torch.empty(max(total, 0), dtype=torch.int32, device=u.device)
+    st = BatchStats()
+    rc = lib().cc_label_batched_ex(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"),
+                                   _dev(edge_off, torch.int64, "edge_off"), _dev(vert_off, torch.int64, "vert_off"),
+                                   G, _dev(out, torch.int32, "labels"), _stream(), tile_edges,
+                                   ctypes.byref(st) if stats else None)
+    _check(rc)
+    if stats:
+        return out, {k: getattr(st, k) for k, _ in BatchStats._fields_ if not k.startswith("reserved")}
+    return out
+
+
+def degree(u, v, n):
+    out = torch.empty(n, dtype=torch.int32, device=u.device)
+    _check(lib().cc_degree(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), int(u.numel()), n,
+                           _dev(out, torch.int32, "deg"), _stream()))
+    return out
+
+
+def degree_histograms(deg: torch.Tensor, tail_cap: int | None = None):
+    n = int(deg.numel())
+    if tail_cap is None:
+        tail_cap = max(1, n)
+    hist64 = torch.empty(64, dtype=torch.int64, device=deg.device)
+    histx = torch.empty(4096, dtype=torch.int64, device=deg.device)
+    tail = torch.empty(max(tail_cap, 1), dtype=torch.int32, device=deg.device)
+    cnt = ctypes.c_int64(0)
+    amax = ctypes.c_int32(-1)
+    _check(lib().cc_degree_histograms(_dev(deg, torch.int32, "deg"), n, _dev(hist64, torch.int64, "hist64"),
+                                      _dev(histx, torch.int64, "histx"), _dev(tail, torch.int32, "tail"), tail_cap,
+                                      ctypes.byref(cnt), ctypes.byref(amax), _stream()))
+    k = min(int(cnt.value), tail_cap)
+    return hist64, histx, tail[:k], int(cnt.value), int(amax.value)
+
+
+def powerlaw_ks(histx, tail):
+    """Host fit: histx int64[4096], tail int32 (numpy arrays)."""
+    import numpy as np
+    hx = np.ascontiguousarray(np.asarray(histx, dtype=np.int64))
+    tl = np.ascontiguousarray(np.asarray(tail, dtype=np.int32))
+    out = (ctypes.c_double * 5)()
+    _check(lib().cc_powerlaw_ks(_VP(hx.ctypes.data), _VP(tl.ctypes.data if tl.size else 0), int(tl.size), out))
+    return dict(ks=out[0], alpha=out[1], dmin=int(out[2]), ntail=int(out[3]), candidates=int(out[4]))
+
+
+def csr(u, v, n, deg):
+    m = int(u.numel())
+    off = torch.empty(n + 1, dtype=torch.int64, device=u.device)
+    adj = torch.empty(max(2 * m, 1), dtype=torch.int32, device=u.device)
+    _check(lib().cc_csr(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n, _dev(deg, torch.int32, "deg"),
+                        _dev(off, torch.int64, "off"), _dev(adj, torch.int32, "adj"), _stream()))
+    return off, adj[: 2 * m]
+
+
+def bfs(off, adj, n, seed):
+    words = (n + 31) // 32
+    vis = torch.empty(max(words, 1), dtype=torch.int32, device=off.device)
+    lv = ctypes.c_int32(0)
+    bu = ctypes.c_int32(0)
+    _check(lib().cc_bfs(_dev(off, torch.int64, "off"), _dev(adj, torch.int32, "adj"), n, int(adj.numel()), seed,
+                        _dev(vis, torch.int32, "visited"), ctypes.byref(lv), ctypes.byref(bu), _stream()))
+    return vis[:words], int(lv.value), int(bu.value)
+
+
+def bfs_filter(u, v, n, visited):
+    m = int(u.numel())
+    labels = torch.empty(n, dtype=torch.int32, device=u.device)
+    fu = torch.empty(max(m, 1), dtype=torch.int32, device=u.device)
+    fv = torch.empty(max(m, 1), dtype=torch.int32, device=u.device)
+    kept = ctypes.c_int64(0)
+    lab = ctypes.c_int32(-1)
+    _check(lib().cc_bfs_filter(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n,
+                               _dev(visited, torch.int32, "visited"), _dev(labels, torch.int32, "labels"),
+                               _dev(fu, torch.int32, "fu"), _dev(fv, torch.int32, "fv"), ctypes.byref(kept),
+                               ctypes.byref(lab), _stream()))
+    k = int(kept.value)
+    return labels, fu[:k], fv[:k], int(lab.value)
+
+
+def mlp_forward(params, x):
+    B = int(x.shape[0])
+    out = torch.empty((B, 3), dtype=torch.float32, device=x.device)
+    _check(lib().cc_mlp_forward(_dev(params, torch.float32, "params"), _dev(x, torch.float32, "x"), B,
+                                _dev(out, torch.float32, "logits"), _stream()))
+    return out
+
+
+def mlp_sgd_step(params, x, y, lr, want_grads=False):
+    B = int(x.shape[0])
+    grads = torch.empty(ROUTER_NPARAMS, dtype=torch.float32, device=x.device) if want_grads else None
+    loss = ctypes.c_float(0.0)
+    _check(lib().cc_mlp_sgd_step(_dev(params, torch.float32, "params"), _dev(x, torch.float32, "x"),
+                                 _dev(y, torch.int32, "y"), B, float(lr),
+                                 _dev(grads, torch.float32, "grads") if grads is not None else None,
+                                 ctypes.byref(loss), _stream()))
+    return float(loss.value), grads
+
+
+def router_load(path: str):
+    _check(lib().cc_router_load(path.encode()))
+
+
+def router_set(params_host) -> None:
+    import numpy as np
+    if params_host is None:
+        _check(lib().cc_router_set(None))
+        return
+    p = np.ascontiguousarray(np.asarray(params_host, dtype=np.float32))
+    if p.size != ROUTER_NPARAMS:
+        raise ValueError("router parameter count")
+    _check(lib().cc_router_set(_VP(p.ctypes.data)))
+
+
+def router_loaded() -> bool:
+    return bool(lib().cc_router_loaded())
+
+
+def release_workspace():
+    _check(lib().cc_release_workspace())

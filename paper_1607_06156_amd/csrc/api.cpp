@@ -1,0 +1,325 @@
+// C ABI of libccmi: validation, workspace, route choice and the host loops
+// that drive the HIP kernels.  See include/cc.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/cc.h"
+#include "common.hpp"
+#include "internal.hpp"
+
+#define CC_API extern "C" __attribute__((visibility("default")))
+
+namespace ccmi {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) return fail(CC_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(CC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// --------------------------------------------------------------- workspace
+Workspace::~Workspace() { release(); }
+
+void Workspace::release() {
+    for (auto& b : bufs) {
+        if (b.ptr) (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+}
+
+int Workspace::get(int slot, size_t bytes, void** out) {
+    if (bytes == 0) bytes = 256;
+    Buf& b = bufs[slot];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            hipError_t e = hipFree(b.ptr);
+            if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = bytes + bytes / 8;  // headroom against repeated growth
+        hipError_t e = hipMalloc(&b.ptr, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b.ptr = nullptr;
+            return hip_fail(e, "hipMalloc(workspace)");
+        }
+        b.bytes = want;
+    }
+    *out = b.ptr;
+    return CC_OK;
+}
+
+int Workspace::pinned(void** out) {
+    if (!host) {
+        hipError_t e = hipHostMalloc(&host, kHostBytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            host = nullptr;
+            return hip_fail(e, "hipHostMalloc");
+        }
+    }
+    *out = host;
+    return CC_OK;
+}
+
+static std::mutex g_ws_mu;
+static std::unordered_map<int, Workspace*> g_ws;
+
+int acquire_workspace(Workspace** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    auto it = g_ws.find(dev);
+    if (it == g_ws.end()) it = g_ws.emplace(dev, new Workspace()).first;
+    it->second->device = dev;
+    *out = it->second;
+    return CC_OK;
+}
+
+// ------------------------------------------------------------------ timing
+Timer::Timer(bool on, hipStream_t s) : enabled(on), stream(s) {}
+Timer::~Timer() {
+    for (auto ev : events) (void)hipEventDestroy(ev);
+}
+int Timer::mark() {
+    if (!enabled) return -1;
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return -1;
+    (void)hipEventRecord(ev, stream);
+    events.push_back(ev);
+    return (int)events.size() - 1;
+}
+double Timer::ms(int a, int b) {
+    if (!enabled || a < 0 || b < 0) return 0.0;
+    (void)hipEventSynchronize(events[b]);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, events[a], events[b]);
+    return (double)t;
+}
+
+// ---------------------------------------------------------------- SV loop
+static int choose_nseg(int64_t m) {
+    int64_t s = (m + 1023) / 1024;
+    if (s < 1) s = 1;
+    if (s > 2048) s = 2048;
+    return (int)s;
+}
+
+int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes) {
+    Workspace& ws = *c.ws;
+    const int64_t m0 = in0.soa ? in0.m : 0;
+    int nseg;
+    int64_t cap;
+    if (in0.soa) {
+        nseg = choose_nseg(m0);
+        cap = (m0 + nseg - 1) / nseg;
+        if (cap < 1) cap = 1;
+    } else {
+        nseg = in0.seg.nseg;
+        cap = in0.seg.cap;
+    }
+    const size_t slots = (size_t)nseg * (size_t)cap;
+    void *pbuf0, *pbuf1, *phook, *pcnt;
+    int rc;
+    // the input segment list (if any) already lives in WS_EDGES0; survivors go
+    // to the other buffer
+    if ((rc = ws.get(WS_EDGES0, slots * sizeof(int2), &pbuf0))) return rc;
+    if ((rc = ws.get(WS_EDGES1, slots * sizeof(int2), &pbuf1))) return rc;
+    if ((rc = ws.get(WS_HOOKED, slots * sizeof(int32_t), &phook))) return rc;
+    if ((rc = ws.get(WS_SEGCOUNT, (size_t)nseg * 4 * sizeof(uint32_t), &pcnt))) return rc;
+    void* ptot;
+    if ((rc = ws.get(WS_TOTALS, 64 * sizeof(unsigned long long), &ptot))) return rc;
+    unsigned long long* totals = (unsigned long long*)ptot;
+    unsigned long long* htot;
+    if ((rc = ws.pinned((void**)&htot))) return rc;
+    uint32_t* cnt[4];
+    for (int i = 0; i < 4; ++i) cnt[i] = (uint32_t*)pcnt + (size_t)i * nseg;
+    uint32_t* hooked_count = cnt[3];
+    int2* bufs[2] = {(int2*)pbuf0, (int2*)pbuf1};
+
+    hipError_t e = hipMemsetAsync(totals, 0, 64 * sizeof(unsigned long long), c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+
+    bool in_soa = in0.soa;
+    SegList in{nullptr, cap, nseg, nullptr};
+    int in_buf = 0, in_cnt = 0;
+    if (!in_soa) {
+        // caller placed the list in WS_EDGES0 with counts in cnt[0]
+        if (in0.seg.buf != bufs[0]) return fail(CC_EINTERNAL, "segment list not in workspace");
+        hipError_t ce = hipMemcpyAsync(cnt[0], in0.seg.count, (size_t)nseg * sizeof(uint32_t),
+                                       hipMemcpyDeviceToDevice, c.stream);
+        if (ce != hipSuccess) return hip_fail(ce, "hipMemcpyAsync(counts)");
+        in = SegList{bufs[0], cap, nseg, cnt[0]};
+    }
+    int64_t m_in = in0.soa ? m0 : in0.m;
+    bool compact_next = (policy == CC_R1_SV);
+    int pass = 0;
+    while (m_in > 0) {
+        if (max_passes > 0 && pass >= max_passes)
+            return fail(CC_EINTERNAL, "SV did not converge within %d passes", max_passes);
+        const bool write = (policy == CC_R1_SV) || compact_next;
+        const int out_buf = in_soa ? 0 : 1 - in_buf;
+        // out counts: any array other than the input's and the hooks'
+        int out_cnt = (in_cnt + 1) % 3;
+        SegList out{bufs[out_buf], cap, nseg, cnt[out_cnt]};
+        if (in_soa)
+            e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, write ? 1 : 0, (int32_t*)phook,
+                                   hooked_count, totals, c.stream);
+        else
+            e = launch_sv_pass_seg(in, c.parent, out, write ? 1 : 0, (int32_t*)phook, hooked_count, totals,
+                                   c.stream);
+        if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
+        e = launch_sv_shortcut(c.parent, (const int32_t*)phook, hooked_count, out.count, cap, nseg, totals,
+                               c.stream);
+        if (e != hipSuccess) return hip_fail(e, "sv_shortcut launch");
+        e = hipMemcpyAsync(htot, totals, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(totals)");
+        e = hipStreamSynchronize(c.stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        if (htot[2]) return fail(CC_ERANGE, "%llu edge endpoints outside [0, n)", (unsigned long long)htot[2]);
+        const int64_t kept = (int64_t)htot[0];
+        const int64_t hooks = (int64_t)htot[1];
+        if (c.stats) {
+            if (c.stats->sv_passes < 64) c.stats->active_edges[c.stats->sv_passes] = m_in;
+            c.stats->sv_passes++;
+            c.stats->hooks_total += hooks;
+            // edges read + two gathers + one atomic per unfinished edge + survivors written + shortcut
+            c.bytes += 16.0 * m_in + 8.0 * kept + (write ? 8.0 * kept : 0.0) + 12.0 * hooks;
+        }
+        ++pass;
+        if (kept == 0) break;
+        if (write) {
+            in = out;
+            in_soa = false;
+            in_buf = out_buf;
+            in_cnt = out_cnt;
+            m_in = kept;
+            compact_next = (policy == CC_R1_SV);
+        } else {
+            // R2: the list is re-read as is; compact once enough of it is finished,
+            // or after a pass with no hook (then every edge is finished)
+            const double finished = 1.0 - (double)kept / (double)m_in;
+            compact_next = (finished >= theta) || hooks == 0;
+        }
+    }
+    e = launch_sv_finalize(c.parent, c.n, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
+    if (c.stats) c.bytes += 8.0 * c.n;
+    return CC_OK;
+}
+
+}  // namespace ccmi
+
+using namespace ccmi;
+
+// ------------------------------------------------------------------- C ABI
+CC_API void cc_default_options(cc_options* opt) {
+    if (!opt) return;
+    memset(opt, 0, sizeof *opt);
+    opt->route = CC_ROUTE_AUTO;
+    opt->max_passes = 0;
+    opt->tau = 0.05;
+    opt->theta = 0.25;
+}
+
+CC_API int cc_version(void) { return CC_VERSION; }
+
+CC_API const char* cc_last_error(void) { return g_err.c_str(); }
+
+static void stats_reset(cc_stats* st) {
+    memset(st, 0, sizeof *st);
+    st->route = -1;
+    st->bfs_seed = -1;
+    st->bfs_label = -1;
+    st->max_degree = -1;
+    st->ks_statistic = NAN;
+    st->ks_alpha = NAN;
+}
+
+CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream,
+                       const cc_options* opt_in, cc_stats* stats) {
+    g_err.clear();
+    cc_options opt;
+    if (opt_in) opt = *opt_in; else cc_default_options(&opt);
+    if (opt.tau <= 0) opt.tau = 0.05;
+    if (opt.theta <= 0) opt.theta = 0.25;
+    if (m < 0 || n < 0) return fail(CC_EINVAL, "negative size (m=%lld, n=%d)", (long long)m, n);
+    if (m > 0 && n == 0) return fail(CC_EINVAL, "edges given for an empty vertex set");
+    if (m > 0 && (!u || !v)) return fail(CC_EINVAL, "NULL edge array");
+    if (n > 0 && !labels) return fail(CC_EINVAL, "NULL labels");
+    if (opt.route < CC_ROUTE_AUTO || opt.route > CC_ROUTE_SV_THETA) return fail(CC_EINVAL, "bad route %d", opt.route);
+    if (opt.max_passes < 0) return fail(CC_EINVAL, "negative max_passes");
+    if (m > (int64_t)2048 * (int64_t)INT32_MAX) return fail(CC_EINVAL, "too many edges");
+    if (stats) stats_reset(stats);
+    if (n == 0) return CC_OK;
+
+    Workspace* ws;
+    int rc = acquire_workspace(&ws);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> guard(ws->mu);
+
+    Call c;
+    c.ws = ws;
+    c.stream = (hipStream_t)stream;
+    c.n = n;
+    c.m = m;
+    c.u = u;
+    c.v = v;
+    c.parent = labels;
+    c.stats = stats;
+    c.opt = opt;
+    Timer tm(stats != nullptr, c.stream);
+    c.timer = &tm;
+    int t0 = tm.mark();
+    rc = run_label(c);
+    int t1 = tm.mark();
+    if (rc) return rc;
+    if (stats) {
+        stats->ms_total = tm.ms(t0, t1);
+        stats->algorithmic_bytes = c.bytes;
+    }
+    hipError_t e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return CC_OK;
+}
+
+CC_API int cc_label(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream) {
+    return cc_label_ex(u, v, m, n, labels, stream, nullptr, nullptr);
+}
+
+CC_API int cc_release_workspace(void) {
+    Workspace* ws;
+    int rc = acquire_workspace(&ws);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> guard(ws->mu);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    ws->release();
+    return CC_OK;
+}

@@ -1,0 +1,101 @@
+// Shared device helpers and internal launch interfaces of libccmi (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccmi {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+
+// -------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int lane_id() { return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// number of set bits of mask in lanes below this lane
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// agent-scope atomics (coherent across the XCDs of one device)
+__device__ __forceinline__ int32_t atomic_min_agent(int32_t* p, int32_t v) {
+    return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t atomic_add_agent(unsigned long long* p, unsigned long long v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t atomic_or_agent(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x in the parent forest.  parent[] may change concurrently (hooks by
+// other lanes) and a plain load may return an older value, but every value
+// parent[x] ever holds is an id <= x of a vertex connected to x, so the walk
+// strictly descends, terminates, and ends at a vertex that was a root when
+// read.
+__device__ __forceinline__ int32_t find_root(const int32_t* parent, int32_t x) {
+    int32_t p = parent[x];
+    while (p != x) {
+        x = p;
+        p = parent[x];
+    }
+    return x;
+}
+
+// Block-wide exclusive prefix of per-wave totals; returns this wave's offset
+// within the block and writes the block total to *total.  lds must hold
+// kWaves + 1 uint32.
+__device__ __forceinline__ uint32_t block_wave_offset(uint32_t wave_total, uint32_t* lds, uint32_t* total) {
+    const int wave = threadIdx.x >> 6;
+    if (lane_id() == 0) lds[wave] = wave_total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < kWaves; ++w) { uint32_t t = lds[w]; lds[w] = acc; acc += t; }
+        lds[kWaves] = acc;
+    }
+    __syncthreads();
+    uint32_t off = lds[wave];
+    *total = lds[kWaves];
+    __syncthreads();
+    return off;
+}
+
+// ------------------------------------------------------ segmented edge lists
+// Active edges live in per-block segments: block b of a pass owns slots
+// [b * cap, b * cap + count[b]) of an int2 buffer (x = smaller root, y =
+// larger).  Passes keep the block count fixed, so block b reads its own
+// segment and writes its survivors to the same slots of the other buffer;
+// no global atomic is needed to place output.
+struct SegList {
+    int2* buf;
+    int64_t cap;        // slots per segment
+    int32_t nseg;       // segments (= blocks)
+    uint32_t* count;    // device, nseg entries
+};
+
+// ------------------------------------------------------ launch interfaces
+// All launchers enqueue on `s` and return the hipError_t of the launch.
+
+// SV (sv.hip)
+hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s);
+// first pass over the caller's SoA edge list (dense, m edges); chunked into
+// nseg blocks of `cap` edges.  Writes survivors into out (if write_out),
+// hooked roots into hooked (segments of the same cap), per-block counts,
+// and accumulates totals[0] (kept), totals[1] (hooks), totals[2] (range errors).
+hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
+                              SegList out, int write_out, int32_t* hooked, uint32_t* hooked_count,
+                              unsigned long long* totals, hipStream_t s);
+// later passes over a segmented list
+hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int32_t* hooked,
+                              uint32_t* hooked_count, unsigned long long* totals, hipStream_t s);
+// pointer-jumps the hooked roots of each segment; block 0 also writes
+// totals[0] = sum(kept_count), totals[1] = sum(hooked_count)
+hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count,
+                              const uint32_t* kept_count, int64_t cap, int32_t nseg, unsigned long long* totals,
+                              hipStream_t s);
+hipError_t launch_sv_finalize(int32_t* parent, int32_t n, hipStream_t s);
+
+}  // namespace ccmi

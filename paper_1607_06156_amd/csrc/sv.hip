@@ -1,0 +1,244 @@
+// Shiloach-Vishkin style iteration on an edge list (Section III-A).
+//
+// The paper keeps tuples <p, q, r> and, per iteration, lets every partition p
+// join its minimum neighbouring partition (two sorts), then pointer-jumps the
+// joined partition once more (two more sorts), and drops completed partitions
+// from the working set (Section III-A.4).  On one GPU the partition of vertex
+// x is represented directly by a parent forest parent[] (labels_out doubles as
+// parent), in which every root is the smallest id of its tree:
+//
+//  * hook    -- for each active edge with roots ra != rb, atomicMin(parent[max],
+//               min): a partition joins the smallest neighbouring partition
+//               that reaches it in this pass (the atomic keeps the minimum of
+//               all candidates, as p_min = min C(p) does);
+//  * shortcut-- each root hooked in the pass is pointed straight at its new
+//               root (pointer jumping, Fig. "doubling");
+//  * compact -- an edge whose endpoints already share a root is finished and
+//               dropped; survivors are rewritten as (root, root), so the next
+//               pass starts from roots.  This is the exclusion of completed
+//               work (Section III-A.4), applied per edge instead of per
+//               partition.
+//
+// Invariant: parent[x] <= x, links only point to connected vertices, and the
+// connectivity of (forest links + active edges) always equals that of the
+// input.  A link can be overwritten only inside the pass that created it, and
+// the edge that created it is kept for the next pass, so no connection is
+// lost; the loop ends when no edge is active, and the forest roots are then
+// the component minima.
+#include "common.hpp"
+
+namespace ccmi {
+
+constexpr int kEPT = 4;   // edges per thread per tile
+
+__global__ __launch_bounds__(kBlock) void sv_init_kernel(int32_t* __restrict__ parent, int32_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (; i < n; i += stride) parent[i] = (int32_t)i;
+}
+
+// One pass: hook + compact over one block segment of edges.
+// SOA: edges come from the caller's u[], v[] (dense); block b takes
+// [b*cap, min((b+1)*cap, m)).  Else from segment b of `in`.
+template <bool SOA>
+__global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restrict__ u, const int32_t* __restrict__ v,
+                                                         int64_t m, int32_t n, SegList in, int32_t* parent,
+                                                         SegList out, int write_out, int32_t* __restrict__ hooked,
+                                                         uint32_t* __restrict__ hooked_count,
+                                                         unsigned long long* __restrict__ totals) {
+    __shared__ uint32_t lds[kWaves + 1];
+    const int b = blockIdx.x;
+    int64_t len;
+    const int2* src = nullptr;
+    int64_t base;
+    if (SOA) {
+        base = (int64_t)b * out.cap;
+        len = m - base;
+        if (len > out.cap) len = out.cap;
+        if (len < 0) len = 0;
+    } else {
+        base = (int64_t)b * in.cap;
+        len = in.count[b];
+        src = in.buf + base;
+    }
+    int2* dst = out.buf + (int64_t)b * out.cap;
+    int32_t* hdst = hooked + (int64_t)b * out.cap;
+    uint32_t kept_off = 0, hook_off = 0, bad = 0;
+
+    for (int64_t t0 = 0; t0 < len; t0 += kBlock * kEPT) {
+        int32_t a[kEPT], c[kEPT], pa[kEPT], pc[kEPT];
+        bool valid[kEPT];
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            int64_t i = t0 + threadIdx.x + (int64_t)k * kBlock;
+            valid[k] = i < len;
+            if (valid[k]) {
+                if (SOA) {
+                    a[k] = u[base + i];
+                    c[k] = v[base + i];
+                    if ((uint32_t)a[k] >= (uint32_t)n || (uint32_t)c[k] >= (uint32_t)n) {
+                        ++bad;
+                        valid[k] = false;
+                    }
+                } else {
+                    int2 e = src[i];
+                    a[k] = e.x;
+                    c[k] = e.y;
+                }
+            }
+        }
+        // issue all first-level gathers before any dependent chase
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            if (valid[k]) {
+                pa[k] = parent[a[k]];
+                pc[k] = parent[c[k]];
+            }
+        }
+        bool keep[kEPT], hk[kEPT];
+        int2 e[kEPT];
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            keep[k] = false;
+            hk[k] = false;
+            if (!valid[k]) continue;
+            int32_t ra = pa[k] == a[k] ? a[k] : find_root(parent, pa[k]);
+            int32_t rc = pc[k] == c[k] ? c[k] : find_root(parent, pc[k]);
+            if (ra == rc) continue;
+            int32_t lo = ra < rc ? ra : rc;
+            int32_t hi = ra < rc ? rc : ra;
+            int32_t old = atomic_min_agent(&parent[hi], lo);
+            hk[k] = (old == hi);
+            keep[k] = true;
+            e[k] = make_int2(lo, hi);
+        }
+        // wave ballots -> slot prefixes; one block scan of packed (kept | hooks << 16)
+        uint64_t km[kEPT], hm[kEPT];
+        uint32_t kpre[kEPT], hpre[kEPT];
+        uint32_t wk = 0, wh = 0;
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            km[k] = ballot(keep[k]);
+            hm[k] = ballot(hk[k]);
+            kpre[k] = wk + lanes_below(km[k]);
+            hpre[k] = wh + lanes_below(hm[k]);
+            wk += (uint32_t)__popcll(km[k]);
+            wh += (uint32_t)__popcll(hm[k]);
+        }
+        uint32_t tot;
+        uint32_t woff = block_wave_offset(wk | (wh << 16), lds, &tot);
+        uint32_t koff = kept_off + (woff & 0xffffu), hoff = hook_off + (woff >> 16);
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            if (write_out && keep[k]) dst[koff + kpre[k]] = e[k];
+            if (hk[k]) hdst[hoff + hpre[k]] = e[k].y;
+        }
+        kept_off += tot & 0xffffu;
+        hook_off += tot >> 16;
+    }
+    // per-block results (no global atomics on the fast path)
+    if (threadIdx.x == 0) {
+        out.count[b] = kept_off;
+        hooked_count[b] = hook_off;
+    }
+    if (SOA) {
+        // range errors are rare: only then touch a global counter
+        for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off);
+        if (lane_id() == 0 && bad) atomic_add_agent(&totals[2], bad);
+    }
+    (void)write_out;
+}
+
+// Pointer jumping for the roots hooked in the last pass; block 0 also reduces
+// the per-block kept / hook counts into totals[0], totals[1].
+__global__ __launch_bounds__(kBlock) void sv_shortcut_kernel(int32_t* parent, const int32_t* __restrict__ hooked,
+                                                             const uint32_t* __restrict__ hooked_count,
+                                                             const uint32_t* __restrict__ kept_count, int64_t cap,
+                                                             int32_t nseg, unsigned long long* __restrict__ totals) {
+    const int b = blockIdx.x;
+    const uint32_t cnt = hooked_count[b];
+    const int32_t* h = hooked + (int64_t)b * cap;
+    for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
+        int32_t x = h[j];
+        int32_t r = find_root(parent, x);
+        parent[x] = r;
+    }
+    if (b == 0) {
+        __shared__ unsigned long long red[2][kWaves];
+        unsigned long long sk = 0, sh = 0;
+        for (int i = threadIdx.x; i < nseg; i += kBlock) {
+            sk += kept_count[i];
+            sh += hooked_count[i];
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            sk += __shfl_xor(sk, off);
+            sh += __shfl_xor(sh, off);
+        }
+        if (lane_id() == 0) {
+            red[0][threadIdx.x >> 6] = sk;
+            red[1][threadIdx.x >> 6] = sh;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long a = 0, c = 0;
+            for (int w = 0; w < kWaves; ++w) { a += red[0][w]; c += red[1][w]; }
+            totals[0] = a;
+            totals[1] = c;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void sv_finalize_kernel(int32_t* parent, int32_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (; i < n; i += stride) {
+        int32_t p = parent[i];
+        if (p == (int32_t)i) continue;
+        int32_t r = find_root(parent, p);
+        if (r != p) parent[i] = r;
+    }
+}
+
+static int grid_for(int64_t n, int per_thread = 1) {
+    int64_t g = (n + (int64_t)kBlock * per_thread - 1) / ((int64_t)kBlock * per_thread);
+    if (g < 1) g = 1;
+    if (g > 16384) g = 16384;
+    return (int)g;
+}
+
+hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    sv_init_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(parent, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
+                              SegList out, int write_out, int32_t* hooked, uint32_t* hooked_count,
+                              unsigned long long* totals, hipStream_t s) {
+    SegList none{nullptr, 0, 0, nullptr};
+    sv_pass_kernel<true><<<out.nseg, kBlock, 0, s>>>(u, v, m, n, none, parent, out, write_out, hooked, hooked_count,
+                                                     totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int32_t* hooked,
+                              uint32_t* hooked_count, unsigned long long* totals, hipStream_t s) {
+    sv_pass_kernel<false><<<in.nseg, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, in, parent, out, write_out, hooked,
+                                                     hooked_count, totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count,
+                              const uint32_t* kept_count, int64_t cap, int32_t nseg, unsigned long long* totals,
+                              hipStream_t s) {
+    sv_shortcut_kernel<<<nseg, kBlock, 0, s>>>(parent, hooked, hooked_count, kept_count, cap, nseg, totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_sv_finalize(int32_t* parent, int32_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    sv_finalize_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(parent, n);
+    return hipGetLastError();
+}
+
+}  // namespace ccmi

@@ -1,0 +1,126 @@
+"""GPU parity of the SV routes (R1 plain SV, R2 SV-theta) against the oracle, bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import assert_labels_equal, oracle_labels, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ccmi = pytest.importorskip("paper_1607_06156_amd")
+ROUTES = ["sv", "sv-theta"]
+
+
+def run(g, route, **kw):
+    say(f"[gpu] {g.name} m={g.m} n={g.n} route={route}")
+    return ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route=route, **kw)
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_closed_forms(route):
+    n = 40_000
+    pi = gen.permutation(n, seed=1)
+    # Hamiltonian path, ids permuted -> one component
+    lab = run(gen.Graph(pi[:-1], pi[1:], n, "path"), route)
+    assert torch.all(lab == 0)
+    # complete grid -> one component
+    lab = run(gen.grid(150, 1.0, seed=2), route)
+    assert torch.all(lab == 0)
+    # no edges -> identity
+    e = np.zeros(0, np.int32)
+    lab = run(gen.Graph(e, e, 1000, "empty"), route)
+    assert torch.equal(lab.cpu(), torch.arange(1000, dtype=torch.int32))
+    # perfect matching
+    a = np.arange(0, n, 2, dtype=np.int32)
+    lab = run(gen.Graph(a + 1, a, n, "matching"), route)
+    assert torch.equal(lab.cpu(), torch.from_numpy(2 * (np.arange(n, dtype=np.int32) // 2)))
+    # self-loops only
+    x = np.arange(777, dtype=np.int32)
+    lab = run(gen.Graph(x, x, 777, "loops"), route)
+    assert torch.equal(lab.cpu(), torch.from_numpy(x))
+    # star
+    leaves = np.array([y for y in range(5000) if y != 1234], np.int32)
+    lab = run(gen.Graph(np.full(4999, 1234, np.int32), leaves, 5000, "star"), route)
+    assert torch.all(lab == 0)
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_random_small_multigraphs(route):
+    rng = np.random.default_rng(7)
+    for trial in range(60):
+        n = int(rng.integers(1, 300))
+        m = int(rng.integers(0, 3 * n))
+        u = rng.integers(0, n, m).astype(np.int32)
+        v = rng.integers(0, n, m).astype(np.int32)
+        if m and trial % 3 == 0:
+            v[: m // 4] = u[: m // 4]
+        g = gen.Graph(u, v, n, f"rand{trial}")
+        assert_labels_equal(run(g, route), oracle_labels(g), g.name)
+
+
+@pytest.mark.parametrize("route", ROUTES)
+@pytest.mark.parametrize("name", ["gnm64k", "rmat16", "grid512", "plcomp1m", "rmat18noisy"])
+def test_workloads_small(route, name):
+    g = gen.workload(name)
+    lab, st = run(g, route, stats=True)
+    assert_labels_equal(lab, oracle_labels(g), f"{name}/{route}")
+    say(f"   passes={st['sv_passes']} active={st['active_edges'][:8]} ms={st['ms_total']:.3f}")
+    # the active set never grows and the loop ends with no active edge
+    act = st["active_edges"]
+    assert all(b <= a for a, b in zip(act, act[1:]))
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_ragged_sizes(route):
+    """m not a multiple of the tile, a few edges per block, one block."""
+    for m in [1, 3, 5, 1023, 1025, 4097, 70001]:
+        g = gen.gnm(max(8, m), m, seed=m)
+        assert_labels_equal(run(g, route), oracle_labels(g), f"gnm m={m}")
+
+
+def test_edge_order_and_orientation_invariance():
+    g = gen.rmat(15, 8, seed=3)
+    rng = np.random.default_rng(0)
+    order = rng.permutation(g.m)
+    swap = rng.random(g.m) < 0.5
+    g2 = gen.Graph(np.where(swap, g.v, g.u)[order], np.where(swap, g.u, g.v)[order], g.n, "shuffled")
+    a = run(g, "sv")
+    b = run(g2, "sv")
+    assert torch.equal(a, b)
+
+
+def test_repeatable():
+    g = gen.workload("rmat16")
+    first = run(g, "sv")
+    for _ in range(10):
+        assert torch.equal(run(g, "sv"), first)
+
+
+def test_errors():
+    u = to_dev(np.array([0, 5], np.int32))
+    v = to_dev(np.array([1, 2], np.int32))
+    with pytest.raises(ccmi.CCError) as ei:
+        ccmi.label(u, v, 5, route="sv")
+    assert ei.value.code == ccmi.CC_ERANGE
+    with pytest.raises(ccmi.CCError) as ei:
+        ccmi.label(u, v, -1, route="sv", out=torch.empty(1, dtype=torch.int32, device="cuda"))
+    assert ei.value.code == ccmi.CC_EINVAL
+    neg = to_dev(np.array([-3], np.int32))
+    with pytest.raises(ccmi.CCError):
+        ccmi.label(neg, neg, 4, route="sv")
+    # m = 0 -> identity, n = 0 -> nothing to do
+    e = to_dev(np.zeros(0, np.int32))
+    assert torch.equal(ccmi.label(e, e, 9, route="sv").cpu(), torch.arange(9, dtype=torch.int32))
+    assert ccmi.label(e, e, 0, route="sv").numel() == 0
+
+
+def test_pass_cap_reports_internal_error():
+    n = 100_000
+    pi = gen.permutation(n, seed=5)
+    u, v = to_dev(pi[:-1]), to_dev(pi[1:])
+    with pytest.raises(ccmi.CCError) as ei:
+        ccmi.label(u, v, n, route="sv", max_passes=1)
+    assert ei.value.code == ccmi.CC_EINTERNAL
+    assert torch.all(ccmi.label(u, v, n, route="sv") == 0)
