@@ -71,8 +71,20 @@ typedef struct cc_options {
     int32_t max_passes;  /* 0: no cap; else CC_EINTERNAL once this many SV passes ran without converging */
     double tau;          /* K-S threshold; <= 0 selects 0.05 (Section V, Table "tab:ks_stat") */
     double theta;        /* R2: compact after a pass only if >= theta of its edges were finished; <= 0 selects 0.25 */
-    int32_t reserved[8]; /* must be zero */
+    int32_t profile;     /* 1: time every kernel launch with HIP events (cc_stats.kernel_*) */
+    int32_t reserved[7]; /* must be zero */
 } cc_options;
+
+/* kernel classes for cc_stats.kernel_* */
+#define CC_K_SV_PASS 0     /* hook + compaction pass over active edges */
+#define CC_K_SV_SHORTCUT 1 /* pointer jumping of hooked roots */
+#define CC_K_SV_FINALIZE 2 /* init + final label pass */
+#define CC_K_DEGREE 3      /* degree (endpoint counting) */
+#define CC_K_HIST 4        /* degree histograms */
+#define CC_K_CSR 5         /* CSR scan + fill */
+#define CC_K_BFS 6         /* BFS levels */
+#define CC_K_FILTER 7      /* BFS label + edge filter */
+#define CC_K_CLASSES 8
 
 typedef struct cc_stats {
     int32_t route;                /* route taken: CC_R0_BFS_SV, CC_R1_SV or CC_R2_SV_THETA */
@@ -98,7 +110,10 @@ typedef struct cc_stats {
     double ms_filter;             /* BFS label + edge filter (R0) */
     double ms_sv;                 /* SV passes, shortcuts and finalize */
     double ms_total;              /* whole call, device time between first and last event */
-    double algorithmic_bytes;     /* bytes the method must move (cost model, see DESIGN) */
+    double algorithmic_bytes;     /* bytes the method must move (cost model) */
+    double kernel_ms[8];          /* device time per kernel class, summed (profile = 1 only) */
+    int32_t kernel_launches[8];   /* launches per kernel class (profile = 1 only) */
+    double kernel_bytes[8];       /* algorithmic bytes per kernel class (profile = 1 only) */
 } cc_stats;
 
 /* Fills *opt with the defaults (route AUTO, no cap, tau 0.05, theta 0.25). */
@@ -171,7 +186,8 @@ int cc_router_loaded(void);
 
 /* Degree (Section III-B, Degree_Distribution): deg[x] = number of edge endpoints
  * equal to x (each undirected edge counts for both ends, a self-loop twice).
- * deg: int32[n], written.  Returns CC_ERANGE if an id is outside [0, n). */
+ * deg: int32[n], written.  Requires n <= 2^29 (bucketed counting in LDS).
+ * Returns CC_ERANGE if an id is outside [0, n). */
 int cc_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* deg, void* stream);
 
 /* Degree histograms: hist64[64] (half-octave log bins: bin 0 = degree 0, degree
@@ -188,18 +204,23 @@ int cc_degree_histograms(const int32_t* deg, int32_t n, int64_t* hist64, int64_t
  * degrees >= 4096).  Clauset-Shalizi-Newman: for each candidate cutoff d_min
  * (distinct degree with >= 50 vertices and >= 2 distinct values at or above
  * it) alpha is the maximum-likelihood exponent on (1, 10] and D the largest
- * CDF gap; the result is the smallest D.  out[0] = D (+inf if no candidate),
- * out[1] = alpha, out[2] = d_min, out[3] = tail size, out[4] = candidates.
- * Host-only, no device work. */
+ * CDF gap; the result is the smallest D (the first such d_min on ties).
+ * out (host double[5]): D (+inf if no candidate), alpha, d_min, tail size,
+ * candidates.  The candidates are fitted on the current device (one
+ * workgroup each, default stream); the call returns when done. */
 int cc_powerlaw_ks(const int64_t* histx, const int32_t* tail, int64_t ntail, double* out);
 
-/* CSR of the undirected graph (both directions of every edge, self-loops
- * twice): off: int64[n+1] = exclusive scan of deg; adj: int32[2m] neighbour
- * lists, each vertex's entries in an unspecified order. */
-int cc_csr(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const int32_t* deg, int64_t* off,
-           int32_t* adj, void* stream);
+/* CSR of the undirected graph (both directions of every edge, a self-loop
+ * twice): off: int64[n+1] = exclusive scan of the degrees; adj: int32[2m]
+ * neighbour lists, each vertex's entries in an unspecified order; deg:
+ * optional int32[n] output of the degrees (NULL if not wanted).  Requires
+ * n <= 2^29.  Returns CC_ERANGE if an id is outside [0, n). */
+int cc_csr(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* deg, int64_t* off, int32_t* adj,
+           void* stream);
 
-/* Direction-optimising BFS from seed over a CSR (off, adj) with n vertices.
+/* Direction-optimising BFS from seed over a CSR (off, adj) with n vertices and
+ * nadj adjacency entries (checked: off[0] = 0, non-decreasing, off[n] = nadj,
+ * entries in [0, n), else CC_EINVAL).
  * visited: uint32[(n+31)/32] bitmap, written (bit x%32 of word x/32).
  * *levels and *bottom_up (host, may be NULL) receive level counts. */
 int cc_bfs(const int64_t* off, const int32_t* adj, int32_t n, int64_t nadj, int32_t seed, uint32_t* visited,

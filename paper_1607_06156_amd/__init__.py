@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libccmi.so")
 ROUTE_AUTO, ROUTE_HEURISTIC, ROUTE_ROUTER, ROUTE_SV, ROUTE_BFS_SV, ROUTE_SV_THETA = range(6)
 R0_BFS_SV, R1_SV, R2_SV_THETA = 0, 1, 2
 ROUTE_NAMES = {R0_BFS_SV: "bfs+sv", R1_SV: "sv", R2_SV_THETA: "sv-theta"}
+KERNEL_CLASSES = ["sv_pass", "sv_shortcut", "sv_finalize", "degree", "hist", "csr", "bfs", "filter"]
 _ROUTE_ARG = {None: ROUTE_AUTO, "auto": ROUTE_AUTO, "heuristic": ROUTE_HEURISTIC, "router": ROUTE_ROUTER,
               "sv": ROUTE_SV, "bfs+sv": ROUTE_BFS_SV, "bfs": ROUTE_BFS_SV, "sv-theta": ROUTE_SV_THETA}
 
@@ -39,7 +40,7 @@ class CCError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("route", ctypes.c_int32), ("max_passes", ctypes.c_int32), ("tau", ctypes.c_double),
-                ("theta", ctypes.c_double), ("reserved", ctypes.c_int32 * 8)]
+                ("theta", ctypes.c_double), ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class Stats(ctypes.Structure):
@@ -52,7 +53,8 @@ class Stats(ctypes.Structure):
                 ("active_edges", ctypes.c_int64 * 64), ("hooks_total", ctypes.c_int64),
                 ("ms_predict", ctypes.c_double), ("ms_csr", ctypes.c_double), ("ms_bfs", ctypes.c_double),
                 ("ms_filter", ctypes.c_double), ("ms_sv", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("algorithmic_bytes", ctypes.c_double)]
+                ("algorithmic_bytes", ctypes.c_double), ("kernel_ms", ctypes.c_double * 8),
+                ("kernel_launches", ctypes.c_int32 * 8), ("kernel_bytes", ctypes.c_double * 8)]
 
     def to_dict(self) -> dict:
         d = {}
@@ -62,8 +64,10 @@ class Stats(ctypes.Structure):
             val = getattr(self, name)
             if name == "active_edges":
                 val = [int(x) for x in val][: max(0, min(self.sv_passes, 64))]
-            elif name == "router_logits":
+            elif name in ("router_logits", "kernel_ms", "kernel_bytes"):
                 val = [float(x) for x in val]
+            elif name == "kernel_launches":
+                val = [int(x) for x in val]
             d[name] = val
         d["route_name"] = ROUTE_NAMES.get(self.route, "none")
         return d
@@ -150,7 +154,8 @@ def version() -> int:
 
 
 def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tensor | None = None,
-          stats: bool = False, max_passes: int = 0, tau: float = 0.05, theta: float = 0.25):
+          stats: bool = False, max_passes: int = 0, tau: float = 0.05, theta: float = 0.25,
+          profile: bool = False):
     """labels[x] = min vertex id of x's component; (u[i], v[i]) are undirected edges."""
     m = int(u.numel())
     if int(v.numel()) != m:
@@ -163,6 +168,7 @@ def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tenso
     opt.max_passes = max_passes
     opt.tau = tau
     opt.theta = theta
+    opt.profile = 1 if profile else 0
     st = Stats()
     rc = lib().cc_label_ex(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n,
                            _dev(out, torch.int32, "labels"), _stream(), ctypes.byref(opt),
@@ -221,13 +227,15 @@ def powerlaw_ks(histx, tail):
     return dict(ks=out[0], alpha=out[1], dmin=int(out[2]), ntail=int(out[3]), candidates=int(out[4]))
 
 
-def csr(u, v, n, deg):
+def csr(u, v, n):
+    """(off int64[n+1], adj int32[2m], deg int32[n]) of the undirected graph."""
     m = int(u.numel())
     off = torch.empty(n + 1, dtype=torch.int64, device=u.device)
     adj = torch.empty(max(2 * m, 1), dtype=torch.int32, device=u.device)
+    deg = torch.empty(max(n, 1), dtype=torch.int32, device=u.device)
     _check(lib().cc_csr(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n, _dev(deg, torch.int32, "deg"),
                         _dev(off, torch.int64, "off"), _dev(adj, torch.int32, "adj"), _stream()))
-    return off, adj[: 2 * m]
+    return off, adj[: 2 * m], deg[:n]
 
 
 def bfs(off, adj, n, seed):

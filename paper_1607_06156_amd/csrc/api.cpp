@@ -124,7 +124,7 @@ double Timer::ms(int a, int b) {
 }
 
 // ---------------------------------------------------------------- SV loop
-static int choose_nseg(int64_t m) {
+int choose_nseg(int64_t m) {
     int64_t s = (m + 1023) / 1024;
     if (s < 1) s = 1;
     if (s > 2048) s = 2048;
@@ -188,6 +188,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         // out counts: any array other than the input's and the hooks'
         int out_cnt = (in_cnt + 1) % 3;
         SegList out{bufs[out_buf], cap, nseg, cnt[out_cnt]};
+        int k0 = c.kbeg();
         if (in_soa)
             e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, write ? 1 : 0, (int32_t*)phook,
                                    hooked_count, totals, c.stream);
@@ -195,9 +196,12 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             e = launch_sv_pass_seg(in, c.parent, out, write ? 1 : 0, (int32_t*)phook, hooked_count, totals,
                                    c.stream);
         if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
+        int rec_pass = c.kend(CC_K_SV_PASS, k0, 0.0);
+        int k1 = c.kbeg();
         e = launch_sv_shortcut(c.parent, (const int32_t*)phook, hooked_count, out.count, cap, nseg, totals,
                                c.stream);
         if (e != hipSuccess) return hip_fail(e, "sv_shortcut launch");
+        int rec_sc = c.kend(CC_K_SV_SHORTCUT, k1, 0.0);
         e = hipMemcpyAsync(htot, totals, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(totals)");
         e = hipStreamSynchronize(c.stream);
@@ -209,8 +213,12 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             if (c.stats->sv_passes < 64) c.stats->active_edges[c.stats->sv_passes] = m_in;
             c.stats->sv_passes++;
             c.stats->hooks_total += hooks;
-            // edges read + two gathers + one atomic per unfinished edge + survivors written + shortcut
-            c.bytes += 16.0 * m_in + 8.0 * kept + (write ? 8.0 * kept : 0.0) + 12.0 * hooks;
+            // edges read (8 B) + two 4 B gathers + one 8 B atomic per unfinished edge
+            // + survivors written (8 B); shortcut: read, gather, write per hooked root
+            const double pass_bytes = 16.0 * m_in + 8.0 * kept + (write ? 8.0 * kept : 0.0);
+            c.bytes += pass_bytes + 12.0 * hooks;
+            c.kbytes(rec_pass, pass_bytes);
+            c.kbytes(rec_sc, 12.0 * hooks);
         }
         ++pass;
         if (kept == 0) break;
@@ -228,8 +236,10 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             compact_next = (finished >= theta) || hooks == 0;
         }
     }
+    int k2 = c.kbeg();
     e = launch_sv_finalize(c.parent, c.n, c.stream);
     if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
+    c.kend(CC_K_SV_FINALIZE, k2, 8.0 * c.n);
     if (c.stats) c.bytes += 8.0 * c.n;
     return CC_OK;
 }
@@ -303,6 +313,12 @@ CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
     if (stats) {
         stats->ms_total = tm.ms(t0, t1);
         stats->algorithmic_bytes = c.bytes;
+        for (const auto& r : c.krecs) {
+            if (r.cls < 0 || r.cls >= CC_K_CLASSES) continue;
+            stats->kernel_ms[r.cls] += tm.ms(r.a, r.b);
+            stats->kernel_launches[r.cls] += 1;
+            stats->kernel_bytes[r.cls] += r.bytes;
+        }
     }
     hipError_t e = hipStreamSynchronize(c.stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");

@@ -1,0 +1,41 @@
+// BFS / filter launch interface (bfs.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace ccmi {
+
+constexpr double kBeamerAlpha = 14.0;
+constexpr double kBeamerBeta = 24.0;
+
+// pre[0..qn] = exclusive prefix of frontier degrees; bsum needs ceil(qn/1024) entries
+hipError_t launch_qdeg_scan(const int32_t* q, int64_t qn, const int64_t* off, int64_t* pre, int64_t* bsum,
+                            int64_t* total, hipStream_t s);
+// ctr[0] += new vertices (appended to nq), ctr[1] += their degrees
+hipError_t launch_topdown(const int32_t* q, int64_t qn, const int64_t* pre, int64_t total_entries,
+                          const int64_t* off, const int32_t* adj, uint32_t* vis, int32_t* nq,
+                          unsigned long long* ctr, hipStream_t s);
+// ctr[0] += new vertices (bits in next), ctr[1] += their degrees, ctr[2] += entries examined
+hipError_t launch_bottomup(int32_t n, const int64_t* off, const int32_t* adj, uint32_t* vis, const uint32_t* front,
+                           uint32_t* next, unsigned long long* ctr, hipStream_t s);
+hipError_t launch_queue_to_bits(const int32_t* q, int64_t qn, uint32_t* bits, hipStream_t s);
+hipError_t launch_bits_to_queue(const uint32_t* bits, int64_t words, int32_t* q, unsigned long long* qn,
+                                hipStream_t s);
+hipError_t launch_diff_bits(const uint32_t* vis, const uint32_t* prev, uint32_t* front, int64_t words,
+                            hipStream_t s);
+// *label (pre-set to INT32_MAX) = min visited id; labels[x] = visited ? *label : x
+hipError_t launch_bfs_label(const uint32_t* vis, int32_t n, int32_t* label, int32_t* labels, hipStream_t s);
+// edges whose first endpoint is unvisited -> segments of out; *total = their count
+// (*bad += edges with an endpoint outside [0, n); those are dropped)
+hipError_t launch_filter(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const uint32_t* vis, SegList out,
+                         unsigned long long* total, unsigned long long* bad, hipStream_t s);
+// *bad += violations of the CSR contract (offsets, entry range)
+hipError_t launch_csr_check(const int64_t* off, int32_t n, const int32_t* adj, int64_t nadj,
+                            unsigned long long* bad, hipStream_t s);
+hipError_t launch_seg_to_soa(SegList in, int64_t* prefix_scratch, int64_t* total_scratch, int32_t* fu, int32_t* fv,
+                             hipStream_t s);
+
+}  // namespace ccmi

@@ -1,0 +1,48 @@
+// Degree / histogram / CSR launch interface (degree.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccmi {
+
+constexpr int kBucketShift = 15;      // 32768 vertices per bucket (LDS counters)
+constexpr int kMaxBuckets = 16384;    // n <= 2^29 for the bucketed degree pass
+constexpr int kExactBins = 4096;      // exact degree histogram below this
+constexpr int kBlockD = 1024;         // threads of the per-bucket kernel
+
+struct BucketPlan {
+    int32_t B;       // vertex buckets
+    int32_t nblk;    // edge-chunk blocks
+    int64_t chunk;   // edges per block
+};
+
+struct BucketBufs {
+    uint32_t* counts;            // [nblk][B]
+    unsigned long long* tot;     // [B]
+    unsigned long long* base;    // [B + 1]
+    unsigned long long* offs;    // [nblk][B]
+    int2* pairs;                 // [2m]
+    unsigned long long* err;     // range errors
+};
+
+// returns -1 if n is too large for the bucketed pass
+int bucket_plan(int32_t n, int64_t m, BucketPlan* p);
+
+// deg[n] (+ histograms when want_hist, + CSR off[n+1]/adj[2m] when want_csr).
+// hist64/histx/tail_count/argmax_key must be zeroed by the caller.
+hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
+                                const BucketBufs& w, int32_t* deg, int want_hist, unsigned long long* hist64,
+                                unsigned long long* histx, int32_t* tail, int64_t tail_cap,
+                                unsigned long long* tail_count, unsigned long long* argmax_key, int want_csr,
+                                int64_t* off, int32_t* adj, hipStream_t s);
+
+// CSR from an earlier launch_bucket_degree's pairs and deg[] (no recount)
+hipError_t launch_bucket_csr_from_deg(int32_t n, const BucketPlan& p, const BucketBufs& w, int32_t* deg,
+                                      int64_t* off, int32_t* adj, hipStream_t s);
+
+hipError_t launch_degree_hist(const int32_t* deg, int32_t n, unsigned long long* hist64, unsigned long long* histx,
+                              int32_t* tail, int64_t tail_cap, unsigned long long* tail_count,
+                              unsigned long long* argmax_key, hipStream_t s);
+
+}  // namespace ccmi

@@ -8,6 +8,7 @@
 
 #include "../../include/cc.h"
 #include "common.hpp"
+#include "degree.hpp"
 
 namespace ccmi {
 
@@ -30,6 +31,8 @@ enum WsSlot {
     WS_BITS,         // visited / frontier bitmaps
     WS_QUEUE,        // BFS queues
     WS_MLP,          // router parameters / features / logits
+    WS_KS,           // power-law fit inputs and results
+    WS_HISTOUT,      // reduced histograms, tail count, arg-max key
     WS_BATCH,        // batched-mode tables
     WS_NSLOTS
 };
@@ -76,6 +79,28 @@ struct Call {
     Timer* timer = nullptr;
     double bytes = 0.0;         // algorithmic bytes (cost model)
     bool range_checked = false;
+    // step entry points may direct the degree pass's outputs into caller arrays
+    int32_t* deg_out = nullptr;
+    int64_t* off_out = nullptr;
+    int32_t* adj_out = nullptr;
+    // per-kernel profiling (opt.profile with stats): event pairs per launch
+    struct KRec {
+        int cls, a, b;
+        double bytes;
+    };
+    std::vector<KRec> krecs;
+    bool profiling() const { return stats && opt.profile && timer; }
+    int kbeg() { return profiling() ? timer->mark() : -1; }
+    // returns the record index (or -1) so bytes can be filled in later
+    int kend(int cls, int a, double kbytes) {
+        if (!profiling()) return -1;
+        int b = timer->mark();
+        krecs.push_back(KRec{cls, a, b, kbytes});
+        return (int)krecs.size() - 1;
+    }
+    void kbytes(int rec, double kbytes) {
+        if (rec >= 0) krecs[rec].bytes = kbytes;
+    }
 };
 
 struct SvInput {
@@ -86,7 +111,35 @@ struct SvInput {
     SegList seg{};       // when !soa: list in WS_EDGES0
 };
 
+int choose_nseg(int64_t m);
 int run_sv(Call& c, const SvInput& in, int policy, double theta, int max_passes);
 int run_label(Call& c);
+
+// result of the degree pass (prediction step)
+struct DegreeResult {
+    BucketPlan plan{};
+    BucketBufs bufs{};
+    int32_t* deg = nullptr;
+    int32_t* tail = nullptr;
+    int64_t tail_cap = 0;
+    unsigned long long* hist64_dev = nullptr;
+    int64_t hist64[64] = {};
+    std::vector<int64_t> histx;
+    int64_t ntail = 0;
+    int64_t max_degree = 0;
+    int32_t argmax = -1;
+    bool csr_built = false;
+    int64_t* off = nullptr;
+    int32_t* adj = nullptr;
+};
+
+struct BfsResult {
+    int levels = 0, bottom_up = 0;
+    int64_t visited = 0, examined = 0;
+};
+
+int run_degree_pass(Call& c, bool want_csr, DegreeResult* r);
+int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32_t seed, int64_t seed_deg,
+            uint32_t** vis_out, BfsResult* br);
 
 }  // namespace ccmi

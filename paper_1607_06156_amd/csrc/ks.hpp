@@ -1,0 +1,29 @@
+// Power-law fit interface (ks.hip + ks_host.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace ccmi {
+
+constexpr double kAlphaLo = 1.0 + 1e-9;
+constexpr double kAlphaHi = 10.0;
+constexpr int64_t kMinTail = 50;   // vertices at or above a candidate cutoff
+
+hipError_t launch_ks_fit(const double* vals, const double* tail_n, const double* tail_s, int32_t V,
+                         const int32_t* cand, int32_t C, double* outD, double* outA, hipStream_t s);
+
+struct KsResult {
+    double ks = INFINITY;
+    double alpha = NAN;
+    int64_t dmin = 0;
+    int64_t ntail = 0;
+    int64_t candidates = 0;
+};
+
+struct Workspace;
+// histx: host int64[4096]; tail: host int32[ntail] (degrees >= 4096, any order)
+int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* tail, int64_t ntail, KsResult* out);
+
+}  // namespace ccmi

@@ -1,30 +1,376 @@
 // Route selection and the hybrid driver of Algorithm 2 (Section III-B).
+//
+//   prediction : degree distribution (bucketed degree pass + histograms);
+//   decision   : K-S statistic of the power-law fit < tau -> BFS step, or the
+//                learned router's argmax;
+//   BFS step   : CSR, direction-optimising BFS from the max-degree vertex,
+//                component label, edge filter;
+//   SV         : the SV iteration on whatever edges remain.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
+#include "bfs.hpp"
+#include "degree.hpp"
 #include "internal.hpp"
+#include "ks.hpp"
+#include "router.hpp"
 
 namespace ccmi {
 
+static int sync_read(Call& c, void* host, const void* dev, size_t bytes) {
+    hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(D2H)");
+    e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return CC_OK;
+}
+
+// ------------------------------------------------------------ prediction
+int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
+    Workspace& ws = *c.ws;
+    BucketPlan p;
+    if (bucket_plan(c.n, c.m, &p)) return fail(CC_EINVAL, "n too large for the degree pass");
+    r->plan = p;
+    const int64_t m = c.m;
+    void *pc, *po, *pp, *pdeg, *ptail;
+    int rc;
+    // WS_HIST: per-block bucket counts, then (8-byte aligned) totals, bases, error counter
+    const size_t counts_bytes = ((size_t)p.nblk * p.B * sizeof(uint32_t) + 255) & ~(size_t)255;
+    if ((rc = ws.get(WS_HIST, counts_bytes + (size_t)(2 * p.B + 2) * sizeof(unsigned long long), &pc))) return rc;
+    if ((rc = ws.get(WS_CURSOR, (size_t)p.nblk * p.B * sizeof(unsigned long long), &po))) return rc;
+    if ((rc = ws.get(WS_QUEUE, (size_t)2 * m * sizeof(int2), &pp))) return rc;  // (endpoint, other) pairs
+    if ((rc = ws.get(WS_DEG, (size_t)c.n * sizeof(int32_t), &pdeg))) return rc;
+    const int64_t tail_cap = std::min<int64_t>(c.n, 2 * m / kExactBins + 1);
+    if ((rc = ws.get(WS_TAIL, (size_t)tail_cap * sizeof(int32_t), &ptail))) return rc;
+    BucketBufs w;
+    w.counts = (uint32_t*)pc;
+    w.tot = (unsigned long long*)((char*)pc + counts_bytes);
+    w.base = w.tot + p.B;
+    w.err = w.base + p.B + 1;
+    w.offs = (unsigned long long*)po;
+    w.pairs = (int2*)pp;
+    r->bufs = w;
+    r->deg = c.deg_out ? c.deg_out : (int32_t*)pdeg;
+    r->tail = (int32_t*)ptail;
+    r->tail_cap = tail_cap;
+    // WS_HISTOUT: hist64[64], histx[4096], tail count, arg-max key
+    void* ph;
+    if ((rc = ws.get(WS_HISTOUT, (64 + kExactBins + 4) * sizeof(unsigned long long), &ph))) return rc;
+    unsigned long long* hist64 = (unsigned long long*)ph;
+    unsigned long long* histx = hist64 + 64;
+    unsigned long long* tail_count = histx + kExactBins;
+    unsigned long long* argmax_key = tail_count + 1;
+    r->hist64_dev = hist64;
+    hipError_t e = hipMemsetAsync(ph, 0, (64 + kExactBins + 4) * sizeof(unsigned long long), c.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w.err, 0, sizeof(unsigned long long), c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    int64_t* off = nullptr;
+    int32_t* adj = nullptr;
+    if (want_csr) {
+        if (c.off_out && c.adj_out) {
+            off = c.off_out;
+            adj = c.adj_out;
+        } else {
+            void *poff, *padj;
+            if ((rc = ws.get(WS_OFF, (size_t)(c.n + 1) * sizeof(int64_t), &poff))) return rc;
+            if ((rc = ws.get(WS_ADJ, (size_t)2 * m * sizeof(int32_t), &padj))) return rc;
+            off = (int64_t*)poff;
+            adj = (int32_t*)padj;
+        }
+        r->off = off;
+        r->adj = adj;
+    }
+    int k0 = c.kbeg();
+    e = launch_bucket_degree(c.u, c.v, m, c.n, p, w, r->deg, 1, hist64, histx, r->tail, tail_cap, tail_count,
+                             argmax_key, want_csr ? 1 : 0, off, adj, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "degree pass launch");
+    // algorithmic bytes: edges read (8 B), degrees written and histogrammed (8 B per vertex),
+    // plus the CSR (8 B per adjacency entry written, 8 B per offset)
+    c.kend(CC_K_DEGREE, k0, 8.0 * m + 8.0 * c.n + (want_csr ? 16.0 * m + 8.0 * c.n : 0.0));
+    if (c.stats) c.bytes += 8.0 * m + 8.0 * c.n + (want_csr ? 16.0 * m + 8.0 * c.n : 0.0);
+    r->csr_built = want_csr;
+    // read back histograms + counters
+    unsigned long long* host;
+    if ((rc = ws.pinned((void**)&host))) return rc;
+    e = hipMemcpyAsync(host, ph, (64 + kExactBins + 2) * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                       c.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host + 64 + kExactBins + 2, w.err, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(hist)");
+    e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (host[64 + kExactBins + 2])
+        return fail(CC_ERANGE, "%llu edges have an endpoint outside [0, n)", host[64 + kExactBins + 2]);
+    for (int i = 0; i < 64; ++i) r->hist64[i] = (int64_t)host[i];
+    r->histx.assign(host + 64, host + 64 + kExactBins);
+    r->ntail = (int64_t)host[64 + kExactBins];
+    const unsigned long long key = host[64 + kExactBins + 1];
+    r->max_degree = (int64_t)(key >> 32);
+    r->argmax = r->max_degree > 0 ? (int32_t)(~(uint32_t)(key & 0xffffffffull)) : -1;
+    c.range_checked = true;
+    if (c.stats) c.stats->max_degree = r->max_degree;
+    return CC_OK;
+}
+
+int decide_heuristic(Call& c, DegreeResult& r, int* route) {
+    std::vector<int32_t> tail;
+    if (r.ntail > 0) {
+        const int64_t k = std::min(r.ntail, r.tail_cap);
+        tail.resize(k);
+        hipError_t e = hipMemcpyAsync(tail.data(), r.tail, k * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tail)");
+        e = hipStreamSynchronize(c.stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
+    KsResult k;
+    int rc = ks_fit(*c.ws, c.stream, r.histx.data(), tail.data(), (int64_t)tail.size(), &k);
+    if (rc) return rc;
+    if (c.stats) {
+        c.stats->ks_statistic = k.ks;
+        c.stats->ks_alpha = k.alpha;
+        c.stats->ks_dmin = k.dmin;
+    }
+    *route = (k.ks < c.opt.tau) ? CC_R0_BFS_SV : CC_R1_SV;
+    return CC_OK;
+}
+
+// ------------------------------------------------------------------- BFS
+int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32_t seed, int64_t seed_deg,
+            uint32_t** vis_out, BfsResult* br) {
+    Workspace& ws = *c.ws;
+    const int32_t n = c.n;
+    const int64_t words = ((int64_t)n + 31) >> 5;
+    void *pbits, *pq, *ppre, *ptot;
+    int rc;
+    if ((rc = ws.get(WS_BITS, (size_t)words * 4 * sizeof(uint32_t), &pbits))) return rc;
+    if ((rc = ws.get(WS_HOOKED, (size_t)n * 2 * sizeof(int32_t), &pq))) return rc;
+    const int64_t nb = ((int64_t)n + 1023) / 1024 + 1;
+    if ((rc = ws.get(WS_SEGCOUNT, (size_t)(n + 1 + nb + 1) * sizeof(int64_t), &ppre))) return rc;
+    if ((rc = ws.get(WS_TOTALS, 64 * sizeof(unsigned long long), &ptot))) return rc;
+    uint32_t* vis = (uint32_t*)pbits;
+    uint32_t* front = vis + words;
+    uint32_t* next = front + words;
+    uint32_t* prev = next + words;
+    int32_t* q = (int32_t*)pq;
+    int32_t* nq = q + n;
+    int64_t* pre = (int64_t*)ppre;
+    int64_t* bsum = pre + n + 1;
+    int64_t* qtot = bsum + nb;
+    unsigned long long* ctr = (unsigned long long*)ptot + 16;
+    unsigned long long* host;
+    if ((rc = ws.pinned((void**)&host))) return rc;
+    hipError_t e = hipMemsetAsync(vis, 0, words * sizeof(uint32_t), c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(vis)");
+    int32_t* hs = (int32_t*)(host + 32);
+    hs[0] = seed;
+    e = hipMemcpyAsync(q, hs, sizeof(int32_t), hipMemcpyHostToDevice, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(seed)");
+    if ((e = launch_queue_to_bits(q, 1, vis, c.stream)) != hipSuccess) return hip_fail(e, "seed bit");
+    int64_t qn = 1, nf = 1, mf = seed_deg, mu = 2 * c.m - seed_deg, prev_nf = 0;
+    int64_t visited = 1, examined = 0;
+    bool topdown = true;
+    int levels = 0, bu_levels = 0;
+    while (nf > 0) {
+        if (topdown && (double)mf > (double)mu / kBeamerAlpha) {
+            // switch to bottom-up: frontier queue -> bitmap
+            if ((e = hipMemsetAsync(front, 0, words * sizeof(uint32_t), c.stream)) != hipSuccess)
+                return hip_fail(e, "hipMemsetAsync(front)");
+            if ((e = launch_queue_to_bits(q, qn, front, c.stream)) != hipSuccess) return hip_fail(e, "q2b");
+            topdown = false;
+        }
+        if ((e = hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), c.stream)) != hipSuccess)
+            return hip_fail(e, "hipMemsetAsync(ctr)");
+        int k0 = c.kbeg();
+        if (topdown) {
+            if ((e = launch_qdeg_scan(q, qn, off, pre, bsum, qtot, c.stream)) != hipSuccess)
+                return hip_fail(e, "qdeg scan");
+            if ((e = launch_topdown(q, qn, pre, mf, off, adj, vis, nq, ctr, c.stream)) != hipSuccess)
+                return hip_fail(e, "topdown");
+        } else {
+            if ((e = launch_bottomup(n, off, adj, vis, front, next, ctr, c.stream)) != hipSuccess)
+                return hip_fail(e, "bottomup");
+        }
+        int rec = c.kend(CC_K_BFS, k0, 0.0);
+        if ((rc = sync_read(c, host, ctr, 3 * sizeof(unsigned long long)))) return rc;
+        const int64_t found = (int64_t)host[0], fdeg = (int64_t)host[1];
+        double lbytes;
+        if (topdown) {
+            // queue + offsets of the frontier, adjacency entries, bitmap probes, queue writes
+            lbytes = 20.0 * qn + 8.0 * mf + 8.0 * found;
+            examined += mf;
+            std::swap(q, nq);
+            qn = found;
+        } else {
+            // offsets of unvisited vertices, entries examined, bitmap words in/out
+            const int64_t exam = (int64_t)host[2];
+            lbytes = 16.0 * (n - visited) + 8.0 * exam + 12.0 * words;
+            examined += exam;
+            std::swap(front, next);
+            ++bu_levels;
+        }
+        c.kbytes(rec, lbytes);
+        if (c.stats) c.bytes += lbytes;
+        ++levels;
+        visited += found;
+        mu -= fdeg;
+        prev_nf = nf;
+        nf = found;
+        mf = fdeg;
+        if (!topdown && nf > 0 && (double)nf < (double)n / kBeamerBeta && nf < prev_nf) {
+            // frontier shrinking: back to top-down, bitmap -> queue
+            if ((e = hipMemsetAsync(ctr + 3, 0, sizeof(unsigned long long), c.stream)) != hipSuccess)
+                return hip_fail(e, "hipMemsetAsync");
+            if ((e = launch_bits_to_queue(front, words, q, ctr + 3, c.stream)) != hipSuccess) return hip_fail(e, "b2q");
+            if ((rc = sync_read(c, host, ctr + 3, sizeof(unsigned long long)))) return rc;
+            qn = (int64_t)host[0];
+            topdown = true;
+        }
+    }
+    (void)prev;
+    (void)nadj;
+    br->levels = levels;
+    br->bottom_up = bu_levels;
+    br->visited = visited;
+    br->examined = examined;
+    *vis_out = vis;
+    return CC_OK;
+}
+
+// R0: CSR (if not built yet), BFS, label, filter, then SV on the rest
+int run_bfs_route(Call& c, DegreeResult& r) {
+    Workspace& ws = *c.ws;
+    int rc;
+    int t0 = c.timer->mark();
+    if (!r.csr_built) {
+        void *poff, *padj;
+        if ((rc = ws.get(WS_OFF, (size_t)(c.n + 1) * sizeof(int64_t), &poff))) return rc;
+        if ((rc = ws.get(WS_ADJ, (size_t)2 * c.m * sizeof(int32_t), &padj))) return rc;
+        r.off = (int64_t*)poff;
+        r.adj = (int32_t*)padj;
+        int k0 = c.kbeg();
+        hipError_t e = launch_bucket_csr_from_deg(c.n, r.plan, r.bufs, r.deg, r.off, r.adj, c.stream);
+        if (e != hipSuccess) return hip_fail(e, "csr launch");
+        c.kend(CC_K_CSR, k0, 16.0 * c.m + 12.0 * c.n);
+        if (c.stats) c.bytes += 16.0 * c.m + 12.0 * c.n;
+        r.csr_built = true;
+    }
+    int t1 = c.timer->mark();
+    uint32_t* vis = nullptr;
+    BfsResult br{};
+    rc = run_bfs(c, r.off, r.adj, 2 * c.m, r.argmax, r.max_degree, &vis, &br);
+    if (rc) return rc;
+    int t2 = c.timer->mark();
+    // label + filter
+    void *ptot, *pe0, *pcnt;
+    if ((rc = ws.get(WS_TOTALS, 64 * sizeof(unsigned long long), &ptot))) return rc;
+    unsigned long long* tot = (unsigned long long*)ptot + 24;
+    int32_t* dlabel = (int32_t*)((unsigned long long*)ptot + 28);
+    const int nseg = choose_nseg(c.m);
+    const int64_t cap = (c.m + nseg - 1) / nseg;
+    if ((rc = ws.get(WS_EDGES0, (size_t)nseg * cap * sizeof(int2), &pe0))) return rc;
+    if ((rc = ws.get(WS_SEGCOUNT, std::max((size_t)nseg * 4 * sizeof(uint32_t),
+                                           (size_t)(c.n + 1 + c.n / 1024 + 3) * sizeof(int64_t)),
+                     &pcnt)))
+        return rc;
+    uint32_t* fcnt = (uint32_t*)pcnt + (size_t)2 * nseg;
+    SegList out{(int2*)pe0, cap, nseg, fcnt};
+    int k0 = c.kbeg();
+    hipError_t e = hipMemsetAsync(dlabel, 0x7f, sizeof(int32_t), c.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(tot + 1, 0, sizeof(unsigned long long), c.stream);
+    if (e == hipSuccess) e = launch_bfs_label(vis, c.n, dlabel, c.parent, c.stream);
+    if (e == hipSuccess) e = launch_filter(c.u, c.v, c.m, c.n, vis, out, tot, tot + 1, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "label/filter launch");
+    int rec = c.kend(CC_K_FILTER, k0, 0.0);
+    unsigned long long* host;
+    if ((rc = ws.pinned((void**)&host))) return rc;
+    e = hipMemcpyAsync(host, tot, sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host + 1, dlabel, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) return hip_fail(e, "filter readback");
+    const int64_t kept = (int64_t)host[0];
+    const int32_t label = *(int32_t*)(host + 1);
+    // labels (4 B per vertex) + bitmap probe per vertex and per edge, edges read, survivors written
+    const double fbytes = 4.0 * c.n + 0.125 * c.n + 8.0 * c.m + 4.0 * c.m + 8.0 * kept;
+    c.kbytes(rec, fbytes);
+    if (c.stats) {
+        c.bytes += fbytes;
+        c.stats->bfs_levels = br.levels;
+        c.stats->bfs_bottom_up_levels = br.bottom_up;
+        c.stats->bfs_seed = r.argmax;
+        c.stats->bfs_label = label;
+        c.stats->bfs_visited = br.visited;
+        c.stats->bfs_edges_examined = br.examined;
+        c.stats->edges_after_filter = kept;
+    }
+    int t3 = c.timer->mark();
+    if (c.stats) {
+        c.stats->ms_csr = c.timer->ms(t0, t1);
+        c.stats->ms_bfs = c.timer->ms(t1, t2);
+        c.stats->ms_filter = c.timer->ms(t2, t3);
+    }
+    if (kept == 0) return CC_OK;
+    SvInput in;
+    in.soa = false;
+    in.m = kept;
+    in.seg = SegList{(int2*)pe0, cap, nseg, fcnt};
+    int t4 = c.timer->mark();
+    rc = run_sv(c, in, CC_R1_SV, c.opt.theta, c.opt.max_passes);
+    int t5 = c.timer->mark();
+    if (c.stats) c.stats->ms_sv = c.timer->ms(t4, t5);
+    return rc;
+}
+
+// --------------------------------------------------------------- driver
 int run_label(Call& c) {
+    int k0 = c.kbeg();
     hipError_t e = launch_sv_init(c.parent, c.n, c.stream);
     if (e != hipSuccess) return hip_fail(e, "sv_init launch");
+    c.kend(CC_K_SV_FINALIZE, k0, 4.0 * c.n);
     if (c.stats) c.bytes += 4.0 * c.n;
-    if (c.m == 0) return CC_OK;
-    int route = CC_R1_SV;
-    switch (c.opt.route) {
-        case CC_ROUTE_SV_THETA: route = CC_R2_SV_THETA; break;
-        default: route = CC_R1_SV; break;
+    if (c.m == 0) {
+        if (c.stats) c.stats->route = CC_R1_SV;
+        return CC_OK;
     }
-    if (c.stats) c.stats->route = route;
+    int req = c.opt.route;
+    if (req == CC_ROUTE_AUTO) req = router_loaded() ? CC_ROUTE_ROUTER : CC_ROUTE_HEURISTIC;
+    if (req == CC_ROUTE_ROUTER && !router_loaded()) return fail(CC_ENOROUTER, "no router weights loaded");
+    BucketPlan probe;
+    const bool can_predict = bucket_plan(c.n, c.m, &probe) == 0 && c.m <= (int64_t)1 << 31;
+    int route = CC_R1_SV;
+    DegreeResult dr;
+    int rc;
+    int tp0 = c.timer->mark();
+    if (req == CC_ROUTE_SV) route = CC_R1_SV;
+    else if (req == CC_ROUTE_SV_THETA) route = CC_R2_SV_THETA;
+    else if (!can_predict) route = CC_R1_SV;   // beyond the bucketed pass: SV handles any size
+    else if (req == CC_ROUTE_BFS_SV) {
+        if ((rc = run_degree_pass(c, true, &dr))) return rc;
+        route = CC_R0_BFS_SV;
+    } else {
+        if ((rc = run_degree_pass(c, false, &dr))) return rc;
+        if (req == CC_ROUTE_HEURISTIC) rc = decide_heuristic(c, dr, &route);
+        else rc = decide_router(c, dr, &route);
+        if (rc) return rc;
+    }
+    int tp1 = c.timer->mark();
+    if (c.stats) {
+        c.stats->route = route;
+        c.stats->ms_predict = c.timer->ms(tp0, tp1);
+    }
+    if (route == CC_R0_BFS_SV) {
+        if (dr.argmax < 0) route = CC_R1_SV;   // no edge with a valid endpoint: nothing to traverse
+        else return run_bfs_route(c, dr);
+    }
     SvInput in;
     in.soa = true;
     in.u = c.u;
     in.v = c.v;
     in.m = c.m;
     int t0 = c.timer->mark();
-    int rc = run_sv(c, in, route, c.opt.theta, c.opt.max_passes);
+    rc = run_sv(c, in, route, c.opt.theta, c.opt.max_passes);
     int t1 = c.timer->mark();
     if (c.stats) c.stats->ms_sv = c.timer->ms(t0, t1);
     return rc;

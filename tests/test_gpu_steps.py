@@ -1,0 +1,240 @@
+"""GPU parity of each step of the path against the oracle: degree, histograms,
+power-law fit, CSR, BFS, label + filter, routes R0 / heuristic / router, and
+the router network kernels."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import assert_labels_equal, oracle_labels, say, to_dev
+from oracle import degree as odeg
+from oracle import hybrid, ks, mlp
+
+pytestmark = pytest.mark.gpu
+ccmi = pytest.importorskip("paper_1607_06156_amd")
+
+SMALL = ["gnm64k", "rmat16", "grid512", "plcomp1m", "rmat18noisy"]
+KS_TOL = 1e-9
+
+
+@pytest.fixture(scope="module", params=SMALL)
+def graph(request):
+    return gen.workload(request.param)
+
+
+def test_degree_exact(graph):
+    say(f"[gpu] degree {graph.name}")
+    d = ccmi.degree(to_dev(graph.u), to_dev(graph.v), graph.n)
+    assert np.array_equal(d.cpu().numpy(), odeg.degree(graph.u, graph.v, graph.n))
+
+
+def test_degree_ragged_and_selfloops():
+    rng = np.random.default_rng(3)
+    for m in [1, 7, 255, 1000, 65537]:
+        n = int(rng.integers(2, 70_000))
+        u = rng.integers(0, n, m).astype(np.int32)
+        v = rng.integers(0, n, m).astype(np.int32)
+        v[::5] = u[::5]
+        d = ccmi.degree(to_dev(u), to_dev(v), n)
+        assert np.array_equal(d.cpu().numpy(), odeg.degree(u, v, n)), m
+
+
+def test_degree_range_error():
+    with pytest.raises(ccmi.CCError) as ei:
+        ccmi.degree(to_dev(np.array([0, 9], np.int32)), to_dev(np.array([1, 1], np.int32)), 5)
+    assert ei.value.code == ccmi.CC_ERANGE
+
+
+def test_histograms_exact(graph):
+    say(f"[gpu] histograms {graph.name}")
+    deg = odeg.degree(graph.u, graph.v, graph.n)
+    h64, hx, tail, tcount, amax = ccmi.degree_histograms(to_dev(deg))
+    e64, ex, etail = odeg.histograms(deg)
+    assert np.array_equal(h64.cpu().numpy(), e64)
+    assert np.array_equal(hx.cpu().numpy(), ex)
+    assert tcount == etail.shape[0]
+    assert np.array_equal(np.sort(tail.cpu().numpy()), etail)
+    assert amax == hybrid.choose_seed(deg)
+
+
+def test_histograms_tail_and_ties():
+    # degrees above 4096 and ties for the maximum (smallest id wins)
+    deg = np.zeros(20_000, np.int32)
+    deg[[5, 17, 9000]] = 7000
+    deg[100:5000] = np.arange(4900) % 5000
+    h64, hx, tail, tcount, amax = ccmi.degree_histograms(to_dev(deg))
+    e64, ex, etail = odeg.histograms(deg)
+    assert np.array_equal(h64.cpu().numpy(), e64) and np.array_equal(hx.cpu().numpy(), ex)
+    assert np.array_equal(np.sort(tail.cpu().numpy()), etail) and amax == 5
+
+
+def _ks_compare(vals_hist, tail):
+    got = ccmi.powerlaw_ks(vals_hist, tail)
+    v, c = odeg.distribution_from_histograms(np.asarray(vals_hist), np.asarray(tail))
+    exp = ks.fit(v, c)
+    say(f"   ks gpu={got['ks']:.12g} oracle={exp['ks']:.12g} alpha {got['alpha']:.10g}/{exp['alpha']:.10g} "
+        f"dmin {got['dmin']}/{exp['dmin']}")
+    if math.isinf(exp["ks"]):
+        assert math.isinf(got["ks"])
+        return got
+    assert abs(got["ks"] - exp["ks"]) <= KS_TOL
+    assert got["candidates"] == exp["candidates"]
+    if got["dmin"] == exp["dmin"]:
+        assert abs(got["alpha"] - exp["alpha"]) <= 1e-8 * exp["alpha"]
+        assert got["ntail"] == exp["ntail"]
+    return got
+
+
+def test_powerlaw_fit_vs_oracle(graph):
+    deg = odeg.degree(graph.u, graph.v, graph.n)
+    _, ex, etail = odeg.histograms(deg)
+    _ks_compare(ex, etail.astype(np.int32))
+
+
+def test_powerlaw_fit_exact_law_and_edge_cases():
+    d = np.arange(1, 3000)
+    pmf = d.astype(float) ** -2.9
+    cnt = np.round(1e12 * pmf / pmf.sum()).astype(np.int64)
+    hx = np.zeros(4096, np.int64)
+    hx[d] = cnt
+    got = _ks_compare(hx, np.zeros(0, np.int32))
+    assert abs(got["alpha"] - 2.9) < 1e-2
+    # no candidate cutoff -> +inf
+    hx = np.zeros(4096, np.int64)
+    hx[3] = 10
+    assert math.isinf(ccmi.powerlaw_ks(hx, np.zeros(0, np.int32))["ks"])
+
+
+def test_csr_exact(graph):
+    say(f"[gpu] csr {graph.name}")
+    off, adj, deg = ccmi.csr(to_dev(graph.u), to_dev(graph.v), graph.n)
+    eoff, eadj = hybrid.csr(graph.u, graph.v, graph.n)
+    off = off.cpu().numpy()
+    assert np.array_equal(off, eoff)
+    assert np.array_equal(deg.cpu().numpy(), np.diff(eoff))
+    # each row holds the same multiset of neighbours
+    rows = np.repeat(np.arange(graph.n), np.diff(eoff))
+    got = np.lexsort((adj.cpu().numpy(), rows))
+    exp = np.lexsort((eadj, rows))
+    assert np.array_equal(adj.cpu().numpy()[got], eadj[exp])
+
+
+def test_bfs_visited_exact(graph):
+    off, adj, deg = ccmi.csr(to_dev(graph.u), to_dev(graph.v), graph.n)
+    d = deg.cpu().numpy()
+    seeds = [hybrid.choose_seed(d), int(np.random.default_rng(1).integers(0, graph.n))]
+    for s in seeds:
+        say(f"[gpu] bfs {graph.name} seed={s}")
+        vis, levels, bu = ccmi.bfs(off, adj, graph.n, s)
+        bits = np.unpackbits(vis.cpu().numpy().view(np.uint8), bitorder="little")[: graph.n].astype(bool)
+        exp = hybrid.bfs_visited(graph.u, graph.v, graph.n, s)
+        assert np.array_equal(bits, exp)
+        assert levels == hybrid.bfs_levels(graph.u, graph.v, graph.n, s)
+
+
+def test_bfs_filter_exact(graph):
+    u, v = to_dev(graph.u), to_dev(graph.v)
+    off, adj, deg = ccmi.csr(u, v, graph.n)
+    r = hybrid.bfs_route(graph.u, graph.v, graph.n)
+    vis, _, _ = ccmi.bfs(off, adj, graph.n, r["seed"])
+    labels, fu, fv, label = ccmi.bfs_filter(u, v, graph.n, vis)
+    assert label == r["label"]
+    exp_lab = np.where(r["visited"], r["label"], np.arange(graph.n))
+    assert np.array_equal(labels.cpu().numpy(), exp_lab)
+    got = np.sort(fu.cpu().numpy().astype(np.int64) * graph.n + fv.cpu().numpy())
+    exp = np.sort(r["u"].astype(np.int64) * graph.n + r["v"])
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("route", ["bfs+sv", "heuristic", "auto"])
+def test_routes_exact(graph, route):
+    lab, st = ccmi.label(to_dev(graph.u), to_dev(graph.v), graph.n, route=route, stats=True)
+    say(f"[gpu] {graph.name} {route}: took {st['route_name']} ks={st['ks_statistic']:.4g} "
+        f"bfs_levels={st['bfs_levels']} visited={st['bfs_visited']} after_filter={st['edges_after_filter']} "
+        f"passes={st['sv_passes']}")
+    assert_labels_equal(lab, oracle_labels(graph), f"{graph.name}/{route}")
+    if route in ("heuristic", "auto") and not ccmi.router_loaded():
+        deg = odeg.degree(graph.u, graph.v, graph.n)
+        v, c = odeg.distribution(deg)
+        exp = ks.fit(v, c)
+        assert abs(st["ks_statistic"] - exp["ks"]) <= KS_TOL
+        assert st["route"] == (ccmi.R0_BFS_SV if ks.decide_bfs(exp["ks"]) else ccmi.R1_SV)
+    if st["route"] == ccmi.R0_BFS_SV:
+        r = hybrid.bfs_route(graph.u, graph.v, graph.n)
+        assert st["bfs_seed"] == r["seed"] and st["bfs_label"] == r["label"]
+        assert st["bfs_visited"] == int(r["visited"].sum())
+        assert st["edges_after_filter"] == r["u"].shape[0]
+
+
+def test_route_edge_cases():
+    for u, v, n in [([], [], 5), ([2], [2], 3), ([0], [1], 2), ([3, 1], [1, 3], 4)]:
+        u = np.array(u, np.int32)
+        v = np.array(v, np.int32)
+        g = gen.Graph(u, v, n, "tiny")
+        for route in ["bfs+sv", "heuristic"]:
+            assert_labels_equal(ccmi.label(to_dev(u), to_dev(v), n, route=route), oracle_labels(g), f"tiny/{route}")
+
+
+# ---------------------------------------------------------------- router
+def _params(seed):
+    ps = mlp.init_params(seed, dtype=np.float64)
+    flat = np.concatenate([p.reshape(-1) for p in ps]).astype(np.float32)
+    assert flat.size == ccmi.ROUTER_NPARAMS
+    return ps, flat
+
+
+def _unflat(flat):
+    out, o = [], 0
+    for shp in [(64, 66), (64,), (64, 64), (64,), (3, 64), (3,)]:
+        k = int(np.prod(shp))
+        out.append(flat[o:o + k].reshape(shp).astype(np.float64))
+        o += k
+    return out
+
+
+def test_mlp_forward_vs_fp64():
+    ps, flat = _params(1)
+    rng = np.random.default_rng(2)
+    x = rng.random((257, 66)).astype(np.float32)
+    got = ccmi.mlp_forward(torch.from_numpy(flat).cuda(), torch.from_numpy(x).cuda()).cpu().numpy()
+    exp, _ = mlp.forward(_unflat(flat), x.astype(np.float64))
+    assert np.allclose(got, exp, rtol=1e-5, atol=1e-5)
+
+
+def test_mlp_sgd_step_vs_fp64():
+    _, flat = _params(3)
+    rng = np.random.default_rng(4)
+    x = rng.random((100, 66)).astype(np.float32)
+    y = rng.integers(0, 3, 100).astype(np.int32)
+    P = torch.from_numpy(flat.copy()).cuda()
+    loss, g = ccmi.mlp_sgd_step(P, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), 0.05, want_grads=True)
+    eloss, egrads = mlp.loss_and_grads(_unflat(flat), x.astype(np.float64), y)
+    eg = np.concatenate([q.reshape(-1) for q in egrads])
+    assert abs(loss - eloss) <= 1e-5 * max(1.0, abs(eloss))
+    assert np.allclose(g.cpu().numpy(), eg, rtol=1e-4, atol=2e-6)
+    assert np.allclose(P.cpu().numpy(), flat - 0.05 * eg, rtol=1e-5, atol=1e-6)
+
+
+def test_router_route_matches_fp64_argmax():
+    g = gen.workload("rmat16")
+    _, flat = _params(5)
+    ccmi.router_set(flat)
+    try:
+        lab, st = ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route="router", stats=True)
+        assert_labels_equal(lab, oracle_labels(g), "router")
+        deg = odeg.degree(g.u, g.v, g.n)
+        log64, _, _ = odeg.histograms(deg)
+        feats = odeg.router_features(log64, g.n, g.m).astype(np.float32).astype(np.float64)
+        z, _ = mlp.forward(_unflat(flat), feats[None, :])
+        assert np.allclose(st["router_logits"], z[0], rtol=1e-4, atol=1e-4)
+        zs = np.sort(z[0])
+        if zs[-1] - zs[-2] > 1e-3:
+            assert st["route"] == int(np.argmax(z[0]))
+    finally:
+        ccmi.router_set(None)
+    with pytest.raises(ccmi.CCError) as ei:
+        ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route="router")
+    assert ei.value.code == ccmi.CC_ENOROUTER
