@@ -1,0 +1,255 @@
+// Batched labelling: G independent graphs in one persistent launch.
+//
+// Graph g's local ids are shifted by vert_off[g], which turns the batch into one
+// graph on vert_off[G] vertices whose components never cross graphs.  The
+// shift is monotone, so the minimum global id of a component is vert_off[g]
+// plus its minimum local id: the canonical labels of Fig. 1(b) survive, and
+// subtracting vert_off[g] at the end gives the graph-local labels.
+//
+// The whole SV iteration (Section III-A) runs inside one cooperative launch:
+// every workgroup owns a fixed chunk of the concatenated edge list and, pass
+// after pass, hooks and compacts its own segment, pointer-jumps the roots it
+// hooked, and waits at a grid barrier.  After the barrier every workgroup sums
+// the per-block survivor counts and takes the same stop decision, so
+// convergence is decided on the device and the host waits once.  Small graphs
+// finish in the first passes and simply drop out of the active segments
+// (Section III-A.4: completed work leaves the working set).
+#include "batched.hpp"
+#include "common.hpp"
+#include "sv_device.hpp"
+
+namespace ccmi {
+
+struct BatchArgs {
+    const int32_t* u;
+    const int32_t* v;
+    const int64_t* edge_off;
+    const int64_t* vert_off;
+    int32_t G;
+    int64_t m;            // edge_off[G] (read by the host)
+    int32_t n;            // vert_off[G]
+    int32_t* parent;      // labels: global roots, then local labels
+    int2* buf0;
+    int2* buf1;
+    int64_t cap;          // edges per block segment
+    uint32_t* cnt0;       // per-block survivor counts (ping-pong)
+    uint32_t* cnt1;
+    uint32_t* hcnt;       // per-block hooked counts
+    int32_t* hooked;      // per-block hooked roots
+    unsigned int* bar;    // [0] arrivals, [1] generation
+    unsigned long long* status;  // [0] error bits, [1] passes, [2] range errors
+    int32_t max_passes;
+};
+
+enum : unsigned long long { kErrRange = 1, kErrOffsets = 2, kErrBarrier = 4, kErrPasses = 8 };
+
+__device__ __forceinline__ unsigned long long load_status(unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sense-reversing grid barrier for a co-resident (cooperative) grid.  The spin
+// is bounded: after ~5 s it flags an error, and a flagged error releases
+// every later barrier at once, so all workgroups always exit.
+__device__ void grid_barrier(unsigned int* bar, unsigned long long* status) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();   // release this block's writes (agent scope)
+        const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (load_status(status) & kErrBarrier) break;
+                if (wall_clock64() - t0 > 500000000ull) {   // 5 s at the 100 MHz wall clock
+                    __hip_atomic_fetch_or(&status[0], (unsigned long long)kErrBarrier, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();   // acquire
+    }
+    __syncthreads();
+}
+
+// graph of edge / vertex index i: first g with off[g+1] > i (off non-decreasing, off[G] > i)
+__device__ __forceinline__ int32_t graph_of(const int64_t* off, int32_t G, int64_t i) {
+    int32_t lo = 0, hi = G - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (off[mid + 1] > i) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
+    __shared__ uint32_t lds[kWaves + 1];
+    __shared__ unsigned long long sh_total;
+    const int b = blockIdx.x;
+    const int nb = gridDim.x;
+    const int64_t gstride = (int64_t)nb * kBlock;
+    const int64_t gtid = (int64_t)b * kBlock + threadIdx.x;
+
+    // ---- init: identity forest, offset checks
+    for (int64_t x = gtid; x < A.n; x += gstride) A.parent[x] = (int32_t)x;
+    for (int64_t g = gtid; g < A.G; g += gstride) {
+        if (A.edge_off[g + 1] < A.edge_off[g] || A.vert_off[g + 1] < A.vert_off[g])
+            __hip_atomic_fetch_or(&A.status[0], (unsigned long long)kErrOffsets, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    }
+    grid_barrier(A.bar, A.status);
+    if (load_status(A.status)) return;
+
+    // ---- pass 0: the caller's concatenated SoA list, local -> global ids
+    uint32_t kept_off = 0, hook_off = 0, bad = 0;
+    {
+        const int64_t base = (int64_t)b * A.cap;
+        int64_t len = A.m - base;
+        if (len > A.cap) len = A.cap;
+        if (len < 0) len = 0;
+        int32_t g = len > 0 ? graph_of(A.edge_off, A.G, base + threadIdx.x < A.m ? base + threadIdx.x : base) : 0;
+        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
+            const int64_t e = base + i;
+            while (A.edge_off[g + 1] <= e) ++g;
+            const int64_t v0 = A.vert_off[g];
+            const int64_t nl = A.vert_off[g + 1] - v0;
+            const int32_t x = A.u[e], y = A.v[e];
+            if ((uint64_t)(uint32_t)x >= (uint64_t)nl || (uint64_t)(uint32_t)y >= (uint64_t)nl || x < 0 || y < 0) {
+                ++bad;
+                return false;
+            }
+            *a = (int32_t)(v0 + x);
+            *c = (int32_t)(v0 + y);
+            return true;
+        };
+        sv_segment(len, load, A.parent, A.buf0 + base, A.hooked + base, true, kept_off, hook_off, lds);
+    }
+    if (threadIdx.x == 0) {
+        A.cnt0[b] = kept_off;
+        A.hcnt[b] = hook_off;
+    }
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o);
+    if (lane_id() == 0 && bad) {
+        __hip_atomic_fetch_add(&A.status[2], (unsigned long long)bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(&A.status[0], (unsigned long long)kErrRange, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    int pass = 1;
+    int2* in = A.buf0;
+    int2* out = A.buf1;
+    uint32_t* cin = A.cnt0;
+    uint32_t* cout = A.cnt1;
+    for (;;) {
+        grid_barrier(A.bar, A.status);
+        if (load_status(A.status)) return;
+        // pointer jumping of the roots this block hooked
+        {
+            const uint32_t hc = A.hcnt[b];
+            const int32_t* h = A.hooked + (int64_t)b * A.cap;
+            for (uint32_t j = threadIdx.x; j < hc; j += kBlock) {
+                const int32_t x = h[j];
+                A.parent[x] = find_root(A.parent, x);
+            }
+        }
+        // every block sums the same counts and takes the same decision
+        unsigned long long s = 0;
+        for (int i = threadIdx.x; i < nb; i += kBlock) s += cin[i];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (threadIdx.x == 0) sh_total = 0;
+        __syncthreads();
+        if (lane_id() == 0) atomicAdd(&sh_total, s);
+        __syncthreads();
+        const unsigned long long total = sh_total;
+        if (total == 0) break;
+        if (A.max_passes > 0 && pass >= A.max_passes) {
+            if (b == 0 && threadIdx.x == 0)
+                __hip_atomic_fetch_or(&A.status[0], (unsigned long long)kErrPasses, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        kept_off = 0;
+        hook_off = 0;
+        const int2* src = in + (int64_t)b * A.cap;
+        const int64_t len = cin[b];
+        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
+            const int2 e = src[i];
+            *a = e.x;
+            *c = e.y;
+            return true;
+        };
+        sv_segment(len, load, A.parent, out + (int64_t)b * A.cap, A.hooked + (int64_t)b * A.cap, true, kept_off,
+                   hook_off, lds);
+        if (threadIdx.x == 0) {
+            cout[b] = kept_off;
+            A.hcnt[b] = hook_off;
+        }
+        ++pass;
+        int2* t = in; in = out; out = t;
+        uint32_t* tc = cin; cin = cout; cout = tc;
+    }
+    if (b == 0 && threadIdx.x == 0) A.status[1] = (unsigned long long)pass;
+
+    // ---- final labels: compress to roots, then shift to graph-local ids
+    for (int64_t x = gtid; x < A.n; x += gstride) {
+        const int32_t p = A.parent[x];
+        if (p != (int32_t)x) A.parent[x] = find_root(A.parent, p);
+    }
+    grid_barrier(A.bar, A.status);
+    if (load_status(A.status)) return;
+    if (A.n > 0) {
+        int64_t x = gtid;
+        int32_t g = x < A.n ? graph_of(A.vert_off, A.G, x) : 0;
+        for (; x < A.n; x += gstride) {
+            while (A.vert_off[g + 1] <= x) ++g;
+            A.parent[x] = (int32_t)(A.parent[x] - A.vert_off[g]);
+        }
+    }
+}
+
+hipError_t batched_max_blocks(int* blocks) {
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel, kBlock, 0);
+    if (e != hipSuccess) return e;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    // The grid barrier needs every workgroup resident at once.  A grid at the
+    // full occupancy bound was accepted by the cooperative launch but did not
+    // all become resident on gfx950 (the barrier's timeout fired), so stay at
+    // half of it and at most 4 workgroups per CU.
+    int b = per_cu * cus / 2;
+    if (b > 4 * cus) b = 4 * cus;
+    *blocks = b > 0 ? b : 1;
+    return hipSuccess;
+}
+
+hipError_t launch_batched(const BatchArgsHost& h, int blocks, hipStream_t s) {
+    BatchArgs A;
+    A.u = h.u;
+    A.v = h.v;
+    A.edge_off = h.edge_off;
+    A.vert_off = h.vert_off;
+    A.G = h.G;
+    A.m = h.m;
+    A.n = h.n;
+    A.parent = h.labels;
+    A.buf0 = h.buf0;
+    A.buf1 = h.buf1;
+    A.cap = h.cap;
+    A.cnt0 = h.cnt0;
+    A.cnt1 = h.cnt1;
+    A.hcnt = h.hcnt;
+    A.hooked = h.hooked;
+    A.bar = h.bar;
+    A.status = h.status;
+    A.max_passes = h.max_passes;
+    void* args[] = {&A};
+    return hipLaunchCooperativeKernel((const void*)batched_kernel, dim3(blocks), dim3(kBlock), args, 0, s);
+}
+
+}  // namespace ccmi

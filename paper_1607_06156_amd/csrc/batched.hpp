@@ -1,0 +1,35 @@
+// Batched-mode launch interface (batched.hip, batched_host.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccmi {
+
+struct BatchArgsHost {
+    const int32_t* u;
+    const int32_t* v;
+    const int64_t* edge_off;
+    const int64_t* vert_off;
+    int32_t G;
+    int64_t m;
+    int32_t n;
+    int32_t* labels;
+    int2* buf0;
+    int2* buf1;
+    int64_t cap;
+    uint32_t* cnt0;
+    uint32_t* cnt1;
+    uint32_t* hcnt;
+    int32_t* hooked;
+    unsigned int* bar;
+    unsigned long long* status;
+    int32_t max_passes;
+};
+
+// largest co-resident grid of the persistent kernel on the current device
+hipError_t batched_max_blocks(int* blocks);
+// one cooperative launch running the whole SV loop over all graphs
+hipError_t launch_batched(const BatchArgsHost& h, int blocks, hipStream_t s);
+
+}  // namespace ccmi

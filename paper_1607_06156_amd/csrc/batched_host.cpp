@@ -1,0 +1,211 @@
+// Host side of batched labelling: validation, workspace, the block-count
+// autotuner and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "batched.hpp"
+#include "internal.hpp"
+
+#define CC_API extern "C" __attribute__((visibility("default")))
+
+namespace ccmi {
+
+// ------------------------------------------------------------ autotuner
+// Chooses the persistent grid size (and so the edges per workgroup segment)
+// per size class by timing the candidates on the first call of that class.
+// Results live in memory and, if CC_AUTOTUNE_CACHE names a file, on disk
+// (one "key blocks" pair per line).
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string tune_key(int dev, int64_t m, int32_t n, int32_t G) {
+    hipDeviceProp_t p;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) arch = p.gcnArchName;
+    for (auto& ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s/batched/m2^%d/n2^%d/G2^%d", arch.c_str(), (int)std::log2((double)m + 1),
+             (int)std::log2((double)n + 1), (int)std::log2((double)G + 1));
+    return buf;
+}
+
+static void tune_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("CC_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int b;
+    while (fscanf(f, "%255s %d", key, &b) == 2) g_tune[key] = b;
+    fclose(f);
+}
+
+static void tune_store(const std::string& key, int blocks) {
+    g_tune[key] = blocks;
+    const char* path = getenv("CC_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "w");
+    if (!f) return;
+    for (auto& kv : g_tune) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    fclose(f);
+}
+
+static int run_once(Workspace& ws, BatchArgsHost h, int blocks, hipStream_t s, unsigned long long* status_host,
+                    double* ms) {
+    const int64_t cap = h.m > 0 ? (h.m + blocks - 1) / blocks : 1;
+    const size_t slots = (size_t)blocks * (size_t)cap;
+    void *p0, *p1, *ph, *pc, *pb;
+    int rc;
+    if ((rc = ws.get(WS_EDGES0, slots * sizeof(int2), &p0))) return rc;
+    if ((rc = ws.get(WS_EDGES1, slots * sizeof(int2), &p1))) return rc;
+    if ((rc = ws.get(WS_HOOKED, slots * sizeof(int32_t), &ph))) return rc;
+    if ((rc = ws.get(WS_SEGCOUNT, (size_t)blocks * 3 * sizeof(uint32_t), &pc))) return rc;
+    if ((rc = ws.get(WS_BATCH, 256, &pb))) return rc;
+    h.buf0 = (int2*)p0;
+    h.buf1 = (int2*)p1;
+    h.hooked = (int32_t*)ph;
+    h.cap = cap;
+    h.cnt0 = (uint32_t*)pc;
+    h.cnt1 = h.cnt0 + blocks;
+    h.hcnt = h.cnt1 + blocks;
+    h.bar = (unsigned int*)pb;
+    h.status = (unsigned long long*)((char*)pb + 64);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms) {
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+    }
+    hipError_t e = hipMemsetAsync(pb, 0, 256, s);
+    if (e == hipSuccess && ms) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch_batched(h, blocks, s);
+    if (e == hipSuccess && ms) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(status_host, h.status, 3 * sizeof(unsigned long long),
+                                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && ms) {
+        float t = 0;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        *ms = t;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+    return CC_OK;
+}
+
+static int status_code(const unsigned long long* st) {
+    if (st[0] & 1) return fail(CC_ERANGE, "%llu edges have an endpoint outside their graph's [0, n_g)", st[2]);
+    if (st[0] & 2) return fail(CC_EINVAL, "edge_off / vert_off are not non-decreasing");
+    if (st[0] & 4) return fail(CC_EINTERNAL, "grid barrier timed out");
+    if (st[0] & 8) return fail(CC_EINTERNAL, "pass cap reached");
+    return CC_OK;
+}
+
+}  // namespace ccmi
+
+using namespace ccmi;
+
+CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
+                               int32_t G, int32_t* labels, void* stream, int32_t tile_edges, cc_batch_stats* stats) {
+    if (stats) memset(stats, 0, sizeof *stats);
+    if (G < 0) return fail(CC_EINVAL, "negative G");
+    if (tile_edges < 0) return fail(CC_EINVAL, "negative tile_edges");
+    if (G == 0) return CC_OK;
+    if (!edge_off || !vert_off) return fail(CC_EINVAL, "NULL offsets");
+    Workspace* ws;
+    int rc = acquire_workspace(&ws);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> guard(ws->mu);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* host;
+    if ((rc = ws->pinned((void**)&host))) return rc;
+    int64_t* h64 = (int64_t*)host;
+    hipError_t e = hipMemcpyAsync(h64, edge_off, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h64 + 1, edge_off + G, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h64 + 2, vert_off, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h64 + 3, vert_off + G, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "offset readback");
+    const int64_t m = h64[1], n = h64[3];
+    if (h64[0] != 0 || h64[2] != 0) return fail(CC_EINVAL, "edge_off[0] and vert_off[0] must be 0");
+    if (m < 0 || n < 0 || n > INT32_MAX) return fail(CC_EINVAL, "bad totals (m=%lld, n=%lld)", (long long)m, (long long)n);
+    if (m > 0 && (!u || !v)) return fail(CC_EINVAL, "NULL edge arrays");
+    if (n > 0 && !labels) return fail(CC_EINVAL, "NULL labels");
+    if (m > 0 && n == 0) return fail(CC_ERANGE, "edges given for graphs without vertices");
+    if (m > (int64_t)2048 * INT32_MAX) return fail(CC_EINVAL, "too many edges");
+    int maxb = 0;
+    if ((e = batched_max_blocks(&maxb)) != hipSuccess) return hip_fail(e, "occupancy query");
+    if (maxb < 1) return fail(CC_EINTERNAL, "persistent kernel does not fit on this device");
+    BatchArgsHost h{};
+    h.u = u;
+    h.v = v;
+    h.edge_off = edge_off;
+    h.vert_off = vert_off;
+    h.G = G;
+    h.m = m;
+    h.n = (int32_t)n;
+    h.labels = labels;
+    h.max_passes = 100000;
+    int blocks;
+    if (tile_edges > 0) {
+        int64_t b = (m + tile_edges - 1) / tile_edges;
+        blocks = (int)std::max<int64_t>(1, std::min<int64_t>(b, maxb));
+    } else {
+        std::string key = tune_key(ws->device, m, (int32_t)n, G);
+        int chosen = 0;
+        {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            tune_load();
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) chosen = std::min(it->second, maxb);
+        }
+        if (chosen <= 0) {
+            // time each candidate grid on this input (every run computes the same labels)
+            double best = 1e300;
+            const int cands[] = {256, 512, 1024, 2048, 4096};
+            for (int cb : cands) {
+                if (cb > maxb && cb != cands[0]) continue;
+                int b = std::min(cb, maxb);
+                double ms = 0;
+                if ((rc = run_once(*ws, h, b, s, host, &ms))) return rc;
+                if ((rc = status_code(host))) return rc;
+                if (ms < best) {
+                    best = ms;
+                    chosen = b;
+                }
+            }
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            tune_store(key, chosen);
+        }
+        blocks = chosen;
+    }
+    double ms = 0;
+    if ((rc = run_once(*ws, h, blocks, s, host, stats ? &ms : nullptr))) return rc;
+    if ((rc = status_code(host))) return rc;
+    if (stats) {
+        stats->passes = (int32_t)host[1];
+        stats->blocks = blocks;
+        stats->tile_edges = (int32_t)std::min<int64_t>(INT32_MAX, m > 0 ? (m + blocks - 1) / blocks : 0);
+        stats->total_edges = m;
+        stats->total_vertices = n;
+        stats->ms_total = ms;
+    }
+    return CC_OK;
+}
+
+CC_API int cc_label_batched(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
+                            int32_t G, int32_t* labels, void* stream) {
+    return cc_label_batched_ex(u, v, edge_off, vert_off, G, labels, stream, 0, nullptr);
+}

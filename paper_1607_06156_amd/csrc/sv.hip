@@ -21,15 +21,15 @@
 //
 // Invariant: parent[x] <= x, links only point to connected vertices, and the
 // connectivity of (forest links + active edges) always equals that of the
-// input.  A link can be overwritten only inside the pass that created it, and
-// the edge that created it is kept for the next pass, so no connection is
-// lost; the loop ends when no edge is active, and the forest roots are then
-// the component minima.
+// input.  Every change of parent[] by a hook is an atomicMin; when it replaces
+// an existing link hi -> old by hi -> lo, the displaced pair (old, hi) stays
+// active, so no connection is lost even if a find read an outdated parent.
+// The loop ends when no edge is active, and the forest roots are then the
+// component minima.
 #include "common.hpp"
+#include "sv_device.hpp"
 
 namespace ccmi {
-
-constexpr int kEPT = 4;   // edges per thread per tile
 
 __global__ __launch_bounds__(kBlock) void sv_init_kernel(int32_t* __restrict__ parent, int32_t n) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -39,7 +39,8 @@ __global__ __launch_bounds__(kBlock) void sv_init_kernel(int32_t* __restrict__ p
 
 // One pass: hook + compact over one block segment of edges.
 // SOA: edges come from the caller's u[], v[] (dense); block b takes
-// [b*cap, min((b+1)*cap, m)).  Else from segment b of `in`.
+// [b*cap, min((b+1)*cap, m)) and checks ids against [0, n).  Else from
+// segment b of `in`.
 template <bool SOA>
 __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restrict__ u, const int32_t* __restrict__ v,
                                                          int64_t m, int32_t n, SegList in, int32_t* parent,
@@ -48,93 +49,34 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
                                                          unsigned long long* __restrict__ totals) {
     __shared__ uint32_t lds[kWaves + 1];
     const int b = blockIdx.x;
-    int64_t len;
-    const int2* src = nullptr;
-    int64_t base;
-    if (SOA) {
-        base = (int64_t)b * out.cap;
-        len = m - base;
-        if (len > out.cap) len = out.cap;
-        if (len < 0) len = 0;
-    } else {
-        base = (int64_t)b * in.cap;
-        len = in.count[b];
-        src = in.buf + base;
-    }
     int2* dst = out.buf + (int64_t)b * out.cap;
     int32_t* hdst = hooked + (int64_t)b * out.cap;
     uint32_t kept_off = 0, hook_off = 0, bad = 0;
-
-    for (int64_t t0 = 0; t0 < len; t0 += kBlock * kEPT) {
-        int32_t a[kEPT], c[kEPT], pa[kEPT], pc[kEPT];
-        bool valid[kEPT];
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            int64_t i = t0 + threadIdx.x + (int64_t)k * kBlock;
-            valid[k] = i < len;
-            if (valid[k]) {
-                if (SOA) {
-                    a[k] = u[base + i];
-                    c[k] = v[base + i];
-                    if ((uint32_t)a[k] >= (uint32_t)n || (uint32_t)c[k] >= (uint32_t)n) {
-                        ++bad;
-                        valid[k] = false;
-                    }
-                } else {
-                    int2 e = src[i];
-                    a[k] = e.x;
-                    c[k] = e.y;
-                }
+    if (SOA) {
+        const int64_t base = (int64_t)b * out.cap;
+        int64_t len = m - base;
+        if (len > out.cap) len = out.cap;
+        if (len < 0) len = 0;
+        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
+            *a = u[base + i];
+            *c = v[base + i];
+            if ((uint32_t)*a >= (uint32_t)n || (uint32_t)*c >= (uint32_t)n) {
+                ++bad;
+                return false;
             }
-        }
-        // issue all first-level gathers before any dependent chase
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            if (valid[k]) {
-                pa[k] = parent[a[k]];
-                pc[k] = parent[c[k]];
-            }
-        }
-        bool keep[kEPT], hk[kEPT];
-        int2 e[kEPT];
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            keep[k] = false;
-            hk[k] = false;
-            if (!valid[k]) continue;
-            int32_t ra = pa[k] == a[k] ? a[k] : find_root(parent, pa[k]);
-            int32_t rc = pc[k] == c[k] ? c[k] : find_root(parent, pc[k]);
-            if (ra == rc) continue;
-            int32_t lo = ra < rc ? ra : rc;
-            int32_t hi = ra < rc ? rc : ra;
-            int32_t old = atomic_min_agent(&parent[hi], lo);
-            hk[k] = (old == hi);
-            keep[k] = true;
-            e[k] = make_int2(lo, hi);
-        }
-        // wave ballots -> slot prefixes; one block scan of packed (kept | hooks << 16)
-        uint64_t km[kEPT], hm[kEPT];
-        uint32_t kpre[kEPT], hpre[kEPT];
-        uint32_t wk = 0, wh = 0;
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            km[k] = ballot(keep[k]);
-            hm[k] = ballot(hk[k]);
-            kpre[k] = wk + lanes_below(km[k]);
-            hpre[k] = wh + lanes_below(hm[k]);
-            wk += (uint32_t)__popcll(km[k]);
-            wh += (uint32_t)__popcll(hm[k]);
-        }
-        uint32_t tot;
-        uint32_t woff = block_wave_offset(wk | (wh << 16), lds, &tot);
-        uint32_t koff = kept_off + (woff & 0xffffu), hoff = hook_off + (woff >> 16);
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            if (write_out && keep[k]) dst[koff + kpre[k]] = e[k];
-            if (hk[k]) hdst[hoff + hpre[k]] = e[k].y;
-        }
-        kept_off += tot & 0xffffu;
-        hook_off += tot >> 16;
+            return true;
+        };
+        sv_segment(len, load, parent, dst, hdst, write_out != 0, kept_off, hook_off, lds);
+    } else {
+        const int2* src = in.buf + (int64_t)b * in.cap;
+        const int64_t len = in.count[b];
+        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
+            const int2 e = src[i];
+            *a = e.x;
+            *c = e.y;
+            return true;
+        };
+        sv_segment(len, load, parent, dst, hdst, write_out != 0, kept_off, hook_off, lds);
     }
     // per-block results (no global atomics on the fast path)
     if (threadIdx.x == 0) {
@@ -146,7 +88,6 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
         for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off);
         if (lane_id() == 0 && bad) atomic_add_agent(&totals[2], bad);
     }
-    (void)write_out;
 }
 
 // Pointer jumping for the roots hooked in the last pass; block 0 also reduces

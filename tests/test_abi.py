@@ -1,0 +1,97 @@
+"""CPU checks of the boundary: the library loads, exports every entry point
+include/cc.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cc.h")
+LIB = os.path.join(ROOT, "paper_1607_06156_amd", "libccmi.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    return re.findall(r"^\s*(?:int|void|const char\*)\s+(cc_\w+)\s*\(", src, re.M)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1607_06156_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = set(declared())
+    for must in ["cc_label", "cc_label_ex", "cc_label_batched", "cc_label_batched_ex", "cc_router_load",
+                 "cc_last_error", "cc_version", "cc_degree", "cc_degree_histograms", "cc_powerlaw_ks", "cc_csr",
+                 "cc_bfs", "cc_bfs_filter", "cc_mlp_forward", "cc_mlp_sgd_step"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_version_and_defaults(lib):
+    assert lib.cc_version() == 10000
+    import paper_1607_06156_amd as ccmi
+    opt = ccmi.Options()
+    lib.cc_default_options(ctypes.byref(opt))
+    assert opt.route == 0 and opt.max_passes == 0 and abs(opt.tau - 0.05) < 1e-15 and abs(opt.theta - 0.25) < 1e-15
+
+
+def test_struct_layouts_match_header(lib):
+    """The Python mirrors of cc_options / cc_stats have the C sizes."""
+    import paper_1607_06156_amd as ccmi
+    # cc_options: 2 int32, 2 double, 8 int32
+    assert ctypes.sizeof(ccmi.Options) == 8 + 16 + 32
+    st = ccmi.Stats()
+    assert ctypes.sizeof(st) % 8 == 0
+    assert ccmi.Stats.active_edges.offset % 8 == 0
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    lib.cc_label.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                             ctypes.c_void_p]
+    lib.cc_last_error.restype = ctypes.c_char_p
+    assert lib.cc_label(None, None, -1, 5, None, None) == -1
+    assert b"negative" in lib.cc_last_error()
+    assert lib.cc_label(None, None, 3, 5, None, None) == -1        # NULL edges with m > 0
+    assert lib.cc_label(None, None, 3, 0, None, None) == -1        # edges but no vertices
+    assert lib.cc_label(None, None, 0, 0, None, None) == 0         # nothing to do
+    lib.cc_label_batched.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.cc_label_batched(None, None, None, None, -2, None, None) == -1
+    assert lib.cc_label_batched(None, None, None, None, 0, None, None) == 0
+    lib.cc_powerlaw_ks.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    assert lib.cc_powerlaw_ks(None, None, 0, None) == -1
+    lib.cc_router_load.argtypes = [ctypes.c_char_p]
+    assert lib.cc_router_load(b"/nonexistent/weights.txt") == -1
+
+
+def test_router_weights_file_roundtrip(lib, tmp_path):
+    import paper_1607_06156_amd as ccmi
+    w = np.arange(ccmi.ROUTER_NPARAMS, dtype=np.float32) * 1e-3
+    p = tmp_path / "w.txt"
+    p.write_text("# test weights\n" + "\n".join(f"{x:.9g}" for x in w) + "\n")
+    lib.cc_router_load.argtypes = [ctypes.c_char_p]
+    assert lib.cc_router_load(str(p).encode()) == 0
+    assert lib.cc_router_loaded() == 1
+    bad = tmp_path / "bad.txt"
+    bad.write_text("1 2 3\n")
+    assert lib.cc_router_load(str(bad).encode()) == -1
+    lib.cc_router_set.argtypes = [ctypes.c_void_p]
+    assert lib.cc_router_set(None) == 0 and lib.cc_router_loaded() == 0
+
+
+def test_binding_fails_loudly_without_device_tensors():
+    import torch
+    import paper_1607_06156_amd as ccmi
+    u = torch.zeros(3, dtype=torch.int32)
+    with pytest.raises((ValueError, RuntimeError, AssertionError)):
+        ccmi.label(u, u, 4, out=torch.empty(4, dtype=torch.int32))

@@ -1,0 +1,107 @@
+"""GPU parity of batched mode (one persistent launch for many graphs) against
+the oracle run graph by graph, bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+ccmi = pytest.importorskip("paper_1607_06156_amd")
+
+
+def run_batch(b, **kw):
+    say(f"[gpu] batched G={b.G} m={int(b.edge_off[-1])} n={int(b.vert_off[-1])} {kw}")
+    return ccmi.label_batched(torch.from_numpy(np.ascontiguousarray(b.u)).cuda(),
+                              torch.from_numpy(np.ascontiguousarray(b.v)).cuda(),
+                              torch.from_numpy(b.edge_off).cuda(), torch.from_numpy(b.vert_off).cuda(), **kw)
+
+
+def expected(b):
+    parts = []
+    for g in range(b.G):
+        sub = b.graph(g)
+        parts.append(oracle.labels_uf(sub.u, sub.v, sub.n))
+    return np.concatenate(parts) if parts else np.zeros(0, np.int32)
+
+
+def test_batch_small_families():
+    b = gen.batch(64, 5_000_000, lg_hi=14.0)
+    lab, st = run_batch(b, stats=True)
+    say(f"   passes={st['passes']} blocks={st['blocks']} tile={st['tile_edges']} ms={st['ms_total']:.3f}")
+    assert np.array_equal(lab.cpu().numpy(), expected(b))
+
+
+def test_batch_uneven_sizes():
+    b = gen.batch(300, 7_000_000, lg_lo=4.0, lg_hi=17.0)
+    lab = run_batch(b)
+    assert np.array_equal(lab.cpu().numpy(), expected(b))
+
+
+@pytest.mark.parametrize("tile", [1, 100, 4096, 1 << 20])
+def test_explicit_tiles_agree(tile):
+    b = gen.batch(40, 9_000_000, lg_hi=13.0)
+    lab = run_batch(b, tile_edges=tile)
+    assert np.array_equal(lab.cpu().numpy(), expected(b))
+
+
+def _manual(graphs):
+    us, vs, eo, vo = [], [], [0], [0]
+    for u, v, n in graphs:
+        us.append(np.asarray(u, np.int32))
+        vs.append(np.asarray(v, np.int32))
+        eo.append(eo[-1] + len(u))
+        vo.append(vo[-1] + n)
+    b = gen.Batch(np.concatenate(us) if us else np.zeros(0, np.int32),
+                  np.concatenate(vs) if vs else np.zeros(0, np.int32),
+                  np.array(eo, np.int64), np.array(vo, np.int64), np.zeros(len(graphs), np.int32))
+    return b
+
+
+def test_edge_cases():
+    big = gen.rmat(16, 8, seed=3)
+    graphs = [([], [], 0), ([], [], 1), ([0], [0], 1), ([], [], 5), ([1, 3], [2, 4], 5),
+              (big.u, big.v, big.n), ([0, 1], [1, 0], 2), ([], [], 0)]
+    b = _manual(graphs)
+    assert np.array_equal(run_batch(b).cpu().numpy(), expected(b))
+    # a single graph
+    b1 = _manual([(big.u, big.v, big.n)])
+    assert np.array_equal(run_batch(b1).cpu().numpy(), oracle.labels_uf(big.u, big.v, big.n))
+    # only edgeless graphs
+    b2 = _manual([([], [], 3), ([], [], 4)])
+    assert np.array_equal(run_batch(b2).cpu().numpy(), np.array([0, 1, 2, 0, 1, 2, 3], np.int32))
+
+
+def test_errors():
+    b = _manual([([0, 1], [1, 2], 3), ([0], [3], 3)])      # local id 3 in a 3-vertex graph
+    with pytest.raises(ccmi.CCError) as ei:
+        run_batch(b)
+    assert ei.value.code == ccmi.CC_ERANGE
+    b = _manual([([0], [1], 2), ([0], [1], 2)])
+    b.edge_off[:] = [0, 2, 1]                               # not non-decreasing... and edge_off[G] = 1
+    with pytest.raises(ccmi.CCError) as ei:
+        run_batch(b)
+    assert ei.value.code == ccmi.CC_EINVAL
+    b = _manual([([0], [1], 2)])
+    b.vert_off[:] = [1, 3]
+    with pytest.raises(ccmi.CCError) as ei:
+        run_batch(b)
+    assert ei.value.code == ccmi.CC_EINVAL
+
+
+def test_repeatable_and_matches_single_calls():
+    b = gen.batch(24, 11_000_000, lg_hi=15.0)
+    first = run_batch(b)
+    for _ in range(5):
+        assert torch.equal(run_batch(b), first)
+    # same labels as per-graph cc_label calls
+    for g in range(b.G):
+        sub = b.graph(g)
+        if sub.n == 0:
+            continue
+        lab = ccmi.label(torch.from_numpy(np.ascontiguousarray(sub.u)).cuda(),
+                         torch.from_numpy(np.ascontiguousarray(sub.v)).cuda(), sub.n, route="sv")
+        a, c = int(b.vert_off[g]), int(b.vert_off[g + 1])
+        assert torch.equal(lab, first[a:c])
