@@ -57,9 +57,9 @@ extern "C" {
 #define CC_ROUTE_AUTO 0       /* router if weights are loaded, else the degree heuristic */
 #define CC_ROUTE_HEURISTIC 1  /* Algorithm 2: K-S statistic < tau -> BFS + SV, else SV */
 #define CC_ROUTE_ROUTER 2     /* argmax of the MLP router's three logits */
-#define CC_ROUTE_SV 3         /* force R1: plain SV, compaction after every pass */
+#define CC_ROUTE_SV 3         /* force R1: plain SV, one hook attempt per edge per pass */
 #define CC_ROUTE_BFS_SV 4     /* force R0: BFS from the max-degree vertex, then SV on the rest */
-#define CC_ROUTE_SV_THETA 5   /* force R2: SV with threshold-gated compaction */
+#define CC_ROUTE_SV_THETA 5   /* force R2: SV with up to theta hook attempts per edge per pass */
 
 /* route ids reported in cc_stats.route and used as router classes */
 #define CC_R0_BFS_SV 0
@@ -70,7 +70,8 @@ typedef struct cc_options {
     int32_t route;       /* CC_ROUTE_* */
     int32_t max_passes;  /* 0: no cap; else CC_EINTERNAL once this many SV passes ran without converging */
     double tau;          /* K-S threshold; <= 0 selects 0.05 (Section V, Table "tab:ks_stat") */
-    double theta;        /* R2: compact after a pass only if >= theta of its edges were finished; <= 0 selects 0.25 */
+    double theta;        /* R2: hook attempts per edge per pass (an edge whose hook finds the root already
+                            linked follows the link and retries); < 1 selects 8 */
     int32_t profile;     /* 1: time every kernel launch with HIP events (cc_stats.kernel_*) */
     int32_t reserved[7]; /* must be zero */
 } cc_options;
@@ -116,7 +117,7 @@ typedef struct cc_stats {
     double kernel_bytes[8];       /* algorithmic bytes per kernel class (profile = 1 only) */
 } cc_stats;
 
-/* Fills *opt with the defaults (route AUTO, no cap, tau 0.05, theta 0.25). */
+/* Fills *opt with the defaults (route AUTO, no cap, tau 0.05, theta 8). */
 void cc_default_options(cc_options* opt);
 
 int cc_version(void);
@@ -151,18 +152,22 @@ int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_
 int cc_label_batched(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
                      int32_t G, int32_t* labels, void* stream);
 
-/* Batched statistics: passes of the persistent loop and tile size used. */
+/* Batched statistics: passes of the persistent loop and the launch shape used. */
 typedef struct cc_batch_stats {
-    int32_t passes;
-    int32_t tile_edges;
-    int32_t blocks;
-    int32_t reserved0;
+    int32_t passes;      /* SV passes of the persistent loop */
+    int32_t tile_edges;  /* edges per workgroup segment */
+    int32_t blocks;      /* workgroups of the persistent grid */
+    int32_t max_link;    /* hook attempts per edge per pass */
     int64_t total_edges;
     int64_t total_vertices;
-    double ms_total;
+    double ms_total;     /* device time of the launch */
+    float pass_ms[32];   /* device time of pass i (the entry after the last pass: final labels) */
 } cc_batch_stats;
 
-/* cc_label_batched with a tile size (0 = autotuned/default) and statistics (may be NULL). */
+/* cc_label_batched with a segment size (tile_edges > 0: that many edges per
+ * workgroup, one hook attempt per edge and pass; 0: autotuned grid size and
+ * hook attempts, timed on the first call of each size class) and statistics
+ * (may be NULL). */
 int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
                         int32_t G, int32_t* labels, void* stream, int32_t tile_edges, cc_batch_stats* stats);
 

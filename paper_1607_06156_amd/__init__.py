@@ -75,8 +75,8 @@ class Stats(ctypes.Structure):
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("tile_edges", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("total_edges", ctypes.c_int64),
-                ("total_vertices", ctypes.c_int64), ("ms_total", ctypes.c_double)]
+                ("max_link", ctypes.c_int32), ("total_edges", ctypes.c_int64),
+                ("total_vertices", ctypes.c_int64), ("ms_total", ctypes.c_double), ("pass_ms", ctypes.c_float * 32)]
 
 
 _lib = None
@@ -154,7 +154,7 @@ def version() -> int:
 
 
 def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tensor | None = None,
-          stats: bool = False, max_passes: int = 0, tau: float = 0.05, theta: float = 0.25,
+          stats: bool = False, max_passes: int = 0, tau: float = 0.05, theta: float = 8.0,
           profile: bool = False):
     """labels[x] = min vertex id of x's component; (u[i], v[i]) are undirected edges."""
     m = int(u.numel())
@@ -190,7 +190,9 @@ def label_batched(u, v, edge_off, vert_off, out=None, tile_edges: int = 0, stats
                                    ctypes.byref(st) if stats else None)
     _check(rc)
     if stats:
-        return out, {k: getattr(st, k) for k, _ in BatchStats._fields_ if not k.startswith("reserved")}
+        d = {k: getattr(st, k) for k, _ in BatchStats._fields_ if k != "pass_ms"}
+        d["pass_ms"] = [round(float(x), 4) for x in st.pass_ms][: st.passes + 1]
+        return out, d
     return out
 
 

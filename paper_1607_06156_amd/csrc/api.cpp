@@ -178,23 +178,25 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         in = SegList{bufs[0], cap, nseg, cnt[0]};
     }
     int64_t m_in = in0.soa ? m0 : in0.m;
-    bool compact_next = (policy == CC_R1_SV);
+    // R1: one hook attempt per edge per pass (the paper's one join per
+    // iteration); R2: up to theta attempts, following the links it meets
+    const int max_link = policy == CC_R2_SV_THETA ? (int)std::min(theta, 1e9) : 1;
     int pass = 0;
     while (m_in > 0) {
         if (max_passes > 0 && pass >= max_passes)
             return fail(CC_EINTERNAL, "SV did not converge within %d passes", max_passes);
-        const bool write = (policy == CC_R1_SV) || compact_next;
+        const bool write = true;
         const int out_buf = in_soa ? 0 : 1 - in_buf;
         // out counts: any array other than the input's and the hooks'
         int out_cnt = (in_cnt + 1) % 3;
         SegList out{bufs[out_buf], cap, nseg, cnt[out_cnt]};
         int k0 = c.kbeg();
         if (in_soa)
-            e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, write ? 1 : 0, (int32_t*)phook,
+            e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, write ? 1 : 0, max_link, (int32_t*)phook,
                                    hooked_count, totals, c.stream);
         else
-            e = launch_sv_pass_seg(in, c.parent, out, write ? 1 : 0, (int32_t*)phook, hooked_count, totals,
-                                   c.stream);
+            e = launch_sv_pass_seg(in, c.parent, out, write ? 1 : 0, max_link, (int32_t*)phook, hooked_count,
+                                   totals, c.stream);
         if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
         int rec_pass = c.kend(CC_K_SV_PASS, k0, 0.0);
         int k1 = c.kbeg();
@@ -222,19 +224,11 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         }
         ++pass;
         if (kept == 0) break;
-        if (write) {
-            in = out;
-            in_soa = false;
-            in_buf = out_buf;
-            in_cnt = out_cnt;
-            m_in = kept;
-            compact_next = (policy == CC_R1_SV);
-        } else {
-            // R2: the list is re-read as is; compact once enough of it is finished,
-            // or after a pass with no hook (then every edge is finished)
-            const double finished = 1.0 - (double)kept / (double)m_in;
-            compact_next = (finished >= theta) || hooks == 0;
-        }
+        in = out;
+        in_soa = false;
+        in_buf = out_buf;
+        in_cnt = out_cnt;
+        m_in = kept;
     }
     int k2 = c.kbeg();
     e = launch_sv_finalize(c.parent, c.n, c.stream);
@@ -255,7 +249,7 @@ CC_API void cc_default_options(cc_options* opt) {
     opt->route = CC_ROUTE_AUTO;
     opt->max_passes = 0;
     opt->tau = 0.05;
-    opt->theta = 0.25;
+    opt->theta = 8.0;
 }
 
 CC_API int cc_version(void) { return CC_VERSION; }
@@ -278,7 +272,7 @@ CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
     cc_options opt;
     if (opt_in) opt = *opt_in; else cc_default_options(&opt);
     if (opt.tau <= 0) opt.tau = 0.05;
-    if (opt.theta <= 0) opt.theta = 0.25;
+    if (opt.theta < 1) opt.theta = 8.0;
     if (m < 0 || n < 0) return fail(CC_EINVAL, "negative size (m=%lld, n=%d)", (long long)m, n);
     if (m > 0 && n == 0) return fail(CC_EINVAL, "edges given for an empty vertex set");
     if (m > 0 && (!u || !v)) return fail(CC_EINVAL, "NULL edge array");

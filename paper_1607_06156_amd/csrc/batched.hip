@@ -39,9 +39,16 @@ struct BatchArgs {
     unsigned int* bar;    // [0] arrivals, [1] generation
     unsigned long long* status;  // [0] error bits, [1] passes, [2] range errors
     int32_t max_passes;
+    int32_t max_link;     // hook attempts per edge per pass (see sv_segment)
 };
 
 enum : unsigned long long { kErrRange = 1, kErrOffsets = 2, kErrBarrier = 4, kErrPasses = 8 };
+constexpr int kStampBase = 8;    // status[8 + i]: wall clock when barrier i was passed
+constexpr int kMaxStamps = 40;
+
+__device__ __forceinline__ void stamp(unsigned long long* status, int i) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && i < kMaxStamps) status[kStampBase + i] = wall_clock64();
+}
 
 __device__ __forceinline__ unsigned long long load_status(unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -103,6 +110,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     }
     grid_barrier(A.bar, A.status);
     if (load_status(A.status)) return;
+    stamp(A.status, 0);
 
     // ---- pass 0: the caller's concatenated SoA list, local -> global ids
     uint32_t kept_off = 0, hook_off = 0, bad = 0;
@@ -126,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
             *c = (int32_t)(v0 + y);
             return true;
         };
-        sv_segment(len, load, A.parent, A.buf0 + base, A.hooked + base, true, kept_off, hook_off, lds);
+        sv_segment(len, load, A.parent, A.buf0 + base, A.hooked + base, true, A.max_link, kept_off, hook_off, lds);
     }
     if (threadIdx.x == 0) {
         A.cnt0[b] = kept_off;
@@ -146,6 +154,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     for (;;) {
         grid_barrier(A.bar, A.status);
         if (load_status(A.status)) return;
+        stamp(A.status, pass);
         // pointer jumping of the roots this block hooked
         {
             const uint32_t hc = A.hcnt[b];
@@ -181,8 +190,8 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
             *c = e.y;
             return true;
         };
-        sv_segment(len, load, A.parent, out + (int64_t)b * A.cap, A.hooked + (int64_t)b * A.cap, true, kept_off,
-                   hook_off, lds);
+        sv_segment(len, load, A.parent, out + (int64_t)b * A.cap, A.hooked + (int64_t)b * A.cap, true, A.max_link,
+                   kept_off, hook_off, lds);
         if (threadIdx.x == 0) {
             cout[b] = kept_off;
             A.hcnt[b] = hook_off;
@@ -200,6 +209,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     }
     grid_barrier(A.bar, A.status);
     if (load_status(A.status)) return;
+    stamp(A.status, pass + 1);
     if (A.n > 0) {
         int64_t x = gtid;
         int32_t g = x < A.n ? graph_of(A.vert_off, A.G, x) : 0;
@@ -248,6 +258,7 @@ hipError_t launch_batched(const BatchArgsHost& h, int blocks, hipStream_t s) {
     A.bar = h.bar;
     A.status = h.status;
     A.max_passes = h.max_passes;
+    A.max_link = h.max_link;
     void* args[] = {&A};
     return hipLaunchCooperativeKernel((const void*)batched_kernel, dim3(blocks), dim3(kBlock), args, 0, s);
 }

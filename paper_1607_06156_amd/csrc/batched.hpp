@@ -25,6 +25,7 @@ struct BatchArgsHost {
     unsigned int* bar;
     unsigned long long* status;
     int32_t max_passes;
+    int32_t max_link;
 };
 
 // largest co-resident grid of the persistent kernel on the current device

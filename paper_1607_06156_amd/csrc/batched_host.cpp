@@ -1,5 +1,5 @@
-// Host side of batched labelling: validation, workspace, the block-count
-// autotuner and the C ABI.
+// Host side of batched labelling: validation, workspace, the autotuner and
+// the C ABI.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,13 +18,21 @@
 
 namespace ccmi {
 
+constexpr size_t kBatchCtl = 1024;      // barrier words + status block
+constexpr int kStatusWords = 48;        // status[0..3) codes, status[8..48) pass stamps
+
 // ------------------------------------------------------------ autotuner
-// Chooses the persistent grid size (and so the edges per workgroup segment)
-// per size class by timing the candidates on the first call of that class.
-// Results live in memory and, if CC_AUTOTUNE_CACHE names a file, on disk
-// (one "key blocks" pair per line).
+// Chooses the persistent grid size (edges per workgroup segment) and the hook
+// attempts per edge and pass, per size class, by timing the candidates on the
+// first call of that class.  Every candidate computes the same labels.
+// Results live in memory and, if CC_AUTOTUNE_CACHE names a file, on disk (one
+// "key blocks link" triple per line).
+struct Tuned {
+    int blocks = 0;
+    int link = 1;
+};
 static std::mutex g_tune_mu;
-static std::map<std::string, int> g_tune;
+static std::map<std::string, Tuned> g_tune;
 static bool g_tune_loaded = false;
 
 static std::string tune_key(int dev, int64_t m, int32_t n, int32_t G) {
@@ -47,23 +55,23 @@ static void tune_load() {
     FILE* f = fopen(path, "r");
     if (!f) return;
     char key[256];
-    int b;
-    while (fscanf(f, "%255s %d", key, &b) == 2) g_tune[key] = b;
+    int b, l;
+    while (fscanf(f, "%255s %d %d", key, &b, &l) == 3) g_tune[key] = Tuned{b, l};
     fclose(f);
 }
 
-static void tune_store(const std::string& key, int blocks) {
-    g_tune[key] = blocks;
+static void tune_store(const std::string& key, Tuned t) {
+    g_tune[key] = t;
     const char* path = getenv("CC_AUTOTUNE_CACHE");
     if (!path) return;
     FILE* f = fopen(path, "w");
     if (!f) return;
-    for (auto& kv : g_tune) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    for (auto& kv : g_tune) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.blocks, kv.second.link);
     fclose(f);
 }
 
-static int run_once(Workspace& ws, BatchArgsHost h, int blocks, hipStream_t s, unsigned long long* status_host,
-                    double* ms) {
+static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStream_t s,
+                    unsigned long long* status_host, double* ms) {
     const int64_t cap = h.m > 0 ? (h.m + blocks - 1) / blocks : 1;
     const size_t slots = (size_t)blocks * (size_t)cap;
     void *p0, *p1, *ph, *pc, *pb;
@@ -72,7 +80,7 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, hipStream_t s, u
     if ((rc = ws.get(WS_EDGES1, slots * sizeof(int2), &p1))) return rc;
     if ((rc = ws.get(WS_HOOKED, slots * sizeof(int32_t), &ph))) return rc;
     if ((rc = ws.get(WS_SEGCOUNT, (size_t)blocks * 3 * sizeof(uint32_t), &pc))) return rc;
-    if ((rc = ws.get(WS_BATCH, 256, &pb))) return rc;
+    if ((rc = ws.get(WS_BATCH, kBatchCtl, &pb))) return rc;
     h.buf0 = (int2*)p0;
     h.buf1 = (int2*)p1;
     h.hooked = (int32_t*)ph;
@@ -82,17 +90,19 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, hipStream_t s, u
     h.hcnt = h.cnt1 + blocks;
     h.bar = (unsigned int*)pb;
     h.status = (unsigned long long*)((char*)pb + 64);
+    h.max_link = link;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ms) {
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
     }
-    hipError_t e = hipMemsetAsync(pb, 0, 256, s);
+    hipError_t e = hipMemsetAsync(pb, 0, kBatchCtl, s);
     if (e == hipSuccess && ms) e = hipEventRecord(e0, s);
     if (e == hipSuccess) e = launch_batched(h, blocks, s);
     if (e == hipSuccess && ms) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(status_host, h.status, 3 * sizeof(unsigned long long),
-                                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(status_host, h.status, kStatusWords * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && ms) {
         float t = 0;
@@ -158,49 +168,60 @@ CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t
     h.n = (int32_t)n;
     h.labels = labels;
     h.max_passes = 100000;
-    int blocks;
+    Tuned cfg;
     if (tile_edges > 0) {
         int64_t b = (m + tile_edges - 1) / tile_edges;
-        blocks = (int)std::max<int64_t>(1, std::min<int64_t>(b, maxb));
+        cfg.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(b, maxb));
+        cfg.link = 1;
     } else {
         std::string key = tune_key(ws->device, m, (int32_t)n, G);
-        int chosen = 0;
         {
             std::lock_guard<std::mutex> g(g_tune_mu);
             tune_load();
             auto it = g_tune.find(key);
-            if (it != g_tune.end()) chosen = std::min(it->second, maxb);
+            if (it != g_tune.end()) {
+                cfg = it->second;
+                cfg.blocks = std::min(cfg.blocks, maxb);
+            }
         }
-        if (chosen <= 0) {
-            // time each candidate grid on this input (every run computes the same labels)
+        if (cfg.blocks <= 0) {
             double best = 1e300;
-            const int cands[] = {256, 512, 1024, 2048, 4096};
-            for (int cb : cands) {
-                if (cb > maxb && cb != cands[0]) continue;
-                int b = std::min(cb, maxb);
-                double ms = 0;
-                if ((rc = run_once(*ws, h, b, s, host, &ms))) return rc;
-                if ((rc = status_code(host))) return rc;
-                if (ms < best) {
-                    best = ms;
-                    chosen = b;
+            const int bc[] = {256, 512, 1024};
+            const int lc[] = {1, 4};
+            for (int cb : bc) {
+                const int b = std::min(cb, maxb);
+                if (cb != bc[0] && cb > maxb) continue;
+                for (int l : lc) {
+                    double ms = 0;
+                    if ((rc = run_once(*ws, h, b, l, s, host, &ms))) return rc;
+                    if ((rc = status_code(host))) return rc;
+                    if (ms < best) {
+                        best = ms;
+                        cfg = Tuned{b, l};
+                    }
                 }
             }
             std::lock_guard<std::mutex> g(g_tune_mu);
-            tune_store(key, chosen);
+            tune_store(key, cfg);
         }
-        blocks = chosen;
     }
     double ms = 0;
-    if ((rc = run_once(*ws, h, blocks, s, host, stats ? &ms : nullptr))) return rc;
+    if ((rc = run_once(*ws, h, cfg.blocks, cfg.link, s, host, stats ? &ms : nullptr))) return rc;
     if ((rc = status_code(host))) return rc;
     if (stats) {
-        stats->passes = (int32_t)host[1];
-        stats->blocks = blocks;
-        stats->tile_edges = (int32_t)std::min<int64_t>(INT32_MAX, m > 0 ? (m + blocks - 1) / blocks : 0);
+        const int passes = (int)host[1];
+        stats->passes = passes;
+        stats->blocks = cfg.blocks;
+        stats->max_link = cfg.link;
+        stats->tile_edges = (int32_t)std::min<int64_t>(INT32_MAX, m > 0 ? (m + cfg.blocks - 1) / cfg.blocks : 0);
         stats->total_edges = m;
         stats->total_vertices = n;
         stats->ms_total = ms;
+        // barrier stamps (100 MHz wall clock): pass i runs between stamps i and i+1
+        for (int i = 0; i < 32 && i + 1 < 40 && i < passes + 1; ++i) {
+            const unsigned long long a = host[8 + i], b = host[8 + i + 1];
+            stats->pass_ms[i] = (b > a) ? (float)((double)(b - a) * 1e-5) : 0.f;
+        }
     }
     return CC_OK;
 }

@@ -86,10 +86,10 @@ hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s);
 // hooked roots into hooked (segments of the same cap), per-block counts,
 // and accumulates totals[0] (kept), totals[1] (hooks), totals[2] (range errors).
 hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
-                              SegList out, int write_out, int32_t* hooked, uint32_t* hooked_count,
+                              SegList out, int write_out, int max_link, int32_t* hooked, uint32_t* hooked_count,
                               unsigned long long* totals, hipStream_t s);
 // later passes over a segmented list
-hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int32_t* hooked,
+hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int max_link, int32_t* hooked,
                               uint32_t* hooked_count, unsigned long long* totals, hipStream_t s);
 // pointer-jumps the hooked roots of each segment; block 0 also writes
 // totals[0] = sum(kept_count), totals[1] = sum(hooked_count)

@@ -143,6 +143,91 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(const int32_t* _
     }
 }
 
+// Same scatter with the tile's pairs first grouped by bucket in LDS, so each
+// bucket's pairs leave the block as one contiguous run per tile (for B up to
+// kStagedMaxB buckets).
+constexpr int kStageThreads = 1024;
+constexpr int kStageEdges = 3;                         // edges per thread per tile (LDS: 2 blocks/CU)
+constexpr int kStagePairs = kStageThreads * kStageEdges * 2;
+
+__global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
+    const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m, int32_t n, int64_t chunk, int32_t B,
+    const unsigned long long* __restrict__ offs, int2* __restrict__ pairs) {
+    __shared__ int2 stage[kStagePairs];
+    __shared__ uint32_t toff[kStagedMaxB + 1];
+    __shared__ uint32_t run[kStagedMaxB];
+    __shared__ uint32_t wsum[kStageThreads / 64];
+    const int t = threadIdx.x;
+    for (int k = t; k < B; k += kStageThreads) run[k] = 0;
+    const unsigned long long* row = offs + (int64_t)blockIdx.x * B;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    int64_t end = beg + chunk;
+    if (end > m) end = m;
+    for (int64_t t0 = beg; t0 < end; t0 += (int64_t)kStageThreads * kStageEdges) {
+        for (int k = t; k <= B; k += kStageThreads) toff[k] = 0;
+        __syncthreads();
+        int2 p[2 * kStageEdges];
+        uint32_t rank[2 * kStageEdges];
+        bool ok[2 * kStageEdges];
+#pragma unroll
+        for (int j = 0; j < kStageEdges; ++j) {
+            const int64_t i = t0 + t + (int64_t)j * kStageThreads;
+            bool val = false;
+            int32_t a = 0, c = 0;
+            if (i < end) {
+                a = u[i];
+                c = v[i];
+                val = (uint32_t)a < (uint32_t)n && (uint32_t)c < (uint32_t)n;
+            }
+            ok[2 * j] = ok[2 * j + 1] = val;
+            p[2 * j] = make_int2(a, c);
+            p[2 * j + 1] = make_int2(c, a);
+            if (val) {
+                rank[2 * j] = atomicAdd(&toff[a >> kShift], 1u);
+                rank[2 * j + 1] = atomicAdd(&toff[c >> kShift], 1u);
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the tile's bucket counts (B <= 2 * 1024 entries)
+        {
+            const uint32_t c0 = 2 * t < B ? toff[2 * t] : 0u;
+            const uint32_t c1 = 2 * t + 1 < B ? toff[2 * t + 1] : 0u;
+            const uint32_t s = c0 + c1;
+            uint32_t incl = s;
+            for (int o = 1; o < 64; o <<= 1) {
+                uint32_t y = __shfl_up(incl, o);
+                if (lane_id() >= o) incl += y;
+            }
+            if (lane_id() == 63) wsum[t >> 6] = incl;
+            __syncthreads();
+            if (t == 0) {
+                uint32_t acc = 0;
+                for (int w = 0; w < kStageThreads / 64; ++w) { uint32_t q = wsum[w]; wsum[w] = acc; acc += q; }
+                toff[B] = acc;
+            }
+            __syncthreads();
+            const uint32_t ex = wsum[t >> 6] + incl - s;
+            if (2 * t < B) toff[2 * t] = ex;
+            if (2 * t + 1 < B) toff[2 * t + 1] = ex + c0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 2 * kStageEdges; ++j)
+            if (ok[j]) stage[toff[p[j].x >> kShift] + rank[j]] = p[j];
+        __syncthreads();
+        // contiguous runs per bucket: staged slot i -> its bucket's next free slot
+        const uint32_t total = toff[B];
+        for (uint32_t i = t; i < total; i += kStageThreads) {
+            const int2 q = stage[i];
+            const int k = q.x >> kShift;
+            pairs[row[k] + run[k] + (i - toff[k])] = q;
+        }
+        __syncthreads();
+        for (int k = t; k < B; k += kStageThreads) run[k] += toff[k + 1] - toff[k];
+        __syncthreads();
+    }
+}
+
 // per-vertex histogram update shared by the bucket pass and the standalone kernel
 struct HistLds {
     uint32_t hx[kExactBins];
@@ -302,7 +387,10 @@ int bucket_plan(int32_t n, int64_t m, BucketPlan* p) {
     if (p->B > kMaxBuckets) return -1;
     int64_t nblk = (m + 65535) / 65536;   // ~64K edges per block chunk
     if (nblk < 1) nblk = 1;
-    if (nblk > 1024) nblk = 1024;
+    // the direct scatter (many buckets) keeps fewer blocks so the open output
+    // runs stay within L2 and get written back as whole lines
+    const int64_t maxblk = p->B > kStagedMaxB ? 256 : 1024;
+    if (nblk > maxblk) nblk = maxblk;
     p->nblk = (int32_t)nblk;
     p->chunk = (m + nblk - 1) / nblk;
     if (p->chunk < 1) p->chunk = 1;
@@ -326,7 +414,10 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
     bucket_totals_kernel<<<(p.B + kBlock - 1) / kBlock, kBlock, 0, s>>>(w.counts, p.nblk, p.B, w.tot);
     bucket_scan_kernel<<<1, 1024, 0, s>>>(w.tot, p.B, w.base);
     bucket_offsets_kernel<<<(p.B + kBlock - 1) / kBlock, kBlock, 0, s>>>(w.counts, p.nblk, p.B, w.base, w.offs);
-    bucket_scatter_kernel<<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.offs, w.pairs);
+    if (p.B <= kStagedMaxB)
+        bucket_scatter_staged_kernel<<<p.nblk, kStageThreads, 0, s>>>(u, v, m, n, p.chunk, p.B, w.offs, w.pairs);
+    else
+        bucket_scatter_kernel<<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.offs, w.pairs);
     bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.pairs, w.base, n, deg, 1, want_hist, hist64, histx, tail,
                                                   tail_cap, tail_count, argmax_key, want_csr, off, adj);
     return hipGetLastError();

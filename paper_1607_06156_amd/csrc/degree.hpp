@@ -10,6 +10,7 @@ constexpr int kBucketShift = 15;      // 32768 vertices per bucket (LDS counters
 constexpr int kMaxBuckets = 16384;    // n <= 2^29 for the bucketed degree pass
 constexpr int kExactBins = 4096;      // exact degree histogram below this
 constexpr int kBlockD = 1024;         // threads of the per-bucket kernel
+constexpr int kStagedMaxB = 2048;     // LDS-staged scatter up to this many buckets (n <= 2^26)
 
 struct BucketPlan {
     int32_t B;       // vertex buckets

@@ -44,7 +44,8 @@ __global__ __launch_bounds__(kBlock) void sv_init_kernel(int32_t* __restrict__ p
 template <bool SOA>
 __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restrict__ u, const int32_t* __restrict__ v,
                                                          int64_t m, int32_t n, SegList in, int32_t* parent,
-                                                         SegList out, int write_out, int32_t* __restrict__ hooked,
+                                                         SegList out, int write_out, int max_link,
+                                                         int32_t* __restrict__ hooked,
                                                          uint32_t* __restrict__ hooked_count,
                                                          unsigned long long* __restrict__ totals) {
     __shared__ uint32_t lds[kWaves + 1];
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
             }
             return true;
         };
-        sv_segment(len, load, parent, dst, hdst, write_out != 0, kept_off, hook_off, lds);
+        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, lds);
     } else {
         const int2* src = in.buf + (int64_t)b * in.cap;
         const int64_t len = in.count[b];
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
             *c = e.y;
             return true;
         };
-        sv_segment(len, load, parent, dst, hdst, write_out != 0, kept_off, hook_off, lds);
+        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, lds);
     }
     // per-block results (no global atomics on the fast path)
     if (threadIdx.x == 0) {
@@ -154,18 +155,18 @@ hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s) {
 }
 
 hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
-                              SegList out, int write_out, int32_t* hooked, uint32_t* hooked_count,
+                              SegList out, int write_out, int max_link, int32_t* hooked, uint32_t* hooked_count,
                               unsigned long long* totals, hipStream_t s) {
     SegList none{nullptr, 0, 0, nullptr};
-    sv_pass_kernel<true><<<out.nseg, kBlock, 0, s>>>(u, v, m, n, none, parent, out, write_out, hooked, hooked_count,
-                                                     totals);
+    sv_pass_kernel<true><<<out.nseg, kBlock, 0, s>>>(u, v, m, n, none, parent, out, write_out, max_link, hooked,
+                                                     hooked_count, totals);
     return hipGetLastError();
 }
 
-hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int32_t* hooked,
+hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int max_link, int32_t* hooked,
                               uint32_t* hooked_count, unsigned long long* totals, hipStream_t s) {
-    sv_pass_kernel<false><<<in.nseg, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, in, parent, out, write_out, hooked,
-                                                     hooked_count, totals);
+    sv_pass_kernel<false><<<in.nseg, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, in, parent, out, write_out, max_link,
+                                                     hooked, hooked_count, totals);
     return hipGetLastError();
 }
 

@@ -10,13 +10,23 @@ namespace ccmi {
 constexpr int kEPT = 4;   // edges per thread per tile
 
 // Process `len` edges of this block.  load(i, &a, &c) fetches edge i of the
-// segment as two vertex ids and returns false to skip it.  Survivors go to
-// dst[kept_off ...] (if write_out), roots hooked for the first time in this
-// pass to hdst[hook_off ...].  Offsets are block-uniform running counts.
+// segment as two vertex ids and returns false to skip it.
+//
+// Per edge: find both roots; if they differ, hook the larger root below the
+// smaller with atomicMin.  The edge is finished (dropped) when its roots
+// agree or when its hook lands on a root (the two trees are then one).  If
+// the atomic finds hi already linked to old != hi, the pair still to be
+// joined is (old, lo) -- hi ~ lo is now a link when old > lo, hi ~ old when
+// old < lo -- and up to max_link attempts are made in this pass; an edge not
+// finished by then is kept as that pair.  max_link = 1 is the plain SV pass
+// (one hook per edge per pass, the rest waits for the next pass).
+//
+// Survivors go to dst[kept_off ...] (if write_out), roots hooked in this pass
+// to hdst[hook_off ...].  Offsets are block-uniform running counts.
 template <class Load>
 __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* parent, int2* __restrict__ dst,
-                                           int32_t* __restrict__ hdst, bool write_out, uint32_t& kept_off,
-                                           uint32_t& hook_off, uint32_t* lds) {
+                                           int32_t* __restrict__ hdst, bool write_out, int max_link,
+                                           uint32_t& kept_off, uint32_t& hook_off, uint32_t* lds) {
     for (int64_t t0 = 0; t0 < len; t0 += kBlock * kEPT) {
         int32_t a[kEPT], c[kEPT], pa[kEPT], pc[kEPT];
         bool valid[kEPT];
@@ -35,24 +45,32 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
         }
         bool keep[kEPT], hk[kEPT];
         int2 e[kEPT];
+        int32_t hroot[kEPT];
 #pragma unroll
         for (int k = 0; k < kEPT; ++k) {
             keep[k] = false;
             hk[k] = false;
+            hroot[k] = 0;
             if (!valid[k]) continue;
-            const int32_t ra = pa[k] == a[k] ? a[k] : find_root(parent, pa[k]);
-            const int32_t rc = pc[k] == c[k] ? c[k] : find_root(parent, pc[k]);
-            if (ra == rc) continue;                       // finished: both ends share a root
-            const int32_t lo = ra < rc ? ra : rc;
-            const int32_t hi = ra < rc ? rc : ra;
-            const int32_t old = atomic_min_agent(&parent[hi], lo);   // hook the larger root
-            hk[k] = (old == hi);
-            keep[k] = true;
-            // If hi had already been linked to some lo < old < hi, the atomic replaced
-            // that link: carry the displaced connection (old, hi) instead (hi ~ lo is now
-            // a forest link).  Connectivity of forest + active edges is then preserved
-            // whatever parent[] values the finds read.
-            e[k] = (old != hi && old > lo) ? make_int2(old, hi) : make_int2(lo, hi);
+            int32_t ra = pa[k] == a[k] ? a[k] : find_root(parent, pa[k]);
+            int32_t rc = pc[k] == c[k] ? c[k] : find_root(parent, pc[k]);
+            for (int tries = 0; ra != rc;) {
+                const int32_t lo = ra < rc ? ra : rc;
+                const int32_t hi = ra < rc ? rc : ra;
+                const int32_t old = atomic_min_agent(&parent[hi], lo);   // hook the larger root
+                if (old == hi) {           // hi was a root: the two trees are joined
+                    hk[k] = true;
+                    hroot[k] = hi;
+                    break;
+                }
+                if (++tries >= max_link) {
+                    keep[k] = true;
+                    e[k] = old > lo ? make_int2(old, hi) : make_int2(lo, hi);
+                    break;
+                }
+                ra = find_root(parent, old);
+                rc = find_root(parent, lo);
+            }
         }
         // wave ballots -> slot prefixes; one block scan of packed (kept | hooks << 16)
         uint64_t km[kEPT], hm[kEPT];
@@ -73,7 +91,7 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
 #pragma unroll
         for (int k = 0; k < kEPT; ++k) {
             if (write_out && keep[k]) dst[koff + kpre[k]] = e[k];
-            if (hk[k]) hdst[hoff + hpre[k]] = e[k].y;
+            if (hk[k]) hdst[hoff + hpre[k]] = hroot[k];
         }
         kept_off += tot & 0xffffu;
         hook_off += tot >> 16;

@@ -43,7 +43,7 @@ def test_version_and_defaults(lib):
     import paper_1607_06156_amd as ccmi
     opt = ccmi.Options()
     lib.cc_default_options(ctypes.byref(opt))
-    assert opt.route == 0 and opt.max_passes == 0 and abs(opt.tau - 0.05) < 1e-15 and abs(opt.theta - 0.25) < 1e-15
+    assert opt.route == 0 and opt.max_passes == 0 and abs(opt.tau - 0.05) < 1e-15 and abs(opt.theta - 8.0) < 1e-15
 
 
 def test_struct_layouts_match_header(lib):
