@@ -61,7 +61,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "(labelling is a single-device job here); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -182,7 +182,7 @@ def bench_batched(args):
     value = m / sec
     st = sts[-1]
     log(f"[bench] batched: {sec * 1e3:.2f} ms/step {value / 1e9:.2f} G edges/s passes={st['passes']} "
-        f"blocks={st['blocks']}")
+        f"blocks={st['blocks']} max_link={st['max_link']} pass_ms={st['pass_ms']}")
     kernel_ms = float(np.mean([s["ms_total"] for s in sts]))
     # per-graph launches of the same SV kernels
     loop = None
@@ -238,6 +238,8 @@ def bench_batched(args):
         "labels_exact_vs_oracle_sampled": exact,
         "kernel_ms": round(kernel_ms, 3),
         "passes": st["passes"],
+        "pass_ms": st["pass_ms"],
+        "max_link": st["max_link"],
         "per_graph_loop": loop,
         "cpu_baseline": cpu,
     }

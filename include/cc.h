@@ -164,12 +164,14 @@ typedef struct cc_batch_stats {
     float pass_ms[32];   /* device time of pass i (the entry after the last pass: final labels) */
 } cc_batch_stats;
 
-/* cc_label_batched with a segment size (tile_edges > 0: that many edges per
- * workgroup, one hook attempt per edge and pass; 0: autotuned grid size and
- * hook attempts, timed on the first call of each size class) and statistics
- * (may be NULL). */
+/* cc_label_batched with an explicit launch shape and statistics (may be NULL).
+ * tile_edges > 0: about that many edges per workgroup (the grid is rounded to
+ * a multiple of 8 and capped at the co-resident maximum); max_link > 0: hook
+ * attempts per edge and pass (1 = plain SV).  A zero in either selects the
+ * autotuned value, timed on the first call of each size class. */
 int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
-                        int32_t G, int32_t* labels, void* stream, int32_t tile_edges, cc_batch_stats* stats);
+                        int32_t G, int32_t* labels, void* stream, int32_t tile_edges, int32_t max_link,
+                        cc_batch_stats* stats);
 
 /* ------------------------------------------------------------------ router */
 /* Number of float32 parameters of the 66 -> 64 -> 64 -> 3 MLP: W1[64][66], b1[64],

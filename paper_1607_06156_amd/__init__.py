@@ -99,7 +99,7 @@ def lib():
                                            ctypes.POINTER(Options), ctypes.POINTER(Stats)]),
             "cc_label_batched": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP]),
             "cc_label_batched_ex": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
-                                                   ctypes.POINTER(BatchStats)]),
+                                                   ctypes.c_int32, ctypes.POINTER(BatchStats)]),
             "cc_router_load": (ctypes.c_int, [ctypes.c_char_p]),
             "cc_router_set": (ctypes.c_int, [_VP]),
             "cc_router_loaded": (ctypes.c_int, []),
@@ -177,8 +177,9 @@ def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tenso
     return (out, st.to_dict()) if stats else out
 
 
-def label_batched(u, v, edge_off, vert_off, out=None, tile_edges: int = 0, stats: bool = False):
-    """Graph-local labels of G graphs (see cc_label_batched)."""
+def label_batched(u, v, edge_off, vert_off, out=None, tile_edges: int = 0, max_link: int = 0,
+                  stats: bool = False):
+    """Graph-local labels of G graphs (see cc_label_batched); 0 = autotuned launch shape."""
     G = int(edge_off.numel()) - 1
     if out is None:
         total = int(vert_off[-1].item()) if G >= 0 else 0
@@ -186,7 +187,7 @@ def label_batched(u, v, edge_off, vert_off, out=None, tile_edges: int = 0, stats
     st = BatchStats()
     rc = lib().cc_label_batched_ex(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"),
                                    _dev(edge_off, torch.int64, "edge_off"), _dev(vert_off, torch.int64, "vert_off"),
-                                   G, _dev(out, torch.int32, "labels"), _stream(), tile_edges,
+                                   G, _dev(out, torch.int32, "labels"), _stream(), tile_edges, max_link,
                                    ctypes.byref(st) if stats else None)
     _check(rc)
     if stats:

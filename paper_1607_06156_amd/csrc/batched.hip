@@ -6,14 +6,16 @@
 // plus its minimum local id: the canonical labels of Fig. 1(b) survive, and
 // subtracting vert_off[g] at the end gives the graph-local labels.
 //
-// The whole SV iteration (Section III-A) runs inside one cooperative launch:
-// every workgroup owns a fixed chunk of the concatenated edge list and, pass
-// after pass, hooks and compacts its own segment, pointer-jumps the roots it
-// hooked, and waits at a grid barrier.  After the barrier every workgroup sums
-// the per-block survivor counts and takes the same stop decision, so
-// convergence is decided on the device and the host waits once.  Small graphs
-// finish in the first passes and simply drop out of the active segments
-// (Section III-A.4: completed work leaves the working set).
+// The whole SV iteration (Section III-A) runs inside one cooperative launch.
+// The concatenated edge list is cut into tiles of 1024 edges; every tile keeps
+// its own output segment (survivors of tile t go to slots [t*1024, ...)), so
+// no global atomic places output.  Pass after pass each workgroup hooks and
+// compacts its tiles, pointer-jumps the roots hooked in them, and waits at a
+// grid barrier.  After the barrier every workgroup sums the per-block survivor
+// partials and takes the same stop decision, so convergence is decided on the
+// device and the host waits once.  Small graphs finish in the first passes and
+// simply drop out of the active tiles (Section III-A.4: completed work leaves
+// the working set).
 #include "batched.hpp"
 #include "common.hpp"
 #include "sv_device.hpp"
@@ -29,18 +31,20 @@ struct BatchArgs {
     int64_t m;            // edge_off[G] (read by the host)
     int32_t n;            // vert_off[G]
     int32_t* parent;      // labels: global roots, then local labels
-    int2* buf0;
+    int2* buf0;           // tile segments, ping-pong
     int2* buf1;
-    int64_t cap;          // edges per block segment
-    uint32_t* cnt0;       // per-block survivor counts (ping-pong)
+    uint32_t* cnt0;       // per-tile survivor counts (ping-pong)
     uint32_t* cnt1;
-    uint32_t* hcnt;       // per-block hooked counts
-    int32_t* hooked;      // per-block hooked roots
+    uint32_t* hcnt;       // per-tile hooked counts
+    int32_t* hooked;      // per-tile hooked roots
     unsigned int* bar;    // [0] arrivals, [1] generation
     unsigned long long* status;  // [0] error bits, [1] passes, [2] range errors
     int32_t max_passes;
     int32_t max_link;     // hook attempts per edge per pass (see sv_segment)
+    unsigned long long* part;   // per-block survivor partials, 2 x gridDim
 };
+
+constexpr int64_t kTileE = (int64_t)kBlock * kEPT;   // edges (or vertices) per tile
 
 enum : unsigned long long { kErrRange = 1, kErrOffsets = 2, kErrBarrier = 4, kErrPasses = 8 };
 constexpr int kStampBase = 8;    // status[8 + i]: wall clock when barrier i was passed
@@ -93,13 +97,41 @@ __device__ __forceinline__ int32_t graph_of(const int64_t* off, int32_t G, int64
     return lo;
 }
 
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
+// XCDs (workgroup b runs on XCD b % 8).  The tiles are cut into 8 contiguous
+// ranges, one per XCD, and the workgroups of one XCD walk their range in
+// lock-step (tile j, j + nbx, ...), so the tiles an XCD processes at any
+// moment are neighbours: they belong to one or a few graphs, whose parent
+// ranges stay in that XCD's L2.
+struct TileWalk {
+    int64_t first, step, end;
+    __device__ TileWalk(int64_t T, int b, int nb) {
+        const int x = b & 7, j = b >> 3;
+        const int nbx = nb >> 3;
+        const int64_t Tx = (T + 7) / 8;
+        first = (int64_t)x * Tx + j;
+        step = nbx;
+        end = (int64_t)(x + 1) * Tx;
+        if (end > T) end = T;
+    }
+};
+
 __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     __shared__ uint32_t lds[kWaves + 1];
     __shared__ unsigned long long sh_total;
+    __shared__ int32_t sh_g;
     const int b = blockIdx.x;
     const int nb = gridDim.x;
     const int64_t gstride = (int64_t)nb * kBlock;
     const int64_t gtid = (int64_t)b * kBlock + threadIdx.x;
+    const int64_t T = (A.m + kTileE - 1) / kTileE;           // edge tiles
+    if (nb < 8 || (nb & 7)) {                                 // the tile walk needs 8 | grid
+        if (b == 0 && threadIdx.x == 0)
+            __hip_atomic_fetch_or(&A.status[0], (unsigned long long)kErrOffsets, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const TileWalk tw(T, b, nb);
 
     // ---- init: identity forest, offset checks
     for (int64_t x = gtid; x < A.n; x += gstride) A.parent[x] = (int32_t)x;
@@ -112,39 +144,93 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     if (load_status(A.status)) return;
     stamp(A.status, 0);
 
-    // ---- pass 0: the caller's concatenated SoA list, local -> global ids
-    uint32_t kept_off = 0, hook_off = 0, bad = 0;
-    {
-        const int64_t base = (int64_t)b * A.cap;
-        int64_t len = A.m - base;
-        if (len > A.cap) len = A.cap;
-        if (len < 0) len = 0;
-        int32_t g = len > 0 ? graph_of(A.edge_off, A.G, base + threadIdx.x < A.m ? base + threadIdx.x : base) : 0;
-        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
-            const int64_t e = base + i;
+    // ---- relabel: the caller's SoA list -> global (a, c) pairs in buf1, tile
+    // by tile, dropping (and counting) edges with an id outside their graph.
+    // Streaming only, so the graph lookup never sits in front of a gather.
+    uint32_t bad = 0;
+    for (int64_t t = tw.first; t < tw.end; t += tw.step) {
+        const int64_t e0 = t * kTileE;
+        int64_t len = A.m - e0;
+        if (len > kTileE) len = kTileE;
+        __syncthreads();   // every thread has read the previous tile's sh_g
+        if (threadIdx.x == 0) sh_g = graph_of(A.edge_off, A.G, e0);
+        __syncthreads();
+        int32_t g = sh_g;
+        int32_t x[kEPT], y[kEPT];
+        bool ok[kEPT];
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            const int64_t i = threadIdx.x + (int64_t)k * kBlock;
+            ok[k] = i < len;
+            if (ok[k]) {
+                x[k] = A.u[e0 + i];
+                y[k] = A.v[e0 + i];
+            }
+        }
+        int2 pr[kEPT];
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            if (!ok[k]) continue;
+            const int64_t e = e0 + threadIdx.x + (int64_t)k * kBlock;
             while (A.edge_off[g + 1] <= e) ++g;
             const int64_t v0 = A.vert_off[g];
             const int64_t nl = A.vert_off[g + 1] - v0;
-            const int32_t x = A.u[e], y = A.v[e];
-            if ((uint64_t)(uint32_t)x >= (uint64_t)nl || (uint64_t)(uint32_t)y >= (uint64_t)nl || x < 0 || y < 0) {
+            if (x[k] < 0 || y[k] < 0 || (int64_t)x[k] >= nl || (int64_t)y[k] >= nl) {
                 ++bad;
-                return false;
+                ok[k] = false;
+                continue;
             }
-            *a = (int32_t)(v0 + x);
-            *c = (int32_t)(v0 + y);
-            return true;
-        };
-        sv_segment(len, load, A.parent, A.buf0 + base, A.hooked + base, true, A.max_link, kept_off, hook_off, lds);
-    }
-    if (threadIdx.x == 0) {
-        A.cnt0[b] = kept_off;
-        A.hcnt[b] = hook_off;
+            pr[k] = make_int2((int32_t)(v0 + x[k]), (int32_t)(v0 + y[k]));
+        }
+        uint64_t mk[kEPT];
+        uint32_t pre[kEPT], wk = 0;
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            mk[k] = ballot(ok[k]);
+            pre[k] = wk + lanes_below(mk[k]);
+            wk += (uint32_t)__popcll(mk[k]);
+        }
+        uint32_t tot;
+        const uint32_t woff = block_wave_offset(wk, lds, &tot);
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k)
+            if (ok[k]) A.buf1[e0 + woff + pre[k]] = pr[k];
+        if (threadIdx.x == 0) A.cnt1[t] = tot;
     }
     for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o);
     if (lane_id() == 0 && bad) {
         __hip_atomic_fetch_add(&A.status[2], (unsigned long long)bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_or(&A.status[0], (unsigned long long)kErrRange, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+
+    // ---- pass 0 over the block's own relabelled tiles (no grid barrier needed:
+    // every tile was written by this block).  The block barrier publishes the
+    // per-tile counts thread 0 wrote, so every thread reads the same length.
+    __syncthreads();
+    unsigned long long block_kept = 0;
+    for (int64_t t = tw.first; t < tw.end; t += tw.step) {
+        const uint32_t len = A.cnt1[t];
+        uint32_t kept = 0, hk = 0;
+        if (len) {
+            const int2* src = A.buf1 + t * kTileE;
+            auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
+                const int2 e = src[i];
+                *a = e.x;
+                *c = e.y;
+                return true;
+            };
+            sv_segment((int64_t)len, load, A.parent, A.buf0 + t * kTileE, A.hooked + t * kTileE, true, A.max_link,
+                       kept, hk, lds);
+        }
+        if (threadIdx.x == 0) {
+            A.cnt0[t] = kept;
+            A.hcnt[t] = hk;
+        }
+        block_kept += kept;
+    }
+    unsigned long long* const part_base = A.part;
+    unsigned long long* part_rd = part_base;
+    if (threadIdx.x == 0) part_base[b] = block_kept;
 
     int pass = 1;
     int2* in = A.buf0;
@@ -155,18 +241,18 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
         grid_barrier(A.bar, A.status);
         if (load_status(A.status)) return;
         stamp(A.status, pass);
-        // pointer jumping of the roots this block hooked
-        {
-            const uint32_t hc = A.hcnt[b];
-            const int32_t* h = A.hooked + (int64_t)b * A.cap;
+        // pointer jumping of the roots hooked in this block's tiles
+        for (int64_t t = tw.first; t < tw.end; t += tw.step) {
+            const uint32_t hc = A.hcnt[t];
+            const int32_t* h = A.hooked + t * kTileE;
             for (uint32_t j = threadIdx.x; j < hc; j += kBlock) {
                 const int32_t x = h[j];
                 A.parent[x] = find_root(A.parent, x);
             }
         }
-        // every block sums the same counts and takes the same decision
+        // every block sums the same partials and takes the same decision
         unsigned long long s = 0;
-        for (int i = threadIdx.x; i < nb; i += kBlock) s += cin[i];
+        for (int i = threadIdx.x; i < nb; i += kBlock) s += part_rd[i];
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (threadIdx.x == 0) sh_total = 0;
         __syncthreads();
@@ -180,40 +266,59 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
                                       __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
-        kept_off = 0;
-        hook_off = 0;
-        const int2* src = in + (int64_t)b * A.cap;
-        const int64_t len = cin[b];
-        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
-            const int2 e = src[i];
-            *a = e.x;
-            *c = e.y;
-            return true;
-        };
-        sv_segment(len, load, A.parent, out + (int64_t)b * A.cap, A.hooked + (int64_t)b * A.cap, true, A.max_link,
-                   kept_off, hook_off, lds);
-        if (threadIdx.x == 0) {
-            cout[b] = kept_off;
-            A.hcnt[b] = hook_off;
+        // Partials alternate between two arrays: other blocks may still be
+        // summing the previous pass's array while this block writes, and an
+        // array is written again only after every block has passed the next
+        // barrier, i.e. finished summing it.
+        unsigned long long* part_out = part_base + (pass & 1) * nb;
+        block_kept = 0;
+        for (int64_t t = tw.first; t < tw.end; t += tw.step) {
+            const uint32_t len = cin[t];
+            uint32_t kept = 0, hk = 0;
+            if (len) {
+                const int2* src = in + t * kTileE;
+                auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
+                    const int2 e = src[i];
+                    *a = e.x;
+                    *c = e.y;
+                    return true;
+                };
+                sv_segment((int64_t)len, load, A.parent, out + t * kTileE, A.hooked + t * kTileE, true, A.max_link,
+                           kept, hk, lds);
+            }
+            if (threadIdx.x == 0) {
+                cout[t] = kept;
+                A.hcnt[t] = hk;
+            }
+            block_kept += kept;
         }
+        if (threadIdx.x == 0) part_out[b] = block_kept;
+        part_rd = part_out;
         ++pass;
-        int2* t = in; in = out; out = t;
+        int2* tt = in; in = out; out = tt;
         uint32_t* tc = cin; cin = cout; cout = tc;
     }
     if (b == 0 && threadIdx.x == 0) A.status[1] = (unsigned long long)pass;
 
     // ---- final labels: compress to roots, then shift to graph-local ids
-    for (int64_t x = gtid; x < A.n; x += gstride) {
-        const int32_t p = A.parent[x];
-        if (p != (int32_t)x) A.parent[x] = find_root(A.parent, p);
+    const int64_t TV = ((int64_t)A.n + kTileE - 1) / kTileE;   // vertex tiles
+    const TileWalk vw(TV, b, nb);
+    for (int64_t t = vw.first; t < vw.end; t += vw.step) {
+        for (int64_t x = t * kTileE + threadIdx.x; x < (t + 1) * kTileE && x < A.n; x += kBlock) {
+            const int32_t p = A.parent[x];
+            if (p != (int32_t)x) A.parent[x] = find_root(A.parent, p);
+        }
     }
     grid_barrier(A.bar, A.status);
     if (load_status(A.status)) return;
     stamp(A.status, pass + 1);
-    if (A.n > 0) {
-        int64_t x = gtid;
-        int32_t g = x < A.n ? graph_of(A.vert_off, A.G, x) : 0;
-        for (; x < A.n; x += gstride) {
+    for (int64_t t = vw.first; t < vw.end; t += vw.step) {
+        const int64_t x0 = t * kTileE;
+        __syncthreads();
+        if (threadIdx.x == 0) sh_g = graph_of(A.vert_off, A.G, x0);
+        __syncthreads();
+        int32_t g = sh_g;
+        for (int64_t x = x0 + threadIdx.x; x < x0 + kTileE && x < A.n; x += kBlock) {
             while (A.vert_off[g + 1] <= x) ++g;
             A.parent[x] = (int32_t)(A.parent[x] - A.vert_off[g]);
         }
@@ -250,7 +355,6 @@ hipError_t launch_batched(const BatchArgsHost& h, int blocks, hipStream_t s) {
     A.parent = h.labels;
     A.buf0 = h.buf0;
     A.buf1 = h.buf1;
-    A.cap = h.cap;
     A.cnt0 = h.cnt0;
     A.cnt1 = h.cnt1;
     A.hcnt = h.hcnt;
@@ -259,6 +363,7 @@ hipError_t launch_batched(const BatchArgsHost& h, int blocks, hipStream_t s) {
     A.status = h.status;
     A.max_passes = h.max_passes;
     A.max_link = h.max_link;
+    A.part = h.part;
     void* args[] = {&A};
     return hipLaunchCooperativeKernel((const void*)batched_kernel, dim3(blocks), dim3(kBlock), args, 0, s);
 }

@@ -17,7 +17,7 @@ struct BatchArgsHost {
     int32_t* labels;
     int2* buf0;
     int2* buf1;
-    int64_t cap;
+    unsigned long long* part;   // 2 x blocks survivor partials
     uint32_t* cnt0;
     uint32_t* cnt1;
     uint32_t* hcnt;
@@ -27,6 +27,8 @@ struct BatchArgsHost {
     int32_t max_passes;
     int32_t max_link;
 };
+
+constexpr int64_t kBatchTile = 1024;   // edges per tile (256 threads x 4)
 
 // largest co-resident grid of the persistent kernel on the current device
 hipError_t batched_max_blocks(int* blocks);

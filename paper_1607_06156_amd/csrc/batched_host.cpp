@@ -72,22 +72,23 @@ static void tune_store(const std::string& key, Tuned t) {
 
 static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStream_t s,
                     unsigned long long* status_host, double* ms) {
-    const int64_t cap = h.m > 0 ? (h.m + blocks - 1) / blocks : 1;
-    const size_t slots = (size_t)blocks * (size_t)cap;
+    const int64_t tiles = h.m > 0 ? (h.m + kBatchTile - 1) / kBatchTile : 1;
+    const size_t slots = (size_t)tiles * (size_t)kBatchTile;
     void *p0, *p1, *ph, *pc, *pb;
     int rc;
     if ((rc = ws.get(WS_EDGES0, slots * sizeof(int2), &p0))) return rc;
     if ((rc = ws.get(WS_EDGES1, slots * sizeof(int2), &p1))) return rc;
     if ((rc = ws.get(WS_HOOKED, slots * sizeof(int32_t), &ph))) return rc;
-    if ((rc = ws.get(WS_SEGCOUNT, (size_t)blocks * 3 * sizeof(uint32_t), &pc))) return rc;
+    const size_t cnt_bytes = ((size_t)tiles * 3 * sizeof(uint32_t) + 255) & ~(size_t)255;
+    if ((rc = ws.get(WS_SEGCOUNT, cnt_bytes + (size_t)blocks * 2 * sizeof(unsigned long long), &pc))) return rc;
     if ((rc = ws.get(WS_BATCH, kBatchCtl, &pb))) return rc;
     h.buf0 = (int2*)p0;
     h.buf1 = (int2*)p1;
     h.hooked = (int32_t*)ph;
-    h.cap = cap;
     h.cnt0 = (uint32_t*)pc;
-    h.cnt1 = h.cnt0 + blocks;
-    h.hcnt = h.cnt1 + blocks;
+    h.cnt1 = h.cnt0 + tiles;
+    h.hcnt = h.cnt1 + tiles;
+    h.part = (unsigned long long*)((char*)pc + cnt_bytes);
     h.bar = (unsigned int*)pb;
     h.status = (unsigned long long*)((char*)pb + 64);
     h.max_link = link;
@@ -128,10 +129,11 @@ static int status_code(const unsigned long long* st) {
 using namespace ccmi;
 
 CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
-                               int32_t G, int32_t* labels, void* stream, int32_t tile_edges, cc_batch_stats* stats) {
+                               int32_t G, int32_t* labels, void* stream, int32_t tile_edges, int32_t max_link,
+                               cc_batch_stats* stats) {
     if (stats) memset(stats, 0, sizeof *stats);
     if (G < 0) return fail(CC_EINVAL, "negative G");
-    if (tile_edges < 0) return fail(CC_EINVAL, "negative tile_edges");
+    if (tile_edges < 0 || max_link < 0) return fail(CC_EINVAL, "negative tile_edges / max_link");
     if (G == 0) return CC_OK;
     if (!edge_off || !vert_off) return fail(CC_EINVAL, "NULL offsets");
     Workspace* ws;
@@ -169,29 +171,38 @@ CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t
     h.labels = labels;
     h.max_passes = 100000;
     Tuned cfg;
+    maxb &= ~7;   // the tile walk gives each of the 8 XCDs the same number of workgroups
+    if (maxb < 8) return fail(CC_EINTERNAL, "persistent grid too small for this device");
+    std::vector<int> bcand, lcand;
     if (tile_edges > 0) {
         int64_t b = (m + tile_edges - 1) / tile_edges;
-        cfg.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(b, maxb));
-        cfg.link = 1;
+        b = std::max<int64_t>(8, std::min<int64_t>(b, maxb));
+        bcand.push_back((int)(b & ~(int64_t)7));
     } else {
+        for (int cb : {256, 512, 1024})
+            if (std::min(cb, maxb) != (bcand.empty() ? -1 : bcand.back())) bcand.push_back(std::min(cb, maxb));
+    }
+    if (max_link > 0) lcand.push_back(max_link);
+    else lcand = {1, 4};
+    if (bcand.size() == 1 && lcand.size() == 1) {
+        cfg = Tuned{bcand[0], lcand[0]};
+    } else {
+        const bool cacheable = tile_edges == 0 && max_link == 0;
         std::string key = tune_key(ws->device, m, (int32_t)n, G);
-        {
+        if (cacheable) {
             std::lock_guard<std::mutex> g(g_tune_mu);
             tune_load();
             auto it = g_tune.find(key);
             if (it != g_tune.end()) {
                 cfg = it->second;
-                cfg.blocks = std::min(cfg.blocks, maxb);
+                cfg.blocks = std::max(8, std::min(cfg.blocks, maxb) & ~7);
             }
         }
         if (cfg.blocks <= 0) {
+            // time every candidate on this input (each computes the same labels)
             double best = 1e300;
-            const int bc[] = {256, 512, 1024};
-            const int lc[] = {1, 4};
-            for (int cb : bc) {
-                const int b = std::min(cb, maxb);
-                if (cb != bc[0] && cb > maxb) continue;
-                for (int l : lc) {
+            for (int b : bcand)
+                for (int l : lcand) {
                     double ms = 0;
                     if ((rc = run_once(*ws, h, b, l, s, host, &ms))) return rc;
                     if ((rc = status_code(host))) return rc;
@@ -200,9 +211,10 @@ CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t
                         cfg = Tuned{b, l};
                     }
                 }
+            if (cacheable) {
+                std::lock_guard<std::mutex> g(g_tune_mu);
+                tune_store(key, cfg);
             }
-            std::lock_guard<std::mutex> g(g_tune_mu);
-            tune_store(key, cfg);
         }
     }
     double ms = 0;
@@ -228,5 +240,5 @@ CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t
 
 CC_API int cc_label_batched(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
                             int32_t G, int32_t* labels, void* stream) {
-    return cc_label_batched_ex(u, v, edge_off, vert_off, G, labels, stream, 0, nullptr);
+    return cc_label_batched_ex(u, v, edge_off, vert_off, G, labels, stream, 0, 0, nullptr);
 }
