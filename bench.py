@@ -19,6 +19,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "CC edges/s + achieved HBM GB/s; routed/batched vs plain SV, exact labels"
 WORKLOAD_DESC = {
     "rmat24": "R-MAT scale 24, edge factor 16 (a,b,c,d = .57,.19,.19,.05), ids permuted, duplicates and "
               "self-loops kept, seed 2",
@@ -131,7 +132,7 @@ def main():
         log(f"[bench] oracle {dt:.2f}s  {g.m / dt / 1e6:.1f} M edges/s; labels exact: {exact}")
 
     rec = {
-        "metric": "CC edges/s (exact labels) + achieved HBM GB/s; routed vs plain SV",
+        "metric": METRIC,
         "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
@@ -228,7 +229,7 @@ def bench_batched(args):
                "sample": f"{len(gs)} of {b.G} graphs (every 16th), {me} edges, one thread, {dt:.2f} s",
                "host_nproc": os.cpu_count()}
     rec = {
-        "metric": "CC edges/s (exact labels); batched vs per-graph launches",
+        "metric": METRIC,
         "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",

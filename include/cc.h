@@ -193,8 +193,8 @@ int cc_router_loaded(void);
 
 /* Degree (Section III-B, Degree_Distribution): deg[x] = number of edge endpoints
  * equal to x (each undirected edge counts for both ends, a self-loop twice).
- * deg: int32[n], written.  Requires n <= 2^29 (bucketed counting in LDS).
- * Returns CC_ERANGE if an id is outside [0, n). */
+ * deg: int32[n], written.  Requires n <= 2^29 (bucketed counting in LDS) and
+ * m < 2^31 (else CC_EINVAL).  Returns CC_ERANGE if an id is outside [0, n). */
 int cc_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* deg, void* stream);
 
 /* Degree histograms: hist64[64] (half-octave log bins: bin 0 = degree 0, degree
@@ -221,7 +221,8 @@ int cc_powerlaw_ks(const int64_t* histx, const int32_t* tail, int64_t ntail, dou
  * twice): off: int64[n+1] = exclusive scan of the degrees; adj: int32[2m]
  * neighbour lists, each vertex's entries in an unspecified order; deg:
  * optional int32[n] output of the degrees (NULL if not wanted).  Requires
- * n <= 2^29.  Returns CC_ERANGE if an id is outside [0, n). */
+ * n <= 2^29 and m < 2^31 (else CC_EINVAL).  Returns CC_ERANGE if an id is
+ * outside [0, n). */
 int cc_csr(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* deg, int64_t* off, int32_t* adj,
            void* stream);
 

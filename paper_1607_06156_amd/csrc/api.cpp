@@ -131,13 +131,29 @@ int choose_nseg(int64_t m) {
     return (int)s;
 }
 
+// Chunks of the first pass.  Within one pass the trees only grow (no
+// shortcut runs while hooks are in flight), so on graphs with many more edges
+// than vertices the finds of late edges walk long chains.  Cutting the first
+// pass into chunks with a full pointer-jumping shortcut after each keeps the
+// trees flat; the shortcut costs O(n), so the chunk count follows m / n.
+int pass0_chunks(int64_t m, int32_t n) {
+    if (n <= 0) return 1;
+    int64_t k = m / (2 * (int64_t)n);
+    if (k < 1) k = 1;
+    if (k > 8) k = 8;
+    return (int)k;
+}
+
 int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes) {
     Workspace& ws = *c.ws;
     const int64_t m0 = in0.soa ? in0.m : 0;
     int nseg;
     int64_t cap;
+    int chunks = 1, nseg_chunk = 0;
     if (in0.soa) {
-        nseg = choose_nseg(m0);
+        chunks = pass0_chunks(m0, c.n);
+        nseg_chunk = choose_nseg((m0 + chunks - 1) / chunks);
+        nseg = chunks * nseg_chunk;
         cap = (m0 + nseg - 1) / nseg;
         if (cap < 1) cap = 1;
     } else {
@@ -190,15 +206,34 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         // out counts: any array other than the input's and the hooks'
         int out_cnt = (in_cnt + 1) % 3;
         SegList out{bufs[out_buf], cap, nseg, cnt[out_cnt]};
-        int k0 = c.kbeg();
-        if (in_soa)
-            e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, write ? 1 : 0, max_link, (int32_t*)phook,
-                                   hooked_count, totals, c.stream);
-        else
+        int rec_pass = -1;
+        double flat_bytes = 0.0;
+        if (in_soa) {
+            for (int k = 0; k < chunks; ++k) {
+                if (k > 0) {
+                    int kf = c.kbeg();
+                    e = launch_sv_finalize(c.parent, c.n, c.stream);
+                    if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
+                    // parent read + one gather per vertex, at most one write
+                    c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n);
+                    flat_bytes += 12.0 * c.n;
+                }
+                int k0 = c.kbeg();
+                e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, k * nseg_chunk, nseg_chunk,
+                                       write ? 1 : 0, max_link, (int32_t*)phook, hooked_count, totals, c.stream);
+                if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
+                // this chunk's edges; the survivors' bytes go to the last chunk below
+                const int64_t e0 = std::min<int64_t>(m0, (int64_t)k * nseg_chunk * cap);
+                const int64_t e1 = std::min<int64_t>(m0, (int64_t)(k + 1) * nseg_chunk * cap);
+                rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)(e1 - e0));
+            }
+        } else {
+            int k0 = c.kbeg();
             e = launch_sv_pass_seg(in, c.parent, out, write ? 1 : 0, max_link, (int32_t*)phook, hooked_count,
                                    totals, c.stream);
-        if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
-        int rec_pass = c.kend(CC_K_SV_PASS, k0, 0.0);
+            if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
+            rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)m_in);
+        }
         int k1 = c.kbeg();
         e = launch_sv_shortcut(c.parent, (const int32_t*)phook, hooked_count, out.count, cap, nseg, totals,
                                c.stream);
@@ -218,8 +253,8 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             // edges read (8 B) + two 4 B gathers + one 8 B atomic per unfinished edge
             // + survivors written (8 B); shortcut: read, gather, write per hooked root
             const double pass_bytes = 16.0 * m_in + 8.0 * kept + (write ? 8.0 * kept : 0.0);
-            c.bytes += pass_bytes + 12.0 * hooks;
-            c.kbytes(rec_pass, pass_bytes);
+            c.bytes += pass_bytes + 12.0 * hooks + flat_bytes;
+            c.kadd(rec_pass, 8.0 * kept + (write ? 8.0 * kept : 0.0));
             c.kbytes(rec_sc, 12.0 * hooks);
         }
         ++pass;

@@ -81,13 +81,14 @@ struct SegList {
 
 // SV (sv.hip)
 hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s);
-// first pass over the caller's SoA edge list (dense, m edges); chunked into
-// nseg blocks of `cap` edges.  Writes survivors into out (if write_out),
-// hooked roots into hooked (segments of the same cap), per-block counts,
-// and accumulates totals[0] (kept), totals[1] (hooks), totals[2] (range errors).
+// first pass over the caller's SoA edge list (dense, m edges), cut into
+// out.nseg segments of out.cap edges; this launch covers segments
+// [seg0, seg0 + nblocks), one block each.  Writes survivors into out (if
+// write_out), hooked roots into hooked (segments of the same cap), per-segment
+// counts, and accumulates totals[2] (range errors).
 hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
-                              SegList out, int write_out, int max_link, int32_t* hooked, uint32_t* hooked_count,
-                              unsigned long long* totals, hipStream_t s);
+                              SegList out, int32_t seg0, int32_t nblocks, int write_out, int max_link,
+                              int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals, hipStream_t s);
 // later passes over a segmented list
 hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int max_link, int32_t* hooked,
                               uint32_t* hooked_count, unsigned long long* totals, hipStream_t s);
@@ -96,6 +97,7 @@ hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int writ
 hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count,
                               const uint32_t* kept_count, int64_t cap, int32_t nseg, unsigned long long* totals,
                               hipStream_t s);
+// parent[x] = root(x) for every x (no hook may run concurrently)
 hipError_t launch_sv_finalize(int32_t* parent, int32_t n, hipStream_t s);
 
 }  // namespace ccmi

@@ -9,8 +9,9 @@
 //      bucket (2^15 consecutive ids);
 //   B. a prefix over (bucket, block) gives every block a private output run per
 //      bucket;
-//   C. each block scatters (endpoint, other end) pairs into its runs (LDS
-//      cursors, coalesced runs);
+//   C. each block scatters its endpoints into its runs (LDS cursors,
+//      coalesced runs): the 16-bit id within the bucket, and the other end
+//      only when a CSR is wanted;
 //   D. one block per bucket counts the degrees of its 32768 vertices in LDS,
 //      writes deg[], folds the degree histograms (log bins, exact bins below
 //      4096, tail list, arg-max) and, when a CSR is wanted, turns the counts
@@ -39,6 +40,7 @@ __device__ __forceinline__ unsigned long long atomic_max_u64_agent(unsigned long
 }
 
 // ------------------------------------------------------------------ pass A
+// counts[k * nblk + b] = endpoints of block b's edge chunk in bucket k
 __global__ __launch_bounds__(kBlock) void bucket_count_kernel(const int32_t* __restrict__ u,
                                                               const int32_t* __restrict__ v, int64_t m, int32_t n,
                                                               int64_t chunk, int32_t B, uint32_t* __restrict__ counts,
@@ -60,20 +62,36 @@ __global__ __launch_bounds__(kBlock) void bucket_count_kernel(const int32_t* __r
         atomicAdd(&h[c >> kShift], 1u);
     }
     __syncthreads();
-    uint32_t* row = counts + (int64_t)blockIdx.x * B;
-    for (int k = threadIdx.x; k < B; k += kBlock) row[k] = h[k];
+    const int nblk = gridDim.x;
+    for (int k = threadIdx.x; k < B; k += kBlock) counts[(int64_t)k * nblk + blockIdx.x] = h[k];
     for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off);
     if (lane_id() == 0 && bad) atomic_add_agent(err, bad);
 }
 
-// column totals: tot[k] = sum_b counts[b][k]
-__global__ __launch_bounds__(kBlock) void bucket_totals_kernel(const uint32_t* __restrict__ counts, int32_t nblk,
-                                                               int32_t B, unsigned long long* __restrict__ tot) {
-    int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= B) return;
-    unsigned long long s = 0;
-    for (int b = 0; b < nblk; ++b) s += counts[(int64_t)b * B + k];
-    tot[k] = s;
+// one block per bucket k: counts[k][.] -> exclusive prefix over the blocks
+// (in place), tot[k] = bucket total.  nblk <= kScanThreads.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void bucket_colscan_kernel(uint32_t* __restrict__ counts, int32_t nblk,
+                                                                      unsigned long long* __restrict__ tot) {
+    __shared__ uint32_t wsum[kScanThreads / 64 + 1];
+    const int k = blockIdx.x, t = threadIdx.x;
+    uint32_t* col = counts + (int64_t)k * nblk;
+    const uint32_t c = t < nblk ? col[t] : 0u;
+    uint32_t incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o);
+        if (lane_id() >= o) incl += y;
+    }
+    if (lane_id() == 63) wsum[t >> 6] = incl;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) { uint32_t q = wsum[w]; wsum[w] = acc; acc += q; }
+        wsum[kScanThreads / 64] = acc;
+    }
+    __syncthreads();
+    if (t < nblk) col[t] = wsum[t >> 6] + incl - c;
+    if (t == 0) tot[k] = wsum[kScanThreads / 64];
 }
 
 // single block: base[k] = exclusive prefix of tot, base[B] = total
@@ -107,25 +125,28 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const unsigned long l
     if (t == 1023) base[B] = part[1023];
 }
 
-// offs[b][k] = base[k] + sum_{b' < b} counts[b'][k]
+// offs[b][k] = base[k] + prefix[k][b]: block b's first output slot in bucket k
+// (only the direct scatter, which has no room to keep these in LDS)
 __global__ __launch_bounds__(kBlock) void bucket_offsets_kernel(const uint32_t* __restrict__ counts, int32_t nblk,
                                                                 int32_t B, const unsigned long long* __restrict__ base,
                                                                 unsigned long long* __restrict__ offs) {
-    int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= B) return;
-    unsigned long long run = base[k];
-    for (int b = 0; b < nblk; ++b) {
-        offs[(int64_t)b * B + k] = run;
-        run += counts[(int64_t)b * B + k];
-    }
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // i = b * B + k
+    if (i >= (int64_t)nblk * B) return;
+    const int b = (int)(i / B), k = (int)(i - (int64_t)b * B);
+    offs[i] = base[k] + counts[(int64_t)k * nblk + b];
 }
 
 // ------------------------------------------------------------------ pass C
+// Bucketed output is structure-of-arrays: loc[i] = endpoint - bucket start
+// (16 bits, all the degree count needs), other[i] = the other endpoint
+// (written only when a CSR is built).
+template <bool OTHER>
 __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(const int32_t* __restrict__ u,
                                                                 const int32_t* __restrict__ v, int64_t m, int32_t n,
                                                                 int64_t chunk, int32_t B,
                                                                 const unsigned long long* __restrict__ offs,
-                                                                int2* __restrict__ pairs) {
+                                                                uint16_t* __restrict__ loc,
+                                                                int32_t* __restrict__ other) {
     extern __shared__ uint32_t cur[];
     for (int k = threadIdx.x; k < B; k += kBlock) cur[k] = 0;
     __syncthreads();
@@ -136,41 +157,51 @@ __global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(const int32_t* _
     for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
         int32_t a = u[i], c = v[i];
         if ((uint32_t)a >= (uint32_t)n || (uint32_t)c >= (uint32_t)n) continue;
-        uint32_t pa = atomicAdd(&cur[a >> kShift], 1u);
-        pairs[row[a >> kShift] + pa] = make_int2(a, c);
-        uint32_t pc = atomicAdd(&cur[c >> kShift], 1u);
-        pairs[row[c >> kShift] + pc] = make_int2(c, a);
+        const unsigned long long pa = row[a >> kShift] + atomicAdd(&cur[a >> kShift], 1u);
+        loc[pa] = (uint16_t)(a & (kBsz - 1));
+        if (OTHER) other[pa] = c;
+        const unsigned long long pc = row[c >> kShift] + atomicAdd(&cur[c >> kShift], 1u);
+        loc[pc] = (uint16_t)(c & (kBsz - 1));
+        if (OTHER) other[pc] = a;
     }
 }
 
-// Same scatter with the tile's pairs first grouped by bucket in LDS, so each
-// bucket's pairs leave the block as one contiguous run per tile (for B up to
-// kStagedMaxB buckets).
+// Same scatter with each tile's entries first grouped by bucket in LDS, so a
+// bucket's entries leave the block as one contiguous run per tile (for B up
+// to kStagedMaxB buckets).  A staged entry packs (bucket << 16 | local id).
 constexpr int kStageThreads = 1024;
-constexpr int kStageEdges = 3;                         // edges per thread per tile (LDS: 2 blocks/CU)
-constexpr int kStagePairs = kStageThreads * kStageEdges * 2;
+template <bool OTHER>
+struct StageCfg {
+    static constexpr int kEdges = OTHER ? 3 : 5;   // edges per thread per tile (2 blocks/CU: LDS, VGPRs)
+    static constexpr int kSlots = kStageThreads * kEdges * 2;
+};
 
-__global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
+template <bool OTHER>
+__global__ __launch_bounds__(kStageThreads, 8) void bucket_scatter_staged_kernel(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m, int32_t n, int64_t chunk, int32_t B,
-    const unsigned long long* __restrict__ offs, int2* __restrict__ pairs) {
-    __shared__ int2 stage[kStagePairs];
+    const uint32_t* __restrict__ prefix, const unsigned long long* __restrict__ base, uint16_t* __restrict__ loc,
+    int32_t* __restrict__ other) {
+    constexpr int E = StageCfg<OTHER>::kEdges;
+    __shared__ uint32_t stage[StageCfg<OTHER>::kSlots];
+    __shared__ int32_t stage_o[OTHER ? StageCfg<OTHER>::kSlots : 1];
     __shared__ uint32_t toff[kStagedMaxB + 1];
-    __shared__ uint32_t run[kStagedMaxB];
+    __shared__ unsigned long long run[kStagedMaxB];   // next output slot of each bucket
     __shared__ uint32_t wsum[kStageThreads / 64];
     const int t = threadIdx.x;
-    for (int k = t; k < B; k += kStageThreads) run[k] = 0;
-    const unsigned long long* row = offs + (int64_t)blockIdx.x * B;
+    const int nblk = gridDim.x;
+    for (int k = t; k < B; k += kStageThreads) run[k] = base[k] + prefix[(int64_t)k * nblk + blockIdx.x];
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     int64_t end = beg + chunk;
     if (end > m) end = m;
-    for (int64_t t0 = beg; t0 < end; t0 += (int64_t)kStageThreads * kStageEdges) {
+    for (int64_t t0 = beg; t0 < end; t0 += (int64_t)kStageThreads * E) {
         for (int k = t; k <= B; k += kStageThreads) toff[k] = 0;
         __syncthreads();
-        int2 p[2 * kStageEdges];
-        uint32_t rank[2 * kStageEdges];
-        bool ok[2 * kStageEdges];
+        uint32_t key[2 * E];
+        int32_t oth[2 * E];
+        uint32_t rank[2 * E];
+        bool ok[2 * E];
 #pragma unroll
-        for (int j = 0; j < kStageEdges; ++j) {
+        for (int j = 0; j < E; ++j) {
             const int64_t i = t0 + t + (int64_t)j * kStageThreads;
             bool val = false;
             int32_t a = 0, c = 0;
@@ -180,8 +211,10 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
                 val = (uint32_t)a < (uint32_t)n && (uint32_t)c < (uint32_t)n;
             }
             ok[2 * j] = ok[2 * j + 1] = val;
-            p[2 * j] = make_int2(a, c);
-            p[2 * j + 1] = make_int2(c, a);
+            key[2 * j] = ((uint32_t)(a >> kShift) << 16) | (uint32_t)(a & (kBsz - 1));
+            key[2 * j + 1] = ((uint32_t)(c >> kShift) << 16) | (uint32_t)(c & (kBsz - 1));
+            oth[2 * j] = c;
+            oth[2 * j + 1] = a;
             if (val) {
                 rank[2 * j] = atomicAdd(&toff[a >> kShift], 1u);
                 rank[2 * j + 1] = atomicAdd(&toff[c >> kShift], 1u);
@@ -212,15 +245,21 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 2 * kStageEdges; ++j)
-            if (ok[j]) stage[toff[p[j].x >> kShift] + rank[j]] = p[j];
+        for (int j = 0; j < 2 * E; ++j)
+            if (ok[j]) {
+                const uint32_t slot = toff[key[j] >> 16] + rank[j];
+                stage[slot] = key[j];
+                if (OTHER) stage_o[slot] = oth[j];
+            }
         __syncthreads();
         // contiguous runs per bucket: staged slot i -> its bucket's next free slot
         const uint32_t total = toff[B];
         for (uint32_t i = t; i < total; i += kStageThreads) {
-            const int2 q = stage[i];
-            const int k = q.x >> kShift;
-            pairs[row[k] + run[k] + (i - toff[k])] = q;
+            const uint32_t q = stage[i];
+            const int k = (int)(q >> 16);
+            const unsigned long long pos = run[k] + (i - toff[k]);
+            loc[pos] = (uint16_t)(q & 0xffffu);
+            if (OTHER) other[pos] = stage_o[i];
         }
         __syncthreads();
         for (int k = t; k < B; k += kStageThreads) run[k] += toff[k + 1] - toff[k];
@@ -266,9 +305,23 @@ __device__ __forceinline__ void hist_flush(HistLds& L, unsigned long long best, 
 }
 
 // ------------------------------------------------------------------ pass D
+// Adds one entry per lane to the LDS counters; lanes of a wave that hit the
+// wave's first key (hub vertices) are folded into one atomic.
+__device__ __forceinline__ void count_lane(uint32_t* cnt, bool ok, int32_t x) {
+    const int32_t lead = __shfl(x, __builtin_ctzll(ballot(ok) | (1ull << 63)) & 63);
+    const uint64_t same = ballot(ok && x == lead);
+    if (ok && x == lead) {
+        if (lanes_below(same) == 0) atomicAdd(&cnt[lead], (uint32_t)__popcll(same));
+    } else if (ok) {
+        atomicAdd(&cnt[x], 1u);
+    }
+}
+
+constexpr int kUnrollD = 4;
+
 __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
-    const int2* __restrict__ pairs, const unsigned long long* __restrict__ base, int32_t n,
-    int32_t* __restrict__ deg, int count_pairs, int want_hist, unsigned long long* __restrict__ hist64,
+    const uint16_t* __restrict__ loc, const int32_t* __restrict__ other, const unsigned long long* __restrict__ base,
+    int32_t n, int32_t* __restrict__ deg, int count_pairs, int want_hist, unsigned long long* __restrict__ hist64,
     unsigned long long* __restrict__ histx, int32_t* __restrict__ tail, int64_t tail_cap,
     unsigned long long* __restrict__ tail_count, unsigned long long* __restrict__ argmax_key, int want_csr,
     int64_t* __restrict__ off, int32_t* __restrict__ adj) {
@@ -289,18 +342,15 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
         for (int j = threadIdx.x; j < nv; j += kBlockD) cnt[j] = (uint32_t)deg[x0 + j];
     }
     // every lane runs the same trip count so the wave-level aggregation can ballot
-    for (unsigned long long i0 = beg; count_pairs && i0 < end; i0 += kBlockD) {
-        const unsigned long long i = i0 + threadIdx.x;
-        bool ok = i < end;
-        int32_t x = ok ? pairs[i].x - x0 : -1;
-        // aggregate lanes that hit the wave's first key (hub vertices)
-        int32_t lead = __shfl(x, __builtin_ctzll(ballot(ok) | (1ull << 63)) & 63);
-        uint64_t same = ballot(ok && x == lead);
-        if (ok && x == lead) {
-            if (lanes_below(same) == 0) atomicAdd(&cnt[lead], (uint32_t)__popcll(same));
-        } else if (ok) {
-            atomicAdd(&cnt[x], 1u);
+    for (unsigned long long i0 = beg; count_pairs && i0 < end; i0 += (unsigned long long)kBlockD * kUnrollD) {
+        int32_t x[kUnrollD];
+#pragma unroll
+        for (int r = 0; r < kUnrollD; ++r) {
+            const unsigned long long i = i0 + threadIdx.x + (unsigned long long)r * kBlockD;
+            x[r] = i < end ? (int32_t)loc[i] : -1;
         }
+#pragma unroll
+        for (int r = 0; r < kUnrollD; ++r) count_lane(cnt, x[r] >= 0, x[r]);
     }
     __syncthreads();
     unsigned long long best = 0;
@@ -343,21 +393,21 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     __syncthreads();
     for (unsigned long long i0 = beg; i0 < end; i0 += kBlockD) {
         const unsigned long long i = i0 + t;
-        bool ok = i < end;
-        int2 p = ok ? pairs[i] : make_int2(x0 - 1, 0);
-        int32_t x = p.x - x0;
+        const bool ok = i < end;
+        const int32_t x = ok ? (int32_t)loc[i] : -1;
+        const int32_t y = ok ? other[i] : 0;
         // lanes sharing the wave's first key reserve their slots with one atomic
-        int first = __builtin_ctzll(ballot(ok) | (1ull << 63)) & 63;
-        int32_t lead = __shfl(x, first);
-        uint64_t same = ballot(ok && x == lead);
-        uint32_t rank = lanes_below(same);
+        const int first = __builtin_ctzll(ballot(ok) | (1ull << 63)) & 63;
+        const int32_t lead = __shfl(x, first);
+        const uint64_t same = ballot(ok && x == lead);
+        const uint32_t rank = lanes_below(same);
         uint32_t basepos = 0;
         if (ok && x == lead && rank == 0) basepos = atomicAdd(&cnt[lead], (uint32_t)__popcll(same));
-        int leader = __builtin_ctzll(same | (1ull << 63)) & 63;
+        const int leader = __builtin_ctzll(same | (1ull << 63)) & 63;
         basepos = __shfl(basepos, leader);
         if (ok) {
-            uint32_t pos = (x == lead) ? basepos + rank : atomicAdd(&cnt[x], 1u);
-            adj[beg + pos] = p.y;
+            const uint32_t pos = (x == lead) ? basepos + rank : atomicAdd(&cnt[x], 1u);
+            adj[beg + pos] = y;
         }
     }
 }
@@ -389,7 +439,7 @@ int bucket_plan(int32_t n, int64_t m, BucketPlan* p) {
     if (nblk < 1) nblk = 1;
     // the direct scatter (many buckets) keeps fewer blocks so the open output
     // runs stay within L2 and get written back as whole lines
-    const int64_t maxblk = p->B > kStagedMaxB ? 256 : 1024;
+    const int64_t maxblk = p->B > kStagedMaxB ? 256 : kScanThreads;
     if (nblk > maxblk) nblk = maxblk;
     p->nblk = (int32_t)nblk;
     p->chunk = (m + nblk - 1) / nblk;
@@ -397,28 +447,58 @@ int bucket_plan(int32_t n, int64_t m, BucketPlan* p) {
     return 0;
 }
 
-hipError_t launch_bucket_csr_from_deg(int32_t n, const BucketPlan& p, const BucketBufs& w, int32_t* deg,
-                                      int64_t* off, int32_t* adj, hipStream_t s) {
-    bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.pairs, w.base, n, deg, 0, 0, nullptr, nullptr, nullptr, 0,
+static hipError_t launch_scatter(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
+                                 const BucketBufs& w, bool with_other, hipStream_t s) {
+    if (p.B <= kStagedMaxB) {
+        if (with_other)
+            bucket_scatter_staged_kernel<true><<<p.nblk, kStageThreads, 0, s>>>(u, v, m, n, p.chunk, p.B, w.counts,
+                                                                                w.base, w.loc, w.other);
+        else
+            bucket_scatter_staged_kernel<false><<<p.nblk, kStageThreads, 0, s>>>(u, v, m, n, p.chunk, p.B, w.counts,
+                                                                                 w.base, w.loc, nullptr);
+    } else {
+        const size_t lds = (size_t)p.B * sizeof(uint32_t);
+        if (with_other)
+            bucket_scatter_kernel<true><<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.offs, w.loc, w.other);
+        else
+            bucket_scatter_kernel<false><<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.offs, w.loc, nullptr);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
+                                      BucketBufs& w, int32_t* deg, int64_t* off, int32_t* adj, hipStream_t s) {
+    if (!w.other_written) {
+        // the degree pass kept only the local ids: scatter again with the
+        // other endpoints.  Both arrays are rewritten together, because the
+        // order inside a tile's run is not reproducible between launches.
+        hipError_t e = launch_scatter(u, v, m, n, p, w, true, s);
+        if (e != hipSuccess) return e;
+        w.other_written = true;
+    }
+    bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, w.other, w.base, n, deg, 0, 0, nullptr, nullptr, nullptr, 0,
                                                   nullptr, nullptr, 1, off, adj);
     return hipGetLastError();
 }
 
 hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
-                                const BucketBufs& w, int32_t* deg, int want_hist, unsigned long long* hist64,
+                                BucketBufs& w, int32_t* deg, int want_hist, unsigned long long* hist64,
                                 unsigned long long* histx, int32_t* tail, int64_t tail_cap,
                                 unsigned long long* tail_count, unsigned long long* argmax_key, int want_csr,
                                 int64_t* off, int32_t* adj, hipStream_t s) {
     const size_t lds = (size_t)p.B * sizeof(uint32_t);
     bucket_count_kernel<<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.counts, w.err);
-    bucket_totals_kernel<<<(p.B + kBlock - 1) / kBlock, kBlock, 0, s>>>(w.counts, p.nblk, p.B, w.tot);
+    bucket_colscan_kernel<<<p.B, kScanThreads, 0, s>>>(w.counts, p.nblk, w.tot);
     bucket_scan_kernel<<<1, 1024, 0, s>>>(w.tot, p.B, w.base);
-    bucket_offsets_kernel<<<(p.B + kBlock - 1) / kBlock, kBlock, 0, s>>>(w.counts, p.nblk, p.B, w.base, w.offs);
-    if (p.B <= kStagedMaxB)
-        bucket_scatter_staged_kernel<<<p.nblk, kStageThreads, 0, s>>>(u, v, m, n, p.chunk, p.B, w.offs, w.pairs);
-    else
-        bucket_scatter_kernel<<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.offs, w.pairs);
-    bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.pairs, w.base, n, deg, 1, want_hist, hist64, histx, tail,
+    if (p.B > kStagedMaxB) {
+        const int64_t cells = (int64_t)p.nblk * p.B;
+        bucket_offsets_kernel<<<(int)((cells + kBlock - 1) / kBlock), kBlock, 0, s>>>(w.counts, p.nblk, p.B, w.base,
+                                                                                       w.offs);
+    }
+    hipError_t e = launch_scatter(u, v, m, n, p, w, want_csr != 0, s);
+    if (e != hipSuccess) return e;
+    w.other_written = want_csr != 0;
+    bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, w.other, w.base, n, deg, 1, want_hist, hist64, histx, tail,
                                                   tail_cap, tail_count, argmax_key, want_csr, off, adj);
     return hipGetLastError();
 }

@@ -19,28 +19,32 @@ struct BucketPlan {
 };
 
 struct BucketBufs {
-    uint32_t* counts;            // [nblk][B]
+    uint32_t* counts;            // [B][nblk]: per-block counts, then their prefix over the blocks
     unsigned long long* tot;     // [B]
     unsigned long long* base;    // [B + 1]
-    unsigned long long* offs;    // [nblk][B]
-    int2* pairs;                 // [2m]
+    unsigned long long* offs;    // [nblk][B], only when B > kStagedMaxB
+    uint16_t* loc;               // [2m] endpoint id within its bucket, grouped by bucket
+    int32_t* other;              // [2m] the other endpoint (CSR builds)
     unsigned long long* err;     // range errors
+    bool other_written = false;
 };
 
-// returns -1 if n is too large for the bucketed pass
+// returns -1 if n is too large for the bucketed pass (m must be < 2^31: the
+// per-bucket prefixes are 32-bit)
 int bucket_plan(int32_t n, int64_t m, BucketPlan* p);
 
 // deg[n] (+ histograms when want_hist, + CSR off[n+1]/adj[2m] when want_csr).
 // hist64/histx/tail_count/argmax_key must be zeroed by the caller.
 hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
-                                const BucketBufs& w, int32_t* deg, int want_hist, unsigned long long* hist64,
+                                BucketBufs& w, int32_t* deg, int want_hist, unsigned long long* hist64,
                                 unsigned long long* histx, int32_t* tail, int64_t tail_cap,
                                 unsigned long long* tail_count, unsigned long long* argmax_key, int want_csr,
                                 int64_t* off, int32_t* adj, hipStream_t s);
 
-// CSR from an earlier launch_bucket_degree's pairs and deg[] (no recount)
-hipError_t launch_bucket_csr_from_deg(int32_t n, const BucketPlan& p, const BucketBufs& w, int32_t* deg,
-                                      int64_t* off, int32_t* adj, hipStream_t s);
+// CSR from an earlier launch_bucket_degree's buckets and deg[] (no recount);
+// scatters the other endpoints first if that pass did not
+hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
+                                      BucketBufs& w, int32_t* deg, int64_t* off, int32_t* adj, hipStream_t s);
 
 hipError_t launch_degree_hist(const int32_t* deg, int32_t n, unsigned long long* hist64, unsigned long long* histx,
                               int32_t* tail, int64_t tail_cap, unsigned long long* tail_count,

@@ -101,6 +101,9 @@ struct Call {
     void kbytes(int rec, double kbytes) {
         if (rec >= 0) krecs[rec].bytes = kbytes;
     }
+    void kadd(int rec, double kbytes) {
+        if (rec >= 0) krecs[rec].bytes += kbytes;
+    }
 };
 
 struct SvInput {
@@ -112,6 +115,7 @@ struct SvInput {
 };
 
 int choose_nseg(int64_t m);
+int pass0_chunks(int64_t m, int32_t n);
 int run_sv(Call& c, const SvInput& in, int policy, double theta, int max_passes);
 int run_label(Call& c);
 

@@ -32,6 +32,7 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     Workspace& ws = *c.ws;
     BucketPlan p;
     if (bucket_plan(c.n, c.m, &p)) return fail(CC_EINVAL, "n too large for the degree pass");
+    if (c.m >= (int64_t)1 << 31) return fail(CC_EINVAL, "m too large for the degree pass (m < 2^31)");
     r->plan = p;
     const int64_t m = c.m;
     void *pc, *po, *pp, *pdeg, *ptail;
@@ -39,8 +40,14 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     // WS_HIST: per-block bucket counts, then (8-byte aligned) totals, bases, error counter
     const size_t counts_bytes = ((size_t)p.nblk * p.B * sizeof(uint32_t) + 255) & ~(size_t)255;
     if ((rc = ws.get(WS_HIST, counts_bytes + (size_t)(2 * p.B + 2) * sizeof(unsigned long long), &pc))) return rc;
-    if ((rc = ws.get(WS_CURSOR, (size_t)p.nblk * p.B * sizeof(unsigned long long), &po))) return rc;
-    if ((rc = ws.get(WS_QUEUE, (size_t)2 * m * sizeof(int2), &pp))) return rc;  // (endpoint, other) pairs
+    if (p.B > kStagedMaxB) {
+        if ((rc = ws.get(WS_CURSOR, (size_t)p.nblk * p.B * sizeof(unsigned long long), &po))) return rc;
+    } else {
+        po = nullptr;
+    }
+    // bucketed endpoints: 16-bit local ids, then (256-aligned) the other ends
+    const size_t loc_bytes = ((size_t)2 * m * sizeof(uint16_t) + 255) & ~(size_t)255;
+    if ((rc = ws.get(WS_QUEUE, loc_bytes + (size_t)2 * m * sizeof(int32_t), &pp))) return rc;
     if ((rc = ws.get(WS_DEG, (size_t)c.n * sizeof(int32_t), &pdeg))) return rc;
     const int64_t tail_cap = std::min<int64_t>(c.n, 2 * m / kExactBins + 1);
     if ((rc = ws.get(WS_TAIL, (size_t)tail_cap * sizeof(int32_t), &ptail))) return rc;
@@ -50,7 +57,8 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     w.base = w.tot + p.B;
     w.err = w.base + p.B + 1;
     w.offs = (unsigned long long*)po;
-    w.pairs = (int2*)pp;
+    w.loc = (uint16_t*)pp;
+    w.other = (int32_t*)((char*)pp + loc_bytes);
     r->bufs = w;
     r->deg = c.deg_out ? c.deg_out : (int32_t*)pdeg;
     r->tail = (int32_t*)ptail;
@@ -251,7 +259,7 @@ int run_bfs_route(Call& c, DegreeResult& r) {
         r.off = (int64_t*)poff;
         r.adj = (int32_t*)padj;
         int k0 = c.kbeg();
-        hipError_t e = launch_bucket_csr_from_deg(c.n, r.plan, r.bufs, r.deg, r.off, r.adj, c.stream);
+        hipError_t e = launch_bucket_csr_from_deg(c.u, c.v, c.m, c.n, r.plan, r.bufs, r.deg, r.off, r.adj, c.stream);
         if (e != hipSuccess) return hip_fail(e, "csr launch");
         c.kend(CC_K_CSR, k0, 16.0 * c.m + 12.0 * c.n);
         if (c.stats) c.bytes += 16.0 * c.m + 12.0 * c.n;
@@ -338,7 +346,7 @@ int run_label(Call& c) {
     if (req == CC_ROUTE_AUTO) req = router_loaded() ? CC_ROUTE_ROUTER : CC_ROUTE_HEURISTIC;
     if (req == CC_ROUTE_ROUTER && !router_loaded()) return fail(CC_ENOROUTER, "no router weights loaded");
     BucketPlan probe;
-    const bool can_predict = bucket_plan(c.n, c.m, &probe) == 0 && c.m <= (int64_t)1 << 31;
+    const bool can_predict = bucket_plan(c.n, c.m, &probe) == 0 && c.m < (int64_t)1 << 31;
     int route = CC_R1_SV;
     DegreeResult dr;
     int rc;

@@ -38,18 +38,18 @@ __global__ __launch_bounds__(kBlock) void sv_init_kernel(int32_t* __restrict__ p
 }
 
 // One pass: hook + compact over one block segment of edges.
-// SOA: edges come from the caller's u[], v[] (dense); block b takes
-// [b*cap, min((b+1)*cap, m)) and checks ids against [0, n).  Else from
-// segment b of `in`.
+// SOA: edges come from the caller's u[], v[] (dense); the block works on
+// segment b = seg0 + blockIdx.x, edges [b*cap, min((b+1)*cap, m)), and checks
+// ids against [0, n).  Else from segment b of `in`.
 template <bool SOA>
 __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restrict__ u, const int32_t* __restrict__ v,
-                                                         int64_t m, int32_t n, SegList in, int32_t* parent,
-                                                         SegList out, int write_out, int max_link,
+                                                         int64_t m, int32_t n, int32_t seg0, SegList in,
+                                                         int32_t* parent, SegList out, int write_out, int max_link,
                                                          int32_t* __restrict__ hooked,
                                                          uint32_t* __restrict__ hooked_count,
                                                          unsigned long long* __restrict__ totals) {
     __shared__ uint32_t lds[kWaves + 1];
-    const int b = blockIdx.x;
+    const int b = seg0 + blockIdx.x;
     int2* dst = out.buf + (int64_t)b * out.cap;
     int32_t* hdst = hooked + (int64_t)b * out.cap;
     uint32_t kept_off = 0, hook_off = 0, bad = 0;
@@ -130,6 +130,10 @@ __global__ __launch_bounds__(kBlock) void sv_shortcut_kernel(int32_t* parent, co
     }
 }
 
+// Full pointer jumping: every vertex is pointed straight at its root.  Run
+// alone (no hook in flight), so the plain stores cannot undo an atomicMin.
+// Serves as the final labelling and as the shortcut between the chunks of the
+// first pass.
 __global__ __launch_bounds__(kBlock) void sv_finalize_kernel(int32_t* parent, int32_t n) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -155,18 +159,19 @@ hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s) {
 }
 
 hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
-                              SegList out, int write_out, int max_link, int32_t* hooked, uint32_t* hooked_count,
-                              unsigned long long* totals, hipStream_t s) {
+                              SegList out, int32_t seg0, int32_t nblocks, int write_out, int max_link,
+                              int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals, hipStream_t s) {
+    if (seg0 < 0 || nblocks < 1 || seg0 + nblocks > out.nseg) return hipErrorInvalidValue;
     SegList none{nullptr, 0, 0, nullptr};
-    sv_pass_kernel<true><<<out.nseg, kBlock, 0, s>>>(u, v, m, n, none, parent, out, write_out, max_link, hooked,
-                                                     hooked_count, totals);
+    sv_pass_kernel<true><<<nblocks, kBlock, 0, s>>>(u, v, m, n, seg0, none, parent, out, write_out, max_link, hooked,
+                                                    hooked_count, totals);
     return hipGetLastError();
 }
 
 hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int max_link, int32_t* hooked,
                               uint32_t* hooked_count, unsigned long long* totals, hipStream_t s) {
-    sv_pass_kernel<false><<<in.nseg, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, in, parent, out, write_out, max_link,
-                                                     hooked, hooked_count, totals);
+    sv_pass_kernel<false><<<in.nseg, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, 0, in, parent, out, write_out,
+                                                     max_link, hooked, hooked_count, totals);
     return hipGetLastError();
 }
 
