@@ -50,6 +50,21 @@ def time_route(ccmi, torch, u, v, n, route, steps, warmup, profile=False):
     return out, (t1 - t0) / steps, stats
 
 
+def measured_traffic(cls, config):
+    """HBM bytes per launch of kernel class `cls` on `config` from the committed
+    rocprofv3 counter summary, or None if there is none or the kernel's source
+    changed since it was taken."""
+    from paper_1607_06156_amd import rocprof_summary as rs
+    path = os.path.join(ROOT, "profiles", f"pmc_{cls}_{config}.txt")
+    if cls not in rs.KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    d = rs.read_pmc_file(path)
+    if d.get("source_sha256") != rs.source_sha256(cls):
+        log(f"[bench] {path}: kernel sources changed since the counters were taken; traffic unknown")
+        return None
+    return float(d["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +74,8 @@ def main():
     ap.add_argument("--route", default="heuristic")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-compare", action="store_true", help="skip the forced-route comparison")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -70,6 +87,13 @@ def main():
 
     import gen
     import paper_1607_06156_amd as ccmi
+
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     if args.config.startswith("batch"):
         return bench_batched(args)
@@ -97,7 +121,8 @@ def main():
     achieved = (kb[dom] / (kms[dom] / 1e3)) / 1e9 if kms[dom] > 0 else 0.0
     roofline = {
         "bound": "hbm", "kernel": ccmi.KERNEL_CLASSES[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(ccmi.KERNEL_CLASSES[dom], args.config),
         "avg_launch_ms": round(float(kms[dom] / max(kl[dom], 1)), 4),
         "bytes_per_launch": float(kb[dom] / max(kl[dom], 1)),
     }
