@@ -10,10 +10,11 @@
 // The concatenated edge list is cut into tiles of 1024 edges; every tile keeps
 // its own output segment (survivors of tile t go to slots [t*1024, ...)), so
 // no global atomic places output.  Pass after pass each workgroup hooks and
-// compacts its tiles, pointer-jumps the roots hooked in them, and waits at a
-// grid barrier.  After the barrier every workgroup sums the per-block survivor
-// partials and takes the same stop decision, so convergence is decided on the
-// device and the host waits once.  Small graphs finish in the first passes and
+// compacts its tiles and waits at a grid barrier.  After the barrier every
+// workgroup sums the per-block survivor and hook partials and takes the same
+// decisions (stop; pointer-jump the roots hooked in its tiles or leave them to
+// the final compression), so convergence is decided on the device and the
+// host waits once.  Small graphs finish in the first passes and
 // simply drop out of the active tiles (Section III-A.4: completed work leaves
 // the working set).
 #include "batched.hpp"
@@ -41,13 +42,14 @@ struct BatchArgs {
     unsigned long long* status;  // [0] error bits, [1] passes, [2] range errors
     int32_t max_passes;
     int32_t max_link;     // hook attempts per edge per pass (see sv_segment)
-    unsigned long long* part;   // per-block survivor partials, 2 x gridDim
+    unsigned long long* part;   // per-block partials: survivors (2 x gridDim), then hooks (2 x gridDim)
 };
 
 constexpr int64_t kTileE = (int64_t)kBlock * kEPT;   // edges (or vertices) per tile
 
 enum : unsigned long long { kErrRange = 1, kErrOffsets = 2, kErrBarrier = 4, kErrPasses = 8 };
 constexpr int kStampBase = 8;    // status[8 + i]: wall clock when barrier i was passed
+constexpr unsigned long long kLazyJump = 8;   // jump hooked roots only if hooks <= 8 x survivors
 constexpr int kMaxStamps = 40;
 
 __device__ __forceinline__ void stamp(unsigned long long* status, int i) {
@@ -118,7 +120,7 @@ struct TileWalk {
 
 __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     __shared__ uint32_t lds[kWaves + 1];
-    __shared__ unsigned long long sh_total;
+    __shared__ unsigned long long sh_total, sh_hooks;
     __shared__ int32_t sh_g;
     const int b = blockIdx.x;
     const int nb = gridDim.x;
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     // every tile was written by this block).  The block barrier publishes the
     // per-tile counts thread 0 wrote, so every thread reads the same length.
     __syncthreads();
-    unsigned long long block_kept = 0;
+    unsigned long long block_kept = 0, block_hooks = 0;
     for (int64_t t = tw.first; t < tw.end; t += tw.step) {
         const uint32_t len = A.cnt1[t];
         uint32_t kept = 0, hk = 0;
@@ -227,10 +229,14 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
             A.hcnt[t] = hk;
         }
         block_kept += kept;
+        block_hooks += hk;
     }
     unsigned long long* const part_base = A.part;
     unsigned long long* part_rd = part_base;
-    if (threadIdx.x == 0) part_base[b] = block_kept;
+    if (threadIdx.x == 0) {
+        part_base[b] = block_kept;
+        part_base[2 * nb + b] = block_hooks;
+    }
 
     int pass = 1;
     int2* in = A.buf0;
@@ -241,25 +247,43 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
         grid_barrier(A.bar, A.status);
         if (load_status(A.status)) return;
         stamp(A.status, pass);
-        // pointer jumping of the roots hooked in this block's tiles
-        for (int64_t t = tw.first; t < tw.end; t += tw.step) {
-            const uint32_t hc = A.hcnt[t];
-            const int32_t* h = A.hooked + t * kTileE;
-            for (uint32_t j = threadIdx.x; j < hc; j += kBlock) {
-                const int32_t x = h[j];
-                A.parent[x] = find_root(A.parent, x);
+        // every block sums the same partials and takes the same decisions
+        unsigned long long s = 0, sh = 0;
+        for (int i = threadIdx.x; i < nb; i += kBlock) {
+            s += part_rd[i];
+            sh += part_rd[2 * nb + i];
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            s += __shfl_xor(s, o);
+            sh += __shfl_xor(sh, o);
+        }
+        if (threadIdx.x == 0) {
+            sh_total = 0;
+            sh_hooks = 0;
+        }
+        __syncthreads();
+        if (lane_id() == 0) {
+            atomicAdd(&sh_total, s);
+            atomicAdd(&sh_hooks, sh);
+        }
+        __syncthreads();
+        const unsigned long long total = sh_total, hooks = sh_hooks;
+        if (total == 0) break;   // the final compression resolves every link
+        // Pointer jumping of the roots hooked in this block's tiles, unless
+        // they far outnumber the surviving edges (typically after the first
+        // pass, when nearly every vertex was hooked): then the next pass's
+        // finds walk the extra links of the few survivors instead, and the
+        // final compression flattens everything once.
+        if (hooks <= kLazyJump * total) {
+            for (int64_t t = tw.first; t < tw.end; t += tw.step) {
+                const uint32_t hc = A.hcnt[t];
+                const int32_t* h = A.hooked + t * kTileE;
+                for (uint32_t j = threadIdx.x; j < hc; j += kBlock) {
+                    const int32_t x = h[j];
+                    A.parent[x] = find_root(A.parent, x);
+                }
             }
         }
-        // every block sums the same partials and takes the same decision
-        unsigned long long s = 0;
-        for (int i = threadIdx.x; i < nb; i += kBlock) s += part_rd[i];
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if (threadIdx.x == 0) sh_total = 0;
-        __syncthreads();
-        if (lane_id() == 0) atomicAdd(&sh_total, s);
-        __syncthreads();
-        const unsigned long long total = sh_total;
-        if (total == 0) break;
         if (A.max_passes > 0 && pass >= A.max_passes) {
             if (b == 0 && threadIdx.x == 0)
                 __hip_atomic_fetch_or(&A.status[0], (unsigned long long)kErrPasses, __ATOMIC_RELAXED,
@@ -272,6 +296,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
         // barrier, i.e. finished summing it.
         unsigned long long* part_out = part_base + (pass & 1) * nb;
         block_kept = 0;
+        block_hooks = 0;
         for (int64_t t = tw.first; t < tw.end; t += tw.step) {
             const uint32_t len = cin[t];
             uint32_t kept = 0, hk = 0;
@@ -291,8 +316,12 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
                 A.hcnt[t] = hk;
             }
             block_kept += kept;
+            block_hooks += hk;
         }
-        if (threadIdx.x == 0) part_out[b] = block_kept;
+        if (threadIdx.x == 0) {
+            part_out[b] = block_kept;
+            part_out[2 * nb + b] = block_hooks;
+        }
         part_rd = part_out;
         ++pass;
         int2* tt = in; in = out; out = tt;

@@ -80,7 +80,8 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     if ((rc = ws.get(WS_EDGES1, slots * sizeof(int2), &p1))) return rc;
     if ((rc = ws.get(WS_HOOKED, slots * sizeof(int32_t), &ph))) return rc;
     const size_t cnt_bytes = ((size_t)tiles * 3 * sizeof(uint32_t) + 255) & ~(size_t)255;
-    if ((rc = ws.get(WS_SEGCOUNT, cnt_bytes + (size_t)blocks * 2 * sizeof(unsigned long long), &pc))) return rc;
+    // per-tile counts, then per-block partials (survivors and hooks, two arrays each)
+    if ((rc = ws.get(WS_SEGCOUNT, cnt_bytes + (size_t)blocks * 4 * sizeof(unsigned long long), &pc))) return rc;
     if ((rc = ws.get(WS_BATCH, kBatchCtl, &pb))) return rc;
     h.buf0 = (int2*)p0;
     h.buf1 = (int2*)p1;

@@ -43,6 +43,27 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
                 pc[k] = parent[c[k]];
             }
         }
+        // Walk the 2 * kEPT root chains of this thread in lockstep: every
+        // step issues the next load of each unfinished chain before using
+        // any, so the dependent loads of different chains overlap instead of
+        // queueing behind each other.  a[k] / c[k] become the roots.
+        for (;;) {
+            bool more = false, mva[kEPT], mvc[kEPT];
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                mva[k] = valid[k] && pa[k] != a[k];
+                mvc[k] = valid[k] && pc[k] != c[k];
+                if (mva[k]) a[k] = pa[k];
+                if (mvc[k]) c[k] = pc[k];
+                more |= mva[k] | mvc[k];
+            }
+            if (!more) break;
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                if (mva[k]) pa[k] = parent[a[k]];
+                if (mvc[k]) pc[k] = parent[c[k]];
+            }
+        }
         bool keep[kEPT], hk[kEPT];
         int2 e[kEPT];
         int32_t hroot[kEPT];
@@ -52,8 +73,8 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
             hk[k] = false;
             hroot[k] = 0;
             if (!valid[k]) continue;
-            int32_t ra = pa[k] == a[k] ? a[k] : find_root(parent, pa[k]);
-            int32_t rc = pc[k] == c[k] ? c[k] : find_root(parent, pc[k]);
+            int32_t ra = a[k];
+            int32_t rc = c[k];
             for (int tries = 0; ra != rc;) {
                 const int32_t lo = ra < rc ? ra : rc;
                 const int32_t hi = ra < rc ? rc : ra;

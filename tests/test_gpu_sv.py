@@ -1,4 +1,5 @@
-"""GPU parity of the SV routes (R1 plain SV, R2 SV-theta) against the oracle, bit-exact."""
+"""GPU parity of the SV routes (R1 plain SV, R2 SV-theta, and R1 chosen after
+the degree pass) against the oracle, bit-exact."""
 import numpy as np
 import pytest
 import torch
@@ -10,12 +11,41 @@ from gpu_util import assert_labels_equal, oracle_labels, say, to_dev
 pytestmark = pytest.mark.gpu
 
 ccmi = pytest.importorskip("paper_1607_06156_amd")
-ROUTES = ["sv", "sv-theta"]
+ROUTES = ["sv", "sv-theta", "predicted-sv"]
 
 
 def run(g, route, **kw):
     say(f"[gpu] {g.name} m={g.m} n={g.n} route={route}")
+    if route == "predicted-sv":
+        # degree pass and power-law fit first, then SV (tau below any K-S value)
+        route, kw = "heuristic", dict(kw, tau=1e-300)
     return ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route=route, **kw)
+
+
+def test_predicted_sv_route_taken():
+    g = gen.workload("rmat16")
+    lab, st = run(g, "predicted-sv", stats=True)
+    assert st["route"] == 1 and st["max_degree"] > 0   # R1 after the degree pass
+    assert_labels_equal(lab, oracle_labels(g), "rmat16/predicted-sv")
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_sparse_buckets_and_hubs(route):
+    """Ids spread over many 2^15-vertex buckets, most of them empty; a hub
+    with most edges; loops and duplicates only in the last bucket."""
+    rng = np.random.default_rng(11)
+    n = 3_000_017
+    u = rng.integers(0, n, 5000).astype(np.int32)
+    v = rng.integers(0, n, 5000).astype(np.int32)
+    g = gen.Graph(u, v, n, "sparse-buckets")
+    assert_labels_equal(run(g, route), oracle_labels(g), g.name)
+    leaves = rng.integers(0, n, 200_000).astype(np.int32)
+    hub = np.full(leaves.size, 2_999_999, np.int32)
+    g = gen.Graph(np.concatenate([hub, leaves[:100]]), np.concatenate([leaves, leaves[:100]]), n, "hub")
+    assert_labels_equal(run(g, route), oracle_labels(g), g.name)
+    tail = np.arange(n - 40, n, dtype=np.int32)
+    g = gen.Graph(np.concatenate([tail, tail[:-1]]), np.concatenate([tail, tail[1:]]), n, "last-bucket")
+    assert_labels_equal(run(g, route), oracle_labels(g), g.name)
 
 
 @pytest.mark.parametrize("route", ROUTES)
