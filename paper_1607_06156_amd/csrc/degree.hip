@@ -125,76 +125,62 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const unsigned long l
     if (t == 1023) base[B] = part[1023];
 }
 
-// offs[b][k] = base[k] + prefix[k][b]: block b's first output slot in bucket k
-// (only the direct scatter, which has no room to keep these in LDS)
-__global__ __launch_bounds__(kBlock) void bucket_offsets_kernel(const uint32_t* __restrict__ counts, int32_t nblk,
-                                                                int32_t B, const unsigned long long* __restrict__ base,
-                                                                unsigned long long* __restrict__ offs) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // i = b * B + k
-    if (i >= (int64_t)nblk * B) return;
-    const int b = (int)(i / B), k = (int)(i - (int64_t)b * B);
-    offs[i] = base[k] + counts[(int64_t)k * nblk + b];
-}
-
 // ------------------------------------------------------------------ pass C
 // Bucketed output is structure-of-arrays: loc[i] = endpoint - bucket start
 // (16 bits, all the degree count needs), other[i] = the other endpoint
 // (written only when a CSR is built).
-template <bool OTHER>
-__global__ __launch_bounds__(kBlock) void bucket_scatter_kernel(const int32_t* __restrict__ u,
-                                                                const int32_t* __restrict__ v, int64_t m, int32_t n,
-                                                                int64_t chunk, int32_t B,
-                                                                const unsigned long long* __restrict__ offs,
-                                                                uint16_t* __restrict__ loc,
-                                                                int32_t* __restrict__ other) {
-    extern __shared__ uint32_t cur[];
-    for (int k = threadIdx.x; k < B; k += kBlock) cur[k] = 0;
-    __syncthreads();
-    const unsigned long long* row = offs + (int64_t)blockIdx.x * B;
-    const int64_t beg = (int64_t)blockIdx.x * chunk;
-    int64_t end = beg + chunk;
-    if (end > m) end = m;
-    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-        int32_t a = u[i], c = v[i];
-        if ((uint32_t)a >= (uint32_t)n || (uint32_t)c >= (uint32_t)n) continue;
-        const unsigned long long pa = row[a >> kShift] + atomicAdd(&cur[a >> kShift], 1u);
-        loc[pa] = (uint16_t)(a & (kBsz - 1));
-        if (OTHER) other[pa] = c;
-        const unsigned long long pc = row[c >> kShift] + atomicAdd(&cur[c >> kShift], 1u);
-        loc[pc] = (uint16_t)(c & (kBsz - 1));
-        if (OTHER) other[pc] = a;
-    }
-}
-
-// Same scatter with each tile's entries first grouped by bucket in LDS, so a
-// bucket's entries leave the block as one contiguous run per tile (for B up
-// to kStagedMaxB buckets).  A staged entry packs (bucket << 16 | local id).
+//
+// Each block groups its tile's entries by bucket in LDS, so a bucket's
+// entries leave the block as one contiguous run per tile.  Up to kStagedMaxB
+// buckets the entries go straight to their buckets (16-bit local ids).  With
+// more buckets (n > 2^26) the tile is grouped by super-bucket (kSub = 8
+// consecutive buckets, 2^18 vertices) and the entries go, as 18-bit local ids
+// in 32-bit words, to the super-bucket's range -- the concatenation of its
+// buckets' ranges -- which bucket_split_kernel then splits.  A staged entry
+// packs (staging bucket << kKeyShift | local id).
 constexpr int kStageThreads = 1024;
+constexpr int kSub = 8;
+constexpr int kSuperShift = kShift + 3;
 template <bool OTHER>
 struct StageCfg {
     static constexpr int kEdges = OTHER ? 3 : 5;   // edges per thread per tile (2 blocks/CU: LDS, VGPRs)
     static constexpr int kSlots = kStageThreads * kEdges * 2;
 };
 
-template <bool OTHER>
+template <bool OTHER, bool SUPER>
 __global__ __launch_bounds__(kStageThreads, 8) void bucket_scatter_staged_kernel(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m, int32_t n, int64_t chunk, int32_t B,
     const uint32_t* __restrict__ prefix, const unsigned long long* __restrict__ base, uint16_t* __restrict__ loc,
-    int32_t* __restrict__ other) {
+    uint32_t* __restrict__ loc32, int32_t* __restrict__ other) {
     constexpr int E = StageCfg<OTHER>::kEdges;
+    constexpr int kSh = SUPER ? kSuperShift : kShift;      // staging bucket = id >> kSh
+    constexpr int kKeyShift = SUPER ? kSuperShift : 16;    // key = staging bucket << kKeyShift | local
+    constexpr uint32_t kLocalMask = (1u << kSh) - 1u;
     __shared__ uint32_t stage[StageCfg<OTHER>::kSlots];
     __shared__ int32_t stage_o[OTHER ? StageCfg<OTHER>::kSlots : 1];
     __shared__ uint32_t toff[kStagedMaxB + 1];
-    __shared__ unsigned long long run[kStagedMaxB];   // next output slot of each bucket
+    __shared__ unsigned long long run[kStagedMaxB];   // next output slot of each staging bucket
     __shared__ uint32_t wsum[kStageThreads / 64];
     const int t = threadIdx.x;
     const int nblk = gridDim.x;
-    for (int k = t; k < B; k += kStageThreads) run[k] = base[k] + prefix[(int64_t)k * nblk + blockIdx.x];
+    const int NB = SUPER ? (B + kSub - 1) / kSub : B;     // staging buckets
+    for (int k = t; k < NB; k += kStageThreads) {
+        if (SUPER) {
+            // block b's first slot in super-bucket k: its first bucket's start
+            // plus what the blocks before b put into each of its buckets
+            const int k0 = k * kSub, k1 = k0 + kSub < B ? k0 + kSub : B;
+            unsigned long long r = base[k0];
+            for (int q = k0; q < k1; ++q) r += prefix[(int64_t)q * nblk + blockIdx.x];
+            run[k] = r;
+        } else {
+            run[k] = base[k] + prefix[(int64_t)k * nblk + blockIdx.x];
+        }
+    }
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     int64_t end = beg + chunk;
     if (end > m) end = m;
     for (int64_t t0 = beg; t0 < end; t0 += (int64_t)kStageThreads * E) {
-        for (int k = t; k <= B; k += kStageThreads) toff[k] = 0;
+        for (int k = t; k <= NB; k += kStageThreads) toff[k] = 0;
         __syncthreads();
         uint32_t key[2 * E];
         int32_t oth[2 * E];
@@ -211,20 +197,20 @@ __global__ __launch_bounds__(kStageThreads, 8) void bucket_scatter_staged_kernel
                 val = (uint32_t)a < (uint32_t)n && (uint32_t)c < (uint32_t)n;
             }
             ok[2 * j] = ok[2 * j + 1] = val;
-            key[2 * j] = ((uint32_t)(a >> kShift) << 16) | (uint32_t)(a & (kBsz - 1));
-            key[2 * j + 1] = ((uint32_t)(c >> kShift) << 16) | (uint32_t)(c & (kBsz - 1));
+            key[2 * j] = ((uint32_t)(a >> kSh) << kKeyShift) | ((uint32_t)a & kLocalMask);
+            key[2 * j + 1] = ((uint32_t)(c >> kSh) << kKeyShift) | ((uint32_t)c & kLocalMask);
             oth[2 * j] = c;
             oth[2 * j + 1] = a;
             if (val) {
-                rank[2 * j] = atomicAdd(&toff[a >> kShift], 1u);
-                rank[2 * j + 1] = atomicAdd(&toff[c >> kShift], 1u);
+                rank[2 * j] = atomicAdd(&toff[a >> kSh], 1u);
+                rank[2 * j + 1] = atomicAdd(&toff[c >> kSh], 1u);
             }
         }
         __syncthreads();
-        // exclusive scan of the tile's bucket counts (B <= 2 * 1024 entries)
+        // exclusive scan of the tile's bucket counts (NB <= 2 * 1024 entries)
         {
-            const uint32_t c0 = 2 * t < B ? toff[2 * t] : 0u;
-            const uint32_t c1 = 2 * t + 1 < B ? toff[2 * t + 1] : 0u;
+            const uint32_t c0 = 2 * t < NB ? toff[2 * t] : 0u;
+            const uint32_t c1 = 2 * t + 1 < NB ? toff[2 * t + 1] : 0u;
             const uint32_t s = c0 + c1;
             uint32_t incl = s;
             for (int o = 1; o < 64; o <<= 1) {
@@ -236,33 +222,107 @@ __global__ __launch_bounds__(kStageThreads, 8) void bucket_scatter_staged_kernel
             if (t == 0) {
                 uint32_t acc = 0;
                 for (int w = 0; w < kStageThreads / 64; ++w) { uint32_t q = wsum[w]; wsum[w] = acc; acc += q; }
-                toff[B] = acc;
+                toff[NB] = acc;
             }
             __syncthreads();
             const uint32_t ex = wsum[t >> 6] + incl - s;
-            if (2 * t < B) toff[2 * t] = ex;
-            if (2 * t + 1 < B) toff[2 * t + 1] = ex + c0;
+            if (2 * t < NB) toff[2 * t] = ex;
+            if (2 * t + 1 < NB) toff[2 * t + 1] = ex + c0;
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < 2 * E; ++j)
             if (ok[j]) {
-                const uint32_t slot = toff[key[j] >> 16] + rank[j];
+                const uint32_t slot = toff[key[j] >> kKeyShift] + rank[j];
                 stage[slot] = key[j];
                 if (OTHER) stage_o[slot] = oth[j];
             }
         __syncthreads();
         // contiguous runs per bucket: staged slot i -> its bucket's next free slot
-        const uint32_t total = toff[B];
+        const uint32_t total = toff[NB];
         for (uint32_t i = t; i < total; i += kStageThreads) {
             const uint32_t q = stage[i];
-            const int k = (int)(q >> 16);
+            const int k = (int)(q >> kKeyShift);
             const unsigned long long pos = run[k] + (i - toff[k]);
-            loc[pos] = (uint16_t)(q & 0xffffu);
+            if (SUPER) loc32[pos] = q & kLocalMask;
+            else loc[pos] = (uint16_t)(q & kLocalMask);
             if (OTHER) other[pos] = stage_o[i];
         }
         __syncthreads();
-        for (int k = t; k < B; k += kStageThreads) run[k] += toff[k + 1] - toff[k];
+        for (int k = t; k < NB; k += kStageThreads) run[k] += toff[k + 1] - toff[k];
+        __syncthreads();
+    }
+}
+
+// Second level for n > 2^26: block S splits super-bucket S (its range is the
+// concatenation of buckets 8S .. 8S+7) into those buckets.  A tile of entries
+// is grouped by bucket in LDS (wave ballots rank the entries, one LDS atomic
+// per wave and bucket) and each bucket's part leaves as one contiguous run.
+constexpr int kSplitE = 4;
+template <bool OTHER>
+__global__ __launch_bounds__(kStageThreads) void bucket_split_kernel(const uint32_t* __restrict__ loc32,
+                                                                     const int32_t* __restrict__ other32,
+                                                                     const unsigned long long* __restrict__ base,
+                                                                     int32_t B, uint16_t* __restrict__ loc,
+                                                                     int32_t* __restrict__ other) {
+    __shared__ uint32_t stage[kStageThreads * kSplitE];
+    __shared__ int32_t stage_o[OTHER ? kStageThreads * kSplitE : 1];
+    __shared__ uint32_t cnt[kSub + 1];
+    __shared__ unsigned long long cur[kSub];
+    const int t = threadIdx.x;
+    const int k0 = blockIdx.x * kSub;
+    const int k1 = k0 + kSub < B ? k0 + kSub : B;
+    const unsigned long long beg = base[k0], end = base[k1];
+    if (t < kSub) cur[t] = k0 + t < k1 ? base[k0 + t] : 0ull;
+    for (unsigned long long t0 = beg; t0 < end; t0 += (unsigned long long)kStageThreads * kSplitE) {
+        if (t <= kSub) cnt[t] = 0;
+        __syncthreads();
+        uint32_t q[kSplitE], rank[kSplitE];
+        int32_t o[kSplitE];
+        bool ok[kSplitE];
+#pragma unroll
+        for (int j = 0; j < kSplitE; ++j) {
+            const unsigned long long i = t0 + t + (unsigned long long)j * kStageThreads;
+            ok[j] = i < end;
+            q[j] = ok[j] ? loc32[i] : 0u;
+            o[j] = (OTHER && ok[j]) ? other32[i] : 0;
+            const int sub = ok[j] ? (int)(q[j] >> kShift) : -1;
+            rank[j] = 0;
+            for (int s = 0; s < kSub; ++s) {
+                const uint64_t mk = ballot(sub == s);
+                if (mk) {
+                    uint32_t b0 = 0;
+                    if (lane_id() == 0) b0 = atomicAdd(&cnt[s], (uint32_t)__popcll(mk));
+                    b0 = __shfl(b0, 0);
+                    if (sub == s) rank[j] = b0 + lanes_below(mk);
+                }
+            }
+        }
+        __syncthreads();
+        if (t == 0) {
+            uint32_t acc = 0;
+            for (int s = 0; s < kSub; ++s) { const uint32_t c = cnt[s]; cnt[s] = acc; acc += c; }
+            cnt[kSub] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSplitE; ++j)
+            if (ok[j]) {
+                const uint32_t slot = cnt[q[j] >> kShift] + rank[j];
+                stage[slot] = q[j];
+                if (OTHER) stage_o[slot] = o[j];
+            }
+        __syncthreads();
+        const uint32_t total = cnt[kSub];
+        for (uint32_t i = t; i < total; i += kStageThreads) {
+            const uint32_t x = stage[i];
+            const int s = (int)(x >> kShift);
+            const unsigned long long pos = cur[s] + (i - cnt[s]);
+            loc[pos] = (uint16_t)(x & (kBsz - 1));
+            if (OTHER) other[pos] = stage_o[i];
+        }
+        __syncthreads();
+        if (t < kSub) cur[t] += cnt[t + 1] - cnt[t];
         __syncthreads();
     }
 }
@@ -437,32 +497,31 @@ int bucket_plan(int32_t n, int64_t m, BucketPlan* p) {
     if (p->B > kMaxBuckets) return -1;
     int64_t nblk = (m + 65535) / 65536;   // ~64K edges per block chunk
     if (nblk < 1) nblk = 1;
-    // the direct scatter (many buckets) keeps fewer blocks so the open output
-    // runs stay within L2 and get written back as whole lines
-    const int64_t maxblk = p->B > kStagedMaxB ? 256 : kScanThreads;
-    if (nblk > maxblk) nblk = maxblk;
+    if (nblk > kScanThreads) nblk = kScanThreads;
     p->nblk = (int32_t)nblk;
     p->chunk = (m + nblk - 1) / nblk;
     if (p->chunk < 1) p->chunk = 1;
     return 0;
 }
 
+template <bool OTHER>
+static void scatter_with(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
+                         const BucketBufs& w, hipStream_t s) {
+    if (p.B <= kStagedMaxB) {
+        bucket_scatter_staged_kernel<OTHER, false><<<p.nblk, kStageThreads, 0, s>>>(
+            u, v, m, n, p.chunk, p.B, w.counts, w.base, w.loc, nullptr, OTHER ? w.other : nullptr);
+    } else {
+        bucket_scatter_staged_kernel<OTHER, true><<<p.nblk, kStageThreads, 0, s>>>(
+            u, v, m, n, p.chunk, p.B, w.counts, w.base, nullptr, w.loc32, OTHER ? w.other32 : nullptr);
+        bucket_split_kernel<OTHER><<<(p.B + kSub - 1) / kSub, kStageThreads, 0, s>>>(
+            w.loc32, OTHER ? w.other32 : nullptr, w.base, p.B, w.loc, OTHER ? w.other : nullptr);
+    }
+}
+
 static hipError_t launch_scatter(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
                                  const BucketBufs& w, bool with_other, hipStream_t s) {
-    if (p.B <= kStagedMaxB) {
-        if (with_other)
-            bucket_scatter_staged_kernel<true><<<p.nblk, kStageThreads, 0, s>>>(u, v, m, n, p.chunk, p.B, w.counts,
-                                                                                w.base, w.loc, w.other);
-        else
-            bucket_scatter_staged_kernel<false><<<p.nblk, kStageThreads, 0, s>>>(u, v, m, n, p.chunk, p.B, w.counts,
-                                                                                 w.base, w.loc, nullptr);
-    } else {
-        const size_t lds = (size_t)p.B * sizeof(uint32_t);
-        if (with_other)
-            bucket_scatter_kernel<true><<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.offs, w.loc, w.other);
-        else
-            bucket_scatter_kernel<false><<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.offs, w.loc, nullptr);
-    }
+    if (with_other) scatter_with<true>(u, v, m, n, p, w, s);
+    else scatter_with<false>(u, v, m, n, p, w, s);
     return hipGetLastError();
 }
 
@@ -490,11 +549,6 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
     bucket_count_kernel<<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.counts, w.err);
     bucket_colscan_kernel<<<p.B, kScanThreads, 0, s>>>(w.counts, p.nblk, w.tot);
     bucket_scan_kernel<<<1, 1024, 0, s>>>(w.tot, p.B, w.base);
-    if (p.B > kStagedMaxB) {
-        const int64_t cells = (int64_t)p.nblk * p.B;
-        bucket_offsets_kernel<<<(int)((cells + kBlock - 1) / kBlock), kBlock, 0, s>>>(w.counts, p.nblk, p.B, w.base,
-                                                                                       w.offs);
-    }
     hipError_t e = launch_scatter(u, v, m, n, p, w, want_csr != 0, s);
     if (e != hipSuccess) return e;
     w.other_written = want_csr != 0;

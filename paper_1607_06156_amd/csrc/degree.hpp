@@ -10,7 +10,7 @@ constexpr int kBucketShift = 15;      // 32768 vertices per bucket (LDS counters
 constexpr int kMaxBuckets = 16384;    // n <= 2^29 for the bucketed degree pass
 constexpr int kExactBins = 4096;      // exact degree histogram below this
 constexpr int kBlockD = 1024;         // threads of the per-bucket kernel
-constexpr int kStagedMaxB = 2048;     // LDS-staged scatter up to this many buckets (n <= 2^26)
+constexpr int kStagedMaxB = 2048;     // one-level scatter up to this many buckets (n <= 2^26), else two levels
 
 struct BucketPlan {
     int32_t B;       // vertex buckets
@@ -22,9 +22,10 @@ struct BucketBufs {
     uint32_t* counts;            // [B][nblk]: per-block counts, then their prefix over the blocks
     unsigned long long* tot;     // [B]
     unsigned long long* base;    // [B + 1]
-    unsigned long long* offs;    // [nblk][B], only when B > kStagedMaxB
     uint16_t* loc;               // [2m] endpoint id within its bucket, grouped by bucket
     int32_t* other;              // [2m] the other endpoint (CSR builds)
+    uint32_t* loc32;             // [2m] first level when B > kStagedMaxB: id within the super-bucket
+    int32_t* other32;            // [2m] its other ends (CSR builds)
     unsigned long long* err;     // range errors
     bool other_written = false;
 };

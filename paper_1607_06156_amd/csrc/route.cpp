@@ -41,7 +41,8 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     const size_t counts_bytes = ((size_t)p.nblk * p.B * sizeof(uint32_t) + 255) & ~(size_t)255;
     if ((rc = ws.get(WS_HIST, counts_bytes + (size_t)(2 * p.B + 2) * sizeof(unsigned long long), &pc))) return rc;
     if (p.B > kStagedMaxB) {
-        if ((rc = ws.get(WS_CURSOR, (size_t)p.nblk * p.B * sizeof(unsigned long long), &po))) return rc;
+        // first level of the two-level scatter: 32-bit ids (+ other ends for a CSR)
+        if ((rc = ws.get(WS_CURSOR, (size_t)2 * m * (want_csr ? 8 : 4), &po))) return rc;
     } else {
         po = nullptr;
     }
@@ -56,7 +57,8 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     w.tot = (unsigned long long*)((char*)pc + counts_bytes);
     w.base = w.tot + p.B;
     w.err = w.base + p.B + 1;
-    w.offs = (unsigned long long*)po;
+    w.loc32 = (uint32_t*)po;
+    w.other32 = po && want_csr ? (int32_t*)((uint32_t*)po + 2 * m) : nullptr;
     w.loc = (uint16_t*)pp;
     w.other = (int32_t*)((char*)pp + loc_bytes);
     r->bufs = w;
@@ -258,6 +260,13 @@ int run_bfs_route(Call& c, DegreeResult& r) {
         if ((rc = ws.get(WS_ADJ, (size_t)2 * c.m * sizeof(int32_t), &padj))) return rc;
         r.off = (int64_t*)poff;
         r.adj = (int32_t*)padj;
+        if (!r.bufs.other_written && r.plan.B > kStagedMaxB) {
+            // the two-level scatter will run again with the other ends
+            void* po;
+            if ((rc = ws.get(WS_CURSOR, (size_t)2 * c.m * 8, &po))) return rc;
+            r.bufs.loc32 = (uint32_t*)po;
+            r.bufs.other32 = (int32_t*)((uint32_t*)po + 2 * c.m);
+        }
         int k0 = c.kbeg();
         hipError_t e = launch_bucket_csr_from_deg(c.u, c.v, c.m, c.n, r.plan, r.bufs, r.deg, r.off, r.adj, c.stream);
         if (e != hipSuccess) return hip_fail(e, "csr launch");

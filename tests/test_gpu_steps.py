@@ -169,6 +169,40 @@ def test_routes_exact(graph, route):
         assert st["edges_after_filter"] == r["u"].shape[0]
 
 
+def test_two_level_buckets_large_n():
+    """n > 2^26, i.e. more than 2048 vertex buckets: the degree pass scatters
+    through super-buckets first.  Degrees, the CSR and the routes that build
+    it (directly, or by scattering again after the prediction) against the
+    oracle; a hub sits in the last, partial super-bucket."""
+    rng = np.random.default_rng(21)
+    n = 70_000_003
+    m = 3_000_000
+    u = rng.integers(0, n, m).astype(np.int32)
+    v = rng.integers(0, n, m).astype(np.int32)
+    v[::7] = u[::7]
+    u[:20_000] = n - 5
+    g = gen.Graph(u, v, n, "large-n")
+    du, dv = to_dev(u), to_dev(v)
+    say("[gpu] degree large-n")
+    d = ccmi.degree(du, dv, n)
+    assert np.array_equal(d.cpu().numpy(), odeg.degree(u, v, n))
+    say("[gpu] csr large-n")
+    off, adj, deg = ccmi.csr(du, dv, n)
+    eoff, eadj = hybrid.csr(u, v, n)
+    assert np.array_equal(off.cpu().numpy(), eoff)
+    rows = np.repeat(np.arange(n), np.diff(eoff))
+    a = adj.cpu().numpy()
+    assert np.array_equal(a[np.lexsort((a, rows))], eadj[np.lexsort((eadj, rows))])
+    del off, adj, deg
+    expect = oracle_labels(g)
+    for route, kw, want in [("bfs+sv", {}, ccmi.R0_BFS_SV), ("heuristic", {"tau": 1e300}, ccmi.R0_BFS_SV),
+                            ("heuristic", {"tau": 1e-300}, ccmi.R1_SV)]:
+        say(f"[gpu] large-n {route} {kw}")
+        lab, st = ccmi.label(du, dv, n, route=route, stats=True, **kw)
+        assert st["route"] == want
+        assert_labels_equal(lab, expect, f"large-n/{route}/{kw}")
+
+
 def test_route_edge_cases():
     for u, v, n in [([], [], 5), ([2], [2], 3), ([0], [1], 2), ([3, 1], [1, 3], 4)]:
         u = np.array(u, np.int32)
