@@ -15,8 +15,9 @@
 //   D. one block per bucket counts the degrees of its 32768 vertices in LDS,
 //      writes deg[], folds the degree histograms (log bins, exact bins below
 //      4096, tail list, arg-max) and, when a CSR is wanted, turns the counts
-//      into offsets (LDS scan) and scatters the neighbour lists into the
-//      bucket's contiguous adjacency range.
+//      into offsets (LDS scan);
+//   S, F. (CSR only) the neighbour lists are placed in two steps whose
+//      writes stay in LDS-sized windows (see below).
 //
 // No global atomic touches a per-vertex counter, which matters on MI355X where
 // random device-scope atomics run far below the streaming rate.
@@ -380,11 +381,11 @@ __device__ __forceinline__ void count_lane(uint32_t* cnt, bool ok, int32_t x) {
 constexpr int kUnrollD = 4;
 
 __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
-    const uint16_t* __restrict__ loc, const int32_t* __restrict__ other, const unsigned long long* __restrict__ base,
-    int32_t n, int32_t* __restrict__ deg, int count_pairs, int want_hist, unsigned long long* __restrict__ hist64,
+    const uint16_t* __restrict__ loc, const unsigned long long* __restrict__ base, int32_t n,
+    int32_t* __restrict__ deg, int count_pairs, int want_hist, unsigned long long* __restrict__ hist64,
     unsigned long long* __restrict__ histx, int32_t* __restrict__ tail, int64_t tail_cap,
-    unsigned long long* __restrict__ tail_count, unsigned long long* __restrict__ argmax_key, int want_csr,
-    int64_t* __restrict__ off, int32_t* __restrict__ adj) {
+    unsigned long long* __restrict__ tail_count, unsigned long long* __restrict__ argmax_key, int want_off,
+    int64_t* __restrict__ off) {
     __shared__ uint32_t cnt[kBsz];
     __shared__ HistLds L;
     __shared__ uint32_t wsum[kBlockD / 64];
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     __syncthreads();
     const unsigned long long beg = base[k], end = base[k + 1];
     if (!count_pairs) {
-        // degrees already known (an earlier pass): only the CSR is built
+        // degrees already known (an earlier pass): only the offsets are wanted
         for (int j = threadIdx.x; j < nv; j += kBlockD) cnt[j] = (uint32_t)deg[x0 + j];
     }
     // every lane runs the same trip count so the wave-level aggregation can ballot
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     }
     __syncthreads();
     if (want_hist && count_pairs) hist_flush(L, best, hist64, histx, argmax_key, kBlockD);
-    if (!want_csr) return;
+    if (!want_off) return;
     __syncthreads();
     // exclusive scan of cnt[0..kBsz) in place: 32 entries per thread
     constexpr int per = kBsz / kBlockD;
@@ -450,24 +451,141 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     __syncthreads();
     for (int j = t; j < nv; j += kBlockD) off[x0 + j] = (int64_t)(beg + cnt[j]);
     if (x0 + nv == n && t == 0) off[n] = (int64_t)end;
-    __syncthreads();
-    for (unsigned long long i0 = beg; i0 < end; i0 += kBlockD) {
-        const unsigned long long i = i0 + t;
-        const bool ok = i < end;
-        const int32_t x = ok ? (int32_t)loc[i] : -1;
-        const int32_t y = ok ? other[i] : 0;
-        // lanes sharing the wave's first key reserve their slots with one atomic
-        const int first = __builtin_ctzll(ballot(ok) | (1ull << 63)) & 63;
-        const int32_t lead = __shfl(x, first);
-        const uint64_t same = ballot(ok && x == lead);
-        const uint32_t rank = lanes_below(same);
-        uint32_t basepos = 0;
-        if (ok && x == lead && rank == 0) basepos = atomicAdd(&cnt[lead], (uint32_t)__popcll(same));
-        const int leader = __builtin_ctzll(same | (1ull << 63)) & 63;
-        basepos = __shfl(basepos, leader);
-        if (ok) {
-            const uint32_t pos = (x == lead) ? basepos + rank : atomicAdd(&cnt[x], 1u);
-            adj[beg + pos] = y;
+}
+
+// ------------------------------------------------------------ CSR fill
+// The CSR's rows are filled in two steps, so that every write to adj[] lands
+// in a window small enough to assemble in LDS:
+//  S. one block per bucket regroups the bucket's entries by group of
+//     2^kGrpShift vertices into tmp arrays indexed like adj[] (a group's
+//     entries take exactly its rows' slots, [off[x_g], off[x_g + 256]));
+//  F. one block per run of groups places each group's entries into an LDS
+//     copy of the group's rows and writes the copy out contiguously (groups
+//     whose rows exceed the window write straight to adj[]).
+constexpr int kGrpShift = 8;
+constexpr int kGrpV = 1 << kGrpShift;            // vertices per group
+constexpr int kGroups = kBsz >> kGrpShift;       // groups per bucket
+constexpr int kGrpE = 4;                         // entries per thread per tile (S)
+constexpr int kFillThreads = 512;
+constexpr int kWin = 16384;                      // adjacency entries assembled in LDS (F)
+
+__global__ __launch_bounds__(kStageThreads) void csr_group_kernel(const uint16_t* __restrict__ loc,
+                                                                  const int32_t* __restrict__ other,
+                                                                  const unsigned long long* __restrict__ base,
+                                                                  const int64_t* __restrict__ off, int32_t n,
+                                                                  uint16_t* __restrict__ tloc,
+                                                                  int32_t* __restrict__ tother) {
+    __shared__ uint16_t sl[kStageThreads * kGrpE];
+    __shared__ int32_t so[kStageThreads * kGrpE];
+    __shared__ uint32_t cnt[kGroups + 1];
+    __shared__ unsigned long long cur[kGroups];
+    const int t = threadIdx.x;
+    const int k = blockIdx.x;
+    const int64_t x0 = (int64_t)k << kShift;
+    const unsigned long long beg = base[k], end = base[k + 1];
+    for (int g = t; g < kGroups; g += kStageThreads) {
+        const int64_t x = x0 + ((int64_t)g << kGrpShift);
+        cur[g] = x < n ? (unsigned long long)off[x] : end;
+    }
+    for (unsigned long long t0 = beg; t0 < end; t0 += (unsigned long long)kStageThreads * kGrpE) {
+        if (t <= kGroups) cnt[t] = 0;
+        __syncthreads();
+        uint16_t q[kGrpE];
+        int32_t o[kGrpE];
+        uint32_t rank[kGrpE];
+        bool ok[kGrpE];
+#pragma unroll
+        for (int j = 0; j < kGrpE; ++j) {
+            const unsigned long long i = t0 + t + (unsigned long long)j * kStageThreads;
+            ok[j] = i < end;
+            q[j] = ok[j] ? loc[i] : (uint16_t)0;
+            o[j] = ok[j] ? other[i] : 0;
+            rank[j] = ok[j] ? atomicAdd(&cnt[q[j] >> kGrpShift], 1u) : 0u;
+        }
+        __syncthreads();
+        if (t < 64) {   // exclusive scan of the kGroups (= 128) counts by one wave
+            const uint32_t c0 = cnt[2 * t], c1 = cnt[2 * t + 1], sm = c0 + c1;
+            uint32_t incl = sm;
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = __shfl_up(incl, d);
+                if (lane_id() >= d) incl += y;
+            }
+            cnt[2 * t] = incl - sm;
+            cnt[2 * t + 1] = incl - sm + c0;
+            if (t == 63) cnt[kGroups] = incl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kGrpE; ++j)
+            if (ok[j]) {
+                const uint32_t slot = cnt[q[j] >> kGrpShift] + rank[j];
+                sl[slot] = q[j];
+                so[slot] = o[j];
+            }
+        __syncthreads();
+        const uint32_t total = cnt[kGroups];
+        for (uint32_t i = t; i < total; i += kStageThreads) {
+            const int g = sl[i] >> kGrpShift;
+            const unsigned long long pos = cur[g] + (i - cnt[g]);
+            tloc[pos] = sl[i];
+            tother[pos] = so[i];
+        }
+        __syncthreads();
+        if (t < kGroups) cur[t] += cnt[t + 1] - cnt[t];
+        __syncthreads();
+    }
+}
+
+// Reserves the next slot of row xl for each lane; lanes of a wave that share
+// the wave's first row (a hub) take consecutive slots with one LDS atomic.
+__device__ __forceinline__ uint32_t row_slot(uint32_t* cur, bool ok, int32_t xl) {
+    const int first = __builtin_ctzll(ballot(ok) | (1ull << 63)) & 63;
+    const int32_t lead = __shfl(xl, first);
+    const uint64_t same = ballot(ok && xl == lead);
+    const uint32_t rank = lanes_below(same);
+    uint32_t basepos = 0;
+    if (ok && xl == lead && rank == 0) basepos = atomicAdd(&cur[lead], (uint32_t)__popcll(same));
+    basepos = __shfl(basepos, __builtin_ctzll(same | (1ull << 63)) & 63);
+    if (!ok) return 0;
+    return xl == lead ? basepos + rank : atomicAdd(&cur[xl], 1u);
+}
+
+__global__ __launch_bounds__(kFillThreads) void csr_fill_kernel(const uint16_t* __restrict__ tloc,
+                                                                const int32_t* __restrict__ tother,
+                                                                const int64_t* __restrict__ off, int32_t n,
+                                                                int64_t ngroups, int32_t gpb,
+                                                                int32_t* __restrict__ adj) {
+    __shared__ int32_t win[kWin];
+    __shared__ uint32_t cur[kGrpV];
+    __shared__ int64_t offs[kGrpV + 1];
+    const int t = threadIdx.x;
+    for (int64_t G = (int64_t)blockIdx.x * gpb; G < ngroups && G < (int64_t)(blockIdx.x + 1) * gpb; ++G) {
+        const int64_t xs = G << kGrpShift;
+        const int64_t xe = xs + kGrpV < n ? xs + kGrpV : n;
+        const int nv = (int)(xe - xs);
+        __syncthreads();   // the previous group is done with offs, cur and win
+        for (int j = t; j <= nv; j += kFillThreads) offs[j] = off[xs + j];
+        for (int j = t; j < kGrpV; j += kFillThreads) cur[j] = 0;
+        __syncthreads();
+        const int64_t a = offs[0], b = offs[nv];
+        if (b - a <= kWin) {
+            for (int64_t i0 = a; i0 < b; i0 += kFillThreads) {
+                const int64_t i = i0 + t;
+                const bool ok = i < b;
+                const int32_t xl = ok ? (int32_t)(tloc[i] & (kGrpV - 1)) : 0;
+                const uint32_t r = row_slot(cur, ok, xl);
+                if (ok) win[offs[xl] - a + r] = tother[i];
+            }
+            __syncthreads();
+            for (int64_t i = t; i < b - a; i += kFillThreads) adj[a + i] = win[i];
+        } else {
+            for (int64_t i0 = a; i0 < b; i0 += kFillThreads) {
+                const int64_t i = i0 + t;
+                const bool ok = i < b;
+                const int32_t xl = ok ? (int32_t)(tloc[i] & (kGrpV - 1)) : 0;
+                const uint32_t r = row_slot(cur, ok, xl);
+                if (ok) adj[offs[xl] + r] = tother[i];
+            }
         }
     }
 }
@@ -525,6 +643,20 @@ static hipError_t launch_scatter(const int32_t* u, const int32_t* v, int64_t m, 
     return hipGetLastError();
 }
 
+// steps S and F of the CSR fill (offsets already in off[])
+static hipError_t launch_csr_fill(int64_t m, int32_t n, const BucketPlan& p, const BucketBufs& w, const int64_t* off,
+                                  int32_t* adj, hipStream_t s) {
+    csr_group_kernel<<<p.B, kStageThreads, 0, s>>>(w.loc, w.other, w.base, off, n, w.tloc, w.tother);
+    const int64_t ngroups = ((int64_t)n + kGrpV - 1) >> kGrpShift;
+    // runs of groups per block: about one LDS window of entries each
+    const int64_t avg = ngroups > 0 ? (2 * m) / ngroups : 0;
+    int gpb = 1;
+    while (gpb < 64 && (int64_t)gpb * 2 * avg <= kWin) gpb *= 2;
+    const int64_t grid = (ngroups + gpb - 1) / gpb;
+    csr_fill_kernel<<<(unsigned)grid, kFillThreads, 0, s>>>(w.tloc, w.tother, off, n, ngroups, gpb, adj);
+    return hipGetLastError();
+}
+
 hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
                                       BucketBufs& w, int32_t* deg, int64_t* off, int32_t* adj, hipStream_t s) {
     if (!w.other_written) {
@@ -535,9 +667,10 @@ hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_
         if (e != hipSuccess) return e;
         w.other_written = true;
     }
-    bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, w.other, w.base, n, deg, 0, 0, nullptr, nullptr, nullptr, 0,
-                                                  nullptr, nullptr, 1, off, adj);
-    return hipGetLastError();
+    bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, w.base, n, deg, 0, 0, nullptr, nullptr, nullptr, 0, nullptr,
+                                                  nullptr, 1, off);
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_csr_fill(m, n, p, w, off, adj, s);
 }
 
 hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
@@ -552,9 +685,11 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
     hipError_t e = launch_scatter(u, v, m, n, p, w, want_csr != 0, s);
     if (e != hipSuccess) return e;
     w.other_written = want_csr != 0;
-    bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, w.other, w.base, n, deg, 1, want_hist, hist64, histx, tail,
-                                                  tail_cap, tail_count, argmax_key, want_csr, off, adj);
-    return hipGetLastError();
+    bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, w.base, n, deg, 1, want_hist, hist64, histx, tail, tail_cap,
+                                                  tail_count, argmax_key, want_csr, off);
+    e = hipGetLastError();
+    if (e != hipSuccess || !want_csr) return e;
+    return launch_csr_fill(m, n, p, w, off, adj, s);
 }
 
 hipError_t launch_degree_hist(const int32_t* deg, int32_t n, unsigned long long* hist64, unsigned long long* histx,

@@ -26,6 +26,8 @@ struct BucketBufs {
     int32_t* other;              // [2m] the other endpoint (CSR builds)
     uint32_t* loc32;             // [2m] first level when B > kStagedMaxB: id within the super-bucket
     int32_t* other32;            // [2m] its other ends (CSR builds)
+    uint16_t* tloc;              // [2m] CSR fill: entries regrouped by 256-vertex group
+    int32_t* tother;             // [2m]
     unsigned long long* err;     // range errors
     bool other_written = false;
 };

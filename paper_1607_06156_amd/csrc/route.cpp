@@ -28,6 +28,21 @@ static int sync_read(Call& c, void* host, const void* dev, size_t bytes) {
 }
 
 // ------------------------------------------------------------ prediction
+// WS_CURSOR holds, one after the other in time, the first level of the
+// two-level scatter (uint32 ids, + int32 other ends for a CSR) and the CSR
+// fill's regrouped entries (uint16 ids, int32 other ends).
+static size_t cursor_bytes(int64_t m, bool csr) {
+    return csr ? (size_t)2 * m * 8 : (size_t)2 * m * 4;
+}
+
+static void set_cursor_bufs(BucketBufs* w, void* po, int64_t m, bool csr) {
+    w->loc32 = (uint32_t*)po;
+    w->other32 = po && csr ? (int32_t*)((uint32_t*)po + 2 * m) : nullptr;
+    w->tloc = csr ? (uint16_t*)po : nullptr;
+    w->tother = po && csr ? (int32_t*)((char*)po + (((size_t)2 * m * sizeof(uint16_t) + 255) & ~(size_t)255))
+                          : nullptr;
+}
+
 int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     Workspace& ws = *c.ws;
     BucketPlan p;
@@ -40,9 +55,10 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     // WS_HIST: per-block bucket counts, then (8-byte aligned) totals, bases, error counter
     const size_t counts_bytes = ((size_t)p.nblk * p.B * sizeof(uint32_t) + 255) & ~(size_t)255;
     if ((rc = ws.get(WS_HIST, counts_bytes + (size_t)(2 * p.B + 2) * sizeof(unsigned long long), &pc))) return rc;
-    if (p.B > kStagedMaxB) {
-        // first level of the two-level scatter: 32-bit ids (+ other ends for a CSR)
-        if ((rc = ws.get(WS_CURSOR, (size_t)2 * m * (want_csr ? 8 : 4), &po))) return rc;
+    if (p.B > kStagedMaxB || want_csr) {
+        // the first level of the two-level scatter (32-bit ids, + other ends
+        // for a CSR) and, later, the CSR fill's regrouped entries share it
+        if ((rc = ws.get(WS_CURSOR, cursor_bytes(m, want_csr), &po))) return rc;
     } else {
         po = nullptr;
     }
@@ -57,8 +73,7 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     w.tot = (unsigned long long*)((char*)pc + counts_bytes);
     w.base = w.tot + p.B;
     w.err = w.base + p.B + 1;
-    w.loc32 = (uint32_t*)po;
-    w.other32 = po && want_csr ? (int32_t*)((uint32_t*)po + 2 * m) : nullptr;
+    set_cursor_bufs(&w, po, m, want_csr);
     w.loc = (uint16_t*)pp;
     w.other = (int32_t*)((char*)pp + loc_bytes);
     r->bufs = w;
@@ -260,12 +275,11 @@ int run_bfs_route(Call& c, DegreeResult& r) {
         if ((rc = ws.get(WS_ADJ, (size_t)2 * c.m * sizeof(int32_t), &padj))) return rc;
         r.off = (int64_t*)poff;
         r.adj = (int32_t*)padj;
-        if (!r.bufs.other_written && r.plan.B > kStagedMaxB) {
-            // the two-level scatter will run again with the other ends
+        if (!r.bufs.other_written) {
+            // the scatter runs again with the other ends, then the fill
             void* po;
-            if ((rc = ws.get(WS_CURSOR, (size_t)2 * c.m * 8, &po))) return rc;
-            r.bufs.loc32 = (uint32_t*)po;
-            r.bufs.other32 = (int32_t*)((uint32_t*)po + 2 * c.m);
+            if ((rc = ws.get(WS_CURSOR, cursor_bytes(c.m, true), &po))) return rc;
+            set_cursor_bufs(&r.bufs, po, c.m, true);
         }
         int k0 = c.kbeg();
         hipError_t e = launch_bucket_csr_from_deg(c.u, c.v, c.m, c.n, r.plan, r.bufs, r.deg, r.off, r.adj, c.stream);

@@ -14,6 +14,9 @@ power-law component-forest generator (a family the router never saw), timed
 end to end with the router and with the degree heuristic.
 
     python -m paper_1607_06156_amd.router_train --n-train 3000 --out weights.txt
+
+Large datasets can be built in pieces (--start, --dataset-out, --build-only)
+and merged when training (--dataset-in).
 """
 from __future__ import annotations
 
@@ -76,13 +79,18 @@ def time_route(u, v, n, route, reps=3):
     return float(np.median(ts))
 
 
-def build_dataset(count, seed0, lg_lo, lg_hi, families, log=None):
-    rng = np.random.default_rng(seed0)
+def draw(seed0, i, lg_lo, lg_hi):
+    """Scale and mean degree of graph i (a function of i alone, so datasets
+    built in separate runs over disjoint index ranges concatenate)."""
+    rng = np.random.default_rng([seed0, i])
+    return float(rng.uniform(lg_lo, lg_hi)), float(rng.uniform(2, 32))
+
+
+def build_dataset(count, seed0, lg_lo, lg_hi, families, log=None, start=0):
     X, T, meta = [], [], []
-    for i in range(count):
+    for i in range(start, start + count):
         fam = families[i % len(families)]
-        lg = float(rng.uniform(lg_lo, lg_hi))
-        deg = float(rng.uniform(2, 32))
+        lg, deg = draw(seed0, i, lg_lo, lg_hi)
         g = make_graph(fam, lg, deg, seed0 + i)
         if g.m == 0:
             continue
@@ -145,13 +153,11 @@ def accuracy(w, X, y):
 def evaluate(w, count, seed0, lg_lo, lg_hi, log=None):
     """End-to-end time with the router vs the degree heuristic on held-out graphs."""
     ccmi.router_set(w)
-    rng = np.random.default_rng(seed0)
     fams = FAMILIES + ["plcomp"]
     rows = []
     for i in range(count):
         fam = fams[i % len(fams)]
-        lg = float(rng.uniform(lg_lo, lg_hi))
-        deg = float(rng.uniform(2, 32))
+        lg, deg = draw(seed0, i, lg_lo, lg_hi)
         g = make_graph(fam, lg, deg, seed0 + i)
         if g.m == 0:
             continue
@@ -164,6 +170,9 @@ def evaluate(w, count, seed0, lg_lo, lg_hi, log=None):
         best = min(time_route(u, v, g.n, r) for r in ("bfs+sv", "sv", "sv-theta"))
         rows.append({"family": fam, "n": g.n, "m": g.m, "router_s": tr, "heuristic_s": th, "best_forced_s": best,
                      "router_route": st_r["route_name"], "heuristic_route": st_h["route_name"]})
+        if log and (i % 100 == 0):
+            log(f"[router] eval {i}/{count} {fam} n={g.n} m={g.m} router {tr * 1e3:.3f} ms "
+                f"heuristic {th * 1e3:.3f} ms")
     ccmi.router_set(None)
     out = {"graphs": len(rows)}
     for key in ["router_s", "heuristic_s", "best_forced_s"]:
@@ -197,13 +206,29 @@ def main():
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--out", default="router_weights.txt")
     ap.add_argument("--report", default="router_report.json")
+    ap.add_argument("--start", type=int, default=0, help="index of the first training graph to build")
+    ap.add_argument("--dataset-in", action="append", default=[], help="earlier dataset (.npz) to prepend")
+    ap.add_argument("--dataset-out", default=None, help="save the dataset built here (.npz)")
+    ap.add_argument("--build-only", action="store_true", help="build (and save) the dataset, do not train")
     args = ap.parse_args()
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
     t0 = time.time()
-    X, T, meta = build_dataset(args.n_train, 10_000_000, args.lg_lo, args.lg_hi, FAMILIES, log)
+    X, T, meta = build_dataset(args.n_train, 10_000_000, args.lg_lo, args.lg_hi, FAMILIES, log, start=args.start)
+    if args.dataset_out:
+        np.savez(args.dataset_out, X=X, T=T, n=np.array([r["n"] for r in meta], np.int64),
+                 m=np.array([r["m"] for r in meta], np.int64),
+                 family=np.array([FAMILIES.index(r["family"]) for r in meta], np.int8))
+        log(f"[router] saved {len(T)} graphs to {args.dataset_out}")
+    if args.build_only:
+        return
+    for path in args.dataset_in:
+        d = np.load(path)
+        X = np.concatenate([d["X"], X]) if len(X) else d["X"]
+        T = np.concatenate([d["T"], T]) if len(T) else d["T"]
+        log(f"[router] loaded {len(d['T'])} graphs from {path}")
     y = np.argmin(T, axis=1)
     log(f"[router] dataset {len(y)} graphs in {time.time() - t0:.0f}s; label counts {np.bincount(y, minlength=3)}")
     ntr = int(0.9 * len(y))
@@ -215,7 +240,8 @@ def main():
     regret = float(np.sum(Tv[np.arange(len(pred)), pred]) / np.sum(Tv.min(axis=1)))
     log(f"[router] train acc {acc_tr:.3f} val acc {acc_va:.3f} val time / best {regret:.4f}")
     note = (f"trained on {ntr} graphs (families {', '.join(FAMILIES)}, log2 n in [{args.lg_lo}, {args.lg_hi}], "
-            f"seeds 1e7+i), labels = fastest measured route; train acc {acc_tr:.3f}, val acc {acc_va:.3f}")
+            f"seeds 1e7+i), labels = fastest measured route; train acc {acc_tr:.3f}, val acc {acc_va:.3f}; "
+            f"held-out {len(y) - ntr} graphs")
     save(w, args.out, note)
     rep, rows = evaluate(w, args.n_eval, 20_000_000, args.lg_lo, args.lg_hi, log)
     rep.update({"train_graphs": ntr, "val_acc": acc_va, "train_acc": acc_tr, "val_time_over_best": regret,

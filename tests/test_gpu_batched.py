@@ -105,3 +105,19 @@ def test_repeatable_and_matches_single_calls():
                          torch.from_numpy(np.ascontiguousarray(sub.v)).cuda(), sub.n, route="sv")
         a, c = int(b.vert_off[g]), int(b.vert_off[g + 1])
         assert torch.equal(lab, first[a:c])
+
+
+def test_dense_and_deep_graphs():
+    """Edge-heavy graphs (2m/n > 8, so the first pass runs in 8 pieces with a
+    flatten after each) next to long permuted paths (deep trees)."""
+    graphs = []
+    for s in range(6):
+        g = gen.rmat(13, 16, seed=40 + s)
+        graphs.append((g.u, g.v, g.n))
+        n = 20_000 + 997 * s
+        pi = gen.permutation(n, seed=60 + s)
+        graphs.append((pi[:-1], pi[1:], n))
+    b = _manual(graphs)
+    exp = expected(b)
+    for kw in [{}, {"max_link": 1}, {"max_link": 4}, {"tile_edges": 1}]:
+        assert np.array_equal(run_batch(b, **kw).cpu().numpy(), exp), kw
