@@ -136,6 +136,9 @@ int choose_nseg(int64_t m) {
 // than vertices the finds of late edges walk long chains.  Cutting the first
 // pass into chunks with a full pointer-jumping shortcut after each keeps the
 // trees flat; the shortcut costs O(n), so the chunk count follows m / n.
+// hooked roots are pointer-jumped after a pass only if at most this many per survivor
+constexpr int64_t kLazyJump = 8;
+
 int pass0_chunks(int64_t m, int32_t n) {
     if (n <= 0) return 1;
     int64_t k = m / (2 * (int64_t)n);
@@ -234,11 +237,8 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
             rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)m_in);
         }
-        int k1 = c.kbeg();
-        e = launch_sv_shortcut(c.parent, (const int32_t*)phook, hooked_count, out.count, cap, nseg, totals,
-                               c.stream);
-        if (e != hipSuccess) return hip_fail(e, "sv_shortcut launch");
-        int rec_sc = c.kend(CC_K_SV_SHORTCUT, k1, 0.0);
+        e = launch_sv_totals(hooked_count, out.count, nseg, totals, c.stream);
+        if (e != hipSuccess) return hip_fail(e, "sv_totals launch");
         e = hipMemcpyAsync(htot, totals, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(totals)");
         e = hipStreamSynchronize(c.stream);
@@ -246,6 +246,18 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         if (htot[2]) return fail(CC_ERANGE, "%llu edge endpoints outside [0, n)", (unsigned long long)htot[2]);
         const int64_t kept = (int64_t)htot[0];
         const int64_t hooks = (int64_t)htot[1];
+        // Shortcut: point the roots hooked in this pass at their roots, unless
+        // nothing survives or they far outnumber the survivors (typically after
+        // the first pass, when nearly every vertex was hooked): then the few
+        // survivors' finds walk the extra links, and the final labelling
+        // flattens everything once.
+        const bool jump = kept > 0 && hooks <= kLazyJump * kept;
+        if (jump) {
+            int k1 = c.kbeg();
+            e = launch_sv_shortcut(c.parent, (const int32_t*)phook, hooked_count, cap, nseg, c.stream);
+            if (e != hipSuccess) return hip_fail(e, "sv_shortcut launch");
+            c.kend(CC_K_SV_SHORTCUT, k1, 12.0 * hooks);
+        }
         if (c.stats) {
             if (c.stats->sv_passes < 64) c.stats->active_edges[c.stats->sv_passes] = m_in;
             c.stats->sv_passes++;
@@ -253,9 +265,8 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             // edges read (8 B) + two 4 B gathers + one 8 B atomic per unfinished edge
             // + survivors written (8 B); shortcut: read, gather, write per hooked root
             const double pass_bytes = 16.0 * m_in + 8.0 * kept + (write ? 8.0 * kept : 0.0);
-            c.bytes += pass_bytes + 12.0 * hooks + flat_bytes;
+            c.bytes += pass_bytes + (jump ? 12.0 * hooks : 0.0) + flat_bytes;
             c.kadd(rec_pass, 8.0 * kept + (write ? 8.0 * kept : 0.0));
-            c.kbytes(rec_sc, 12.0 * hooks);
         }
         ++pass;
         if (kept == 0) break;

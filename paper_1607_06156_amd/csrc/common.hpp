@@ -92,11 +92,12 @@ hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int
 // later passes over a segmented list
 hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int max_link, int32_t* hooked,
                               uint32_t* hooked_count, unsigned long long* totals, hipStream_t s);
-// pointer-jumps the hooked roots of each segment; block 0 also writes
-// totals[0] = sum(kept_count), totals[1] = sum(hooked_count)
-hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count,
-                              const uint32_t* kept_count, int64_t cap, int32_t nseg, unsigned long long* totals,
-                              hipStream_t s);
+// pointer-jumps the hooked roots of each segment (no hook may run concurrently)
+hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count, int64_t cap,
+                              int32_t nseg, hipStream_t s);
+// totals[0] = sum(kept_count), totals[1] = sum(hooked_count) over nseg segments
+hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg,
+                            unsigned long long* totals, hipStream_t s);
 // parent[x] = root(x) for every x (no hook may run concurrently)
 hipError_t launch_sv_finalize(int32_t* parent, int32_t n, hipStream_t s);
 

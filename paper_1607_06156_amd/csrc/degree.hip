@@ -466,8 +466,9 @@ constexpr int kGrpShift = 8;
 constexpr int kGrpV = 1 << kGrpShift;            // vertices per group
 constexpr int kGroups = kBsz >> kGrpShift;       // groups per bucket
 constexpr int kGrpE = 4;                         // entries per thread per tile (S)
-constexpr int kFillThreads = 512;
+constexpr int kFillThreads = 1024;
 constexpr int kWin = 16384;                      // adjacency entries assembled in LDS (F)
+constexpr int kFillU = 4;                        // entries per thread per step (F)
 
 __global__ __launch_bounds__(kStageThreads) void csr_group_kernel(const uint16_t* __restrict__ loc,
                                                                   const int32_t* __restrict__ other,
@@ -475,11 +476,15 @@ __global__ __launch_bounds__(kStageThreads) void csr_group_kernel(const uint16_t
                                                                   const int64_t* __restrict__ off, int32_t n,
                                                                   uint16_t* __restrict__ tloc,
                                                                   int32_t* __restrict__ tother) {
+    constexpr int kW = kStageThreads / 64;   // waves
     __shared__ uint16_t sl[kStageThreads * kGrpE];
     __shared__ int32_t so[kStageThreads * kGrpE];
-    __shared__ uint32_t cnt[kGroups + 1];
+    // per-wave counts, group-major ([g][w]), turned into slot offsets by one scan
+    __shared__ uint32_t wc[kGroups * kW];
+    __shared__ uint32_t gstart[kGroups + 1];
+    __shared__ uint32_t wsum[kStageThreads / 64];
     __shared__ unsigned long long cur[kGroups];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, w = t >> 6;
     const int k = blockIdx.x;
     const int64_t x0 = (int64_t)k << kShift;
     const unsigned long long beg = base[k], end = base[k + 1];
@@ -488,7 +493,7 @@ __global__ __launch_bounds__(kStageThreads) void csr_group_kernel(const uint16_t
         cur[g] = x < n ? (unsigned long long)off[x] : end;
     }
     for (unsigned long long t0 = beg; t0 < end; t0 += (unsigned long long)kStageThreads * kGrpE) {
-        if (t <= kGroups) cnt[t] = 0;
+        for (int i = t; i < kGroups * kW; i += kStageThreads) wc[i] = 0;
         __syncthreads();
         uint16_t q[kGrpE];
         int32_t o[kGrpE];
@@ -500,38 +505,48 @@ __global__ __launch_bounds__(kStageThreads) void csr_group_kernel(const uint16_t
             ok[j] = i < end;
             q[j] = ok[j] ? loc[i] : (uint16_t)0;
             o[j] = ok[j] ? other[i] : 0;
-            rank[j] = ok[j] ? atomicAdd(&cnt[q[j] >> kGrpShift], 1u) : 0u;
+            rank[j] = ok[j] ? atomicAdd(&wc[(q[j] >> kGrpShift) * kW + w], 1u) : 0u;
         }
         __syncthreads();
-        if (t < 64) {   // exclusive scan of the kGroups (= 128) counts by one wave
-            const uint32_t c0 = cnt[2 * t], c1 = cnt[2 * t + 1], sm = c0 + c1;
+        // exclusive scan of wc[0 .. kGroups * kW) (2 entries per thread)
+        {
+            const uint32_t c0 = wc[2 * t], c1 = wc[2 * t + 1], sm = c0 + c1;
             uint32_t incl = sm;
             for (int d = 1; d < 64; d <<= 1) {
                 const uint32_t y = __shfl_up(incl, d);
                 if (lane_id() >= d) incl += y;
             }
-            cnt[2 * t] = incl - sm;
-            cnt[2 * t + 1] = incl - sm + c0;
-            if (t == 63) cnt[kGroups] = incl;
+            if (lane_id() == 63) wsum[w] = incl;
+            __syncthreads();
+            if (t == 0) {
+                uint32_t acc = 0;
+                for (int i = 0; i < kStageThreads / 64; ++i) { const uint32_t c = wsum[i]; wsum[i] = acc; acc += c; }
+                gstart[kGroups] = acc;
+            }
+            __syncthreads();
+            const uint32_t ex = wsum[w] + incl - sm;
+            wc[2 * t] = ex;
+            wc[2 * t + 1] = ex + c0;
         }
         __syncthreads();
+        if (t < kGroups) gstart[t] = wc[t * kW];
 #pragma unroll
         for (int j = 0; j < kGrpE; ++j)
             if (ok[j]) {
-                const uint32_t slot = cnt[q[j] >> kGrpShift] + rank[j];
+                const uint32_t slot = wc[(q[j] >> kGrpShift) * kW + w] + rank[j];
                 sl[slot] = q[j];
                 so[slot] = o[j];
             }
         __syncthreads();
-        const uint32_t total = cnt[kGroups];
+        const uint32_t total = gstart[kGroups];
         for (uint32_t i = t; i < total; i += kStageThreads) {
             const int g = sl[i] >> kGrpShift;
-            const unsigned long long pos = cur[g] + (i - cnt[g]);
+            const unsigned long long pos = cur[g] + (i - gstart[g]);
             tloc[pos] = sl[i];
             tother[pos] = so[i];
         }
         __syncthreads();
-        if (t < kGroups) cur[t] += cnt[t + 1] - cnt[t];
+        if (t < kGroups) cur[t] += gstart[t + 1] - gstart[t];
         __syncthreads();
     }
 }
@@ -568,24 +583,30 @@ __global__ __launch_bounds__(kFillThreads) void csr_fill_kernel(const uint16_t* 
         for (int j = t; j < kGrpV; j += kFillThreads) cur[j] = 0;
         __syncthreads();
         const int64_t a = offs[0], b = offs[nv];
-        if (b - a <= kWin) {
-            for (int64_t i0 = a; i0 < b; i0 += kFillThreads) {
-                const int64_t i = i0 + t;
-                const bool ok = i < b;
-                const int32_t xl = ok ? (int32_t)(tloc[i] & (kGrpV - 1)) : 0;
-                const uint32_t r = row_slot(cur, ok, xl);
-                if (ok) win[offs[xl] - a + r] = tother[i];
+        const bool staged = b - a <= kWin;   // block-uniform
+        // kFillU entries per thread per step, loaded before any is placed
+        for (int64_t i0 = a; i0 < b; i0 += (int64_t)kFillThreads * kFillU) {
+            int32_t xl[kFillU], y[kFillU];
+            bool ok[kFillU];
+#pragma unroll
+            for (int u = 0; u < kFillU; ++u) {
+                const int64_t i = i0 + t + (int64_t)u * kFillThreads;
+                ok[u] = i < b;
+                xl[u] = ok[u] ? (int32_t)(tloc[i] & (kGrpV - 1)) : 0;
+                y[u] = ok[u] ? tother[i] : 0;
             }
+#pragma unroll
+            for (int u = 0; u < kFillU; ++u) {
+                const uint32_t r = row_slot(cur, ok[u], xl[u]);
+                if (ok[u]) {
+                    if (staged) win[offs[xl[u]] - a + r] = y[u];
+                    else adj[offs[xl[u]] + r] = y[u];
+                }
+            }
+        }
+        if (staged) {
             __syncthreads();
             for (int64_t i = t; i < b - a; i += kFillThreads) adj[a + i] = win[i];
-        } else {
-            for (int64_t i0 = a; i0 < b; i0 += kFillThreads) {
-                const int64_t i = i0 + t;
-                const bool ok = i < b;
-                const int32_t xl = ok ? (int32_t)(tloc[i] & (kGrpV - 1)) : 0;
-                const uint32_t r = row_slot(cur, ok, xl);
-                if (ok) adj[offs[xl] + r] = tother[i];
-            }
         }
     }
 }

@@ -11,7 +11,8 @@
 //     d_min) at every observed degree and just before the next one, and the
 //     block reduces the largest gap to the empirical CDF.
 // The Hurwitz zeta function and its first two s-derivatives come from the
-// Euler-Maclaurin formula (12 direct terms, 7 Bernoulli corrections), in fp64.
+// Euler-Maclaurin formula (direct terms up to argument 20, 7 Bernoulli
+// corrections), in fp64.
 #include <math.h>
 
 #include "common.hpp"
@@ -25,31 +26,41 @@ struct Z3 {
     double z, d1, d2;
 };
 
+// Euler-Maclaurin for zeta(s, q): the terms (q + k)^-s are summed directly
+// until the argument reaches a = q + N >= 20, and the tail from a is
+// a^(1-s)/(s-1) + a^-s/2 + sum_j B_2j/(2j)! s(s+1)..(s+2j-2) a^(-s-2j+1),
+// j = 1..7.  At a >= 20 the first omitted term is below 2e-14 of the sum for
+// s <= 10.  The tail's powers of a come from one exp and multiplications by
+// 1/a^2, so a large argument (a degree >= 20) costs one log and one exp.
+__device__ __forceinline__ int direct_terms(double q) { return q < 20.0 ? (int)ceil(20.0 - q) : 0; }
+
 // zeta(s, q) and its first two derivatives in s
 __device__ Z3 hurwitz3(double s, double q) {
     const double C[7] = {1.0 / 6 / 2, -1.0 / 30 / 24, 1.0 / 42 / 720, -1.0 / 30 / 40320, 5.0 / 66 / 3628800,
                          -691.0 / 2730 / 479001600, 7.0 / 6 / 87178291200.0};
     double z = 0, d1 = 0, d2 = 0;
-    for (int k = 0; k < 12; ++k) {
+    const int N = direct_terms(q);
+    for (int k = 0; k < N; ++k) {
         double L = log(q + k);
         double t = exp(-s * L);
         z += t;
         d1 -= L * t;
         d2 += L * L * t;
     }
-    const double a = q + 12.0, La = log(a);
+    const double a = q + N, La = log(a);
     const double r = 1.0 / (s - 1.0);
-    const double p1 = exp((1.0 - s) * La);
+    const double p0 = exp(-s * La);   // a^-s
+    const double p1 = a * p0;         // a^(1-s)
     z += p1 * r;
     d1 += p1 * (-La * r - r * r);
     d2 += p1 * (La * La * r + 2.0 * La * r * r + 2.0 * r * r * r);
-    const double p0 = exp(-s * La);
     z += 0.5 * p0;
     d1 -= 0.5 * La * p0;
     d2 += 0.5 * La * La * p0;
+    const double ia2 = 1.0 / (a * a);
+    double P = p0 / a;                // a^(-s-2j+1), j = 1
     double R = s, R1 = 1.0, R2 = 0.0;
     for (int j = 1; j <= 7; ++j) {
-        const double P = exp((-s - 2.0 * j + 1.0) * La);
         const double c = C[j - 1];
         z += c * R * P;
         d1 += c * P * (R1 - La * R);
@@ -60,6 +71,7 @@ __device__ Z3 hurwitz3(double s, double q) {
         R = R * f1 * f2;
         R1 = nR1;
         R2 = nR2;
+        P *= ia2;
     }
     return Z3{z, d1, d2};
 }
@@ -68,13 +80,17 @@ __device__ double hurwitz(double s, double q) {
     const double C[7] = {1.0 / 6 / 2, -1.0 / 30 / 24, 1.0 / 42 / 720, -1.0 / 30 / 40320, 5.0 / 66 / 3628800,
                          -691.0 / 2730 / 479001600, 7.0 / 6 / 87178291200.0};
     double z = 0;
-    for (int k = 0; k < 12; ++k) z += exp(-s * log(q + k));
-    const double a = q + 12.0, La = log(a);
-    z += exp((1.0 - s) * La) / (s - 1.0) + 0.5 * exp(-s * La);
-    double R = s;
+    const int N = direct_terms(q);
+    for (int k = 0; k < N; ++k) z += exp(-s * log(q + k));
+    const double a = q + N, La = log(a);
+    const double p0 = exp(-s * La);
+    z += a * p0 / (s - 1.0) + 0.5 * p0;
+    const double ia2 = 1.0 / (a * a);
+    double P = p0 / a, R = s;
     for (int j = 1; j <= 7; ++j) {
-        z += C[j - 1] * R * exp((-s - 2.0 * j + 1.0) * La);
+        z += C[j - 1] * R * P;
         R *= (s + 2.0 * j - 1.0) * (s + 2.0 * j);
+        P *= ia2;
     }
     return z;
 }

@@ -91,12 +91,10 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
     }
 }
 
-// Pointer jumping for the roots hooked in the last pass; block 0 also reduces
-// the per-block kept / hook counts into totals[0], totals[1].
+// Pointer jumping for the roots hooked in the last pass: each is pointed
+// straight at its current root.  Runs between passes (no hook in flight).
 __global__ __launch_bounds__(kBlock) void sv_shortcut_kernel(int32_t* parent, const int32_t* __restrict__ hooked,
-                                                             const uint32_t* __restrict__ hooked_count,
-                                                             const uint32_t* __restrict__ kept_count, int64_t cap,
-                                                             int32_t nseg, unsigned long long* __restrict__ totals) {
+                                                             const uint32_t* __restrict__ hooked_count, int64_t cap) {
     const int b = blockIdx.x;
     const uint32_t cnt = hooked_count[b];
     const int32_t* h = hooked + (int64_t)b * cap;
@@ -105,28 +103,33 @@ __global__ __launch_bounds__(kBlock) void sv_shortcut_kernel(int32_t* parent, co
         int32_t r = find_root(parent, x);
         parent[x] = r;
     }
-    if (b == 0) {
-        __shared__ unsigned long long red[2][kWaves];
-        unsigned long long sk = 0, sh = 0;
-        for (int i = threadIdx.x; i < nseg; i += kBlock) {
-            sk += kept_count[i];
-            sh += hooked_count[i];
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            sk += __shfl_xor(sk, off);
-            sh += __shfl_xor(sh, off);
-        }
-        if (lane_id() == 0) {
-            red[0][threadIdx.x >> 6] = sk;
-            red[1][threadIdx.x >> 6] = sh;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long a = 0, c = 0;
-            for (int w = 0; w < kWaves; ++w) { a += red[0][w]; c += red[1][w]; }
-            totals[0] = a;
-            totals[1] = c;
-        }
+}
+
+// One block: totals[0] = sum of the per-segment survivor counts, totals[1] =
+// sum of the per-segment hook counts.
+__global__ __launch_bounds__(kBlock) void sv_totals_kernel(const uint32_t* __restrict__ hooked_count,
+                                                           const uint32_t* __restrict__ kept_count, int32_t nseg,
+                                                           unsigned long long* __restrict__ totals) {
+    __shared__ unsigned long long red[2][kWaves];
+    unsigned long long sk = 0, sh = 0;
+    for (int i = threadIdx.x; i < nseg; i += kBlock) {
+        sk += kept_count[i];
+        sh += hooked_count[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sk += __shfl_xor(sk, off);
+        sh += __shfl_xor(sh, off);
+    }
+    if (lane_id() == 0) {
+        red[0][threadIdx.x >> 6] = sk;
+        red[1][threadIdx.x >> 6] = sh;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, c = 0;
+        for (int w = 0; w < kWaves; ++w) { a += red[0][w]; c += red[1][w]; }
+        totals[0] = a;
+        totals[1] = c;
     }
 }
 
@@ -175,10 +178,15 @@ hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int writ
     return hipGetLastError();
 }
 
-hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count,
-                              const uint32_t* kept_count, int64_t cap, int32_t nseg, unsigned long long* totals,
-                              hipStream_t s) {
-    sv_shortcut_kernel<<<nseg, kBlock, 0, s>>>(parent, hooked, hooked_count, kept_count, cap, nseg, totals);
+hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count, int64_t cap,
+                              int32_t nseg, hipStream_t s) {
+    sv_shortcut_kernel<<<nseg, kBlock, 0, s>>>(parent, hooked, hooked_count, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg,
+                            unsigned long long* totals, hipStream_t s) {
+    sv_totals_kernel<<<1, kBlock, 0, s>>>(hooked_count, kept_count, nseg, totals);
     return hipGetLastError();
 }
 
