@@ -5,7 +5,7 @@ decision, then BFS + filter and/or the SV passes) over the synthetic
 workload, inputs already resident in HBM.  Prints one JSON line on stdout;
 progress goes to stderr.
 
-    python bench.py [--steps K] [--warmup W] [--config rmat24] [--route heuristic]
+    python bench.py [--steps K] [--warmup W] [--config rmat24] [--route heuristic|router|sv|...]
 """
 from __future__ import annotations
 
@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--route", default="heuristic")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-compare", action="store_true", help="skip the forced-route comparison")
+    ap.add_argument("--router-weights", default=os.path.join(ROOT, "paper_1607_06156_amd", "router_weights.txt"),
+                    help="weights loaded for --route router / auto")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
     args = ap.parse_args()
@@ -97,6 +99,8 @@ def main():
 
     if args.config.startswith("batch"):
         return bench_batched(args)
+    if args.route in ("router", "auto"):
+        ccmi.router_load(args.router_weights)
 
     t = time.time()
     g = gen.workload(args.config)
@@ -162,7 +166,8 @@ def main():
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOAD_DESC.get(args.config, args.config)}", "n": g.n, "m": g.m,
-                   "route_requested": args.route, "route_taken": st["route_name"]},
+                   "route_requested": args.route, "route_taken": st["route_name"],
+                   "router_weights": os.path.relpath(args.router_weights, ROOT) if ccmi.router_loaded() else None},
         "labels_exact_vs_oracle": exact,
         "algorithmic_GBps_whole_call": round(whole_gbs, 2),
         "roofline": roofline,
@@ -210,6 +215,13 @@ def bench_batched(args):
     log(f"[bench] batched: {sec * 1e3:.2f} ms/step {value / 1e9:.2f} G edges/s passes={st['passes']} "
         f"blocks={st['blocks']} max_link={st['max_link']} pass_ms={st['pass_ms']}")
     kernel_ms = float(np.mean([s["ms_total"] for s in sts]))
+    # the persistent kernel is the only kernel: algorithmic bytes of one launch
+    # (a lower bound: later passes, ~1 % of the edges, are not counted)
+    kbytes = 32.0 * m + 16.0 * n
+    achieved = kbytes / (kernel_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "batched_kernel", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("batched", args.config),
+                "avg_launch_ms": round(kernel_ms, 4), "bytes_per_launch": kbytes}
     # per-graph launches of the same SV kernels
     loop = None
     if not args.no_compare:
@@ -263,6 +275,7 @@ def bench_batched(args):
                    "blocks": st["blocks"], "tile_edges": st["tile_edges"]},
         "labels_exact_vs_oracle_sampled": exact,
         "kernel_ms": round(kernel_ms, 3),
+        "roofline": roofline,
         "passes": st["passes"],
         "pass_ms": st["pass_ms"],
         "max_link": st["max_link"],

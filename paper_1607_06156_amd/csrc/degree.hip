@@ -42,6 +42,17 @@ __device__ __forceinline__ unsigned long long atomic_max_u64_agent(unsigned long
 
 // ------------------------------------------------------------------ pass A
 // counts[k * nblk + b] = endpoints of block b's edge chunk in bucket k
+__device__ __forceinline__ void count_edge(uint32_t* h, int32_t a, int32_t c, int32_t n, uint32_t& bad) {
+    if ((uint32_t)a >= (uint32_t)n || (uint32_t)c >= (uint32_t)n) {
+        ++bad;
+        return;
+    }
+    atomicAdd(&h[a >> kShift], 1u);
+    atomicAdd(&h[c >> kShift], 1u);
+}
+
+// VEC: u and v are 16-byte aligned, so the chunk's middle is read as int4
+template <bool VEC>
 __global__ __launch_bounds__(kBlock) void bucket_count_kernel(const int32_t* __restrict__ u,
                                                               const int32_t* __restrict__ v, int64_t m, int32_t n,
                                                               int64_t chunk, int32_t B, uint32_t* __restrict__ counts,
@@ -53,14 +64,22 @@ __global__ __launch_bounds__(kBlock) void bucket_count_kernel(const int32_t* __r
     int64_t end = beg + chunk;
     if (end > m) end = m;
     uint32_t bad = 0;
-    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-        int32_t a = u[i], c = v[i];
-        if ((uint32_t)a >= (uint32_t)n || (uint32_t)c >= (uint32_t)n) {
-            ++bad;
-            continue;
+    int64_t a4 = VEC ? (beg + 3) & ~(int64_t)3 : end;
+    if (a4 > end) a4 = end;
+    int64_t e4 = VEC ? end & ~(int64_t)3 : end;
+    if (e4 < a4) e4 = a4;
+    for (int64_t i = beg + threadIdx.x; i < a4; i += kBlock) count_edge(h, u[i], v[i], n, bad);
+    for (int64_t i = e4 + threadIdx.x; i < end; i += kBlock) count_edge(h, u[i], v[i], n, bad);
+    if (VEC) {
+        const int4* u4 = (const int4*)u;
+        const int4* v4 = (const int4*)v;
+        for (int64_t j = (a4 >> 2) + threadIdx.x; j < (e4 >> 2); j += kBlock) {
+            const int4 x = u4[j], y = v4[j];
+            count_edge(h, x.x, y.x, n, bad);
+            count_edge(h, x.y, y.y, n, bad);
+            count_edge(h, x.z, y.z, n, bad);
+            count_edge(h, x.w, y.w, n, bad);
         }
-        atomicAdd(&h[a >> kShift], 1u);
-        atomicAdd(&h[c >> kShift], 1u);
     }
     __syncthreads();
     const int nblk = gridDim.x;
@@ -142,18 +161,28 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const unsigned long l
 constexpr int kStageThreads = 1024;
 constexpr int kSub = 8;
 constexpr int kSuperShift = kShift + 3;
+// Tile sizes (measured on MI355X).  Ids alone (4 bytes of LDS per entry):
+// two blocks per CU, one edge chunk each.  With the other ends (8 bytes per
+// entry, CSR builds) one block per CU walks kChunks consecutive edge chunks
+// -- their runs are consecutive in the prefix layout, so the cursors simply
+// continue -- with a tile twice as long as two blocks could stage, which
+// makes the runs per bucket longer (2.7 ms instead of 3.1 ms on R-MAT scale
+// 24; the same change made the ids-only scatter slower, 1.5 ms against 1.3).
 template <bool OTHER>
 struct StageCfg {
-    static constexpr int kEdges = OTHER ? 3 : 5;   // edges per thread per tile (2 blocks/CU: LDS, VGPRs)
+    static constexpr int kEdges = OTHER ? 6 : 5;   // edges per thread per tile
+    static constexpr int kWaves = OTHER ? 4 : 8;   // waves per SIMD (LDS, VGPRs)
+    static constexpr int kChunks = OTHER ? 4 : 1;  // edge chunks per block
     static constexpr int kSlots = kStageThreads * kEdges * 2;
 };
 
 template <bool OTHER, bool SUPER>
-__global__ __launch_bounds__(kStageThreads, 8) void bucket_scatter_staged_kernel(
+__global__ __launch_bounds__(kStageThreads, StageCfg<OTHER>::kWaves) void bucket_scatter_staged_kernel(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m, int32_t n, int64_t chunk, int32_t B,
-    const uint32_t* __restrict__ prefix, const unsigned long long* __restrict__ base, uint16_t* __restrict__ loc,
-    uint32_t* __restrict__ loc32, int32_t* __restrict__ other) {
+    int32_t nblk, const uint32_t* __restrict__ prefix, const unsigned long long* __restrict__ base,
+    uint16_t* __restrict__ loc, uint32_t* __restrict__ loc32, int32_t* __restrict__ other) {
     constexpr int E = StageCfg<OTHER>::kEdges;
+    constexpr int G = StageCfg<OTHER>::kChunks;
     constexpr int kSh = SUPER ? kSuperShift : kShift;      // staging bucket = id >> kSh
     constexpr int kKeyShift = SUPER ? kSuperShift : 16;    // key = staging bucket << kKeyShift | local
     constexpr uint32_t kLocalMask = (1u << kSh) - 1u;
@@ -163,22 +192,22 @@ __global__ __launch_bounds__(kStageThreads, 8) void bucket_scatter_staged_kernel
     __shared__ unsigned long long run[kStagedMaxB];   // next output slot of each staging bucket
     __shared__ uint32_t wsum[kStageThreads / 64];
     const int t = threadIdx.x;
-    const int nblk = gridDim.x;
+    const int c0 = blockIdx.x * G;                         // first edge chunk of this block
     const int NB = SUPER ? (B + kSub - 1) / kSub : B;     // staging buckets
     for (int k = t; k < NB; k += kStageThreads) {
         if (SUPER) {
-            // block b's first slot in super-bucket k: its first bucket's start
-            // plus what the blocks before b put into each of its buckets
+            // chunk c0's first slot in super-bucket k: its first bucket's start
+            // plus what the chunks before c0 put into each of its buckets
             const int k0 = k * kSub, k1 = k0 + kSub < B ? k0 + kSub : B;
             unsigned long long r = base[k0];
-            for (int q = k0; q < k1; ++q) r += prefix[(int64_t)q * nblk + blockIdx.x];
+            for (int q = k0; q < k1; ++q) r += prefix[(int64_t)q * nblk + c0];
             run[k] = r;
         } else {
-            run[k] = base[k] + prefix[(int64_t)k * nblk + blockIdx.x];
+            run[k] = base[k] + prefix[(int64_t)k * nblk + c0];
         }
     }
-    const int64_t beg = (int64_t)blockIdx.x * chunk;
-    int64_t end = beg + chunk;
+    const int64_t beg = (int64_t)c0 * chunk;
+    int64_t end = beg + (int64_t)G * chunk;
     if (end > m) end = m;
     for (int64_t t0 = beg; t0 < end; t0 += (int64_t)kStageThreads * E) {
         for (int k = t; k <= NB; k += kStageThreads) toff[k] = 0;
@@ -366,18 +395,6 @@ __device__ __forceinline__ void hist_flush(HistLds& L, unsigned long long best, 
 }
 
 // ------------------------------------------------------------------ pass D
-// Adds one entry per lane to the LDS counters; lanes of a wave that hit the
-// wave's first key (hub vertices) are folded into one atomic.
-__device__ __forceinline__ void count_lane(uint32_t* cnt, bool ok, int32_t x) {
-    const int32_t lead = __shfl(x, __builtin_ctzll(ballot(ok) | (1ull << 63)) & 63);
-    const uint64_t same = ballot(ok && x == lead);
-    if (ok && x == lead) {
-        if (lanes_below(same) == 0) atomicAdd(&cnt[lead], (uint32_t)__popcll(same));
-    } else if (ok) {
-        atomicAdd(&cnt[x], 1u);
-    }
-}
-
 constexpr int kUnrollD = 4;
 
 __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
@@ -402,16 +419,36 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
         // degrees already known (an earlier pass): only the offsets are wanted
         for (int j = threadIdx.x; j < nv; j += kBlockD) cnt[j] = (uint32_t)deg[x0 + j];
     }
-    // every lane runs the same trip count so the wave-level aggregation can ballot
-    for (unsigned long long i0 = beg; count_pairs && i0 < end; i0 += (unsigned long long)kBlockD * kUnrollD) {
-        int32_t x[kUnrollD];
+    if (count_pairs) {
+        // 8-byte loads of four ids between the first and last multiple of 4
+        // (loc is 256-byte aligned); the few entries outside one at a time.
+        // Plain LDS atomics: a hub's entries are spread over its bucket's
+        // range, so lanes of one wave rarely share a counter.
+        const unsigned long long a4 = (beg + 3) & ~3ull, e4 = end & ~3ull;
+        if (a4 >= e4) {
+            for (unsigned long long i = beg + threadIdx.x; i < end; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
+        } else {
+            for (unsigned long long i = beg + threadIdx.x; i < a4; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
+            for (unsigned long long i = e4 + threadIdx.x; i < end; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
+            const uint2* q = (const uint2*)(loc + a4);
+            const long long nq = (long long)((e4 - a4) >> 2);
+            for (long long j0 = 0; j0 < nq; j0 += (long long)kBlockD * kUnrollD) {
+                uint2 w[kUnrollD];
 #pragma unroll
-        for (int r = 0; r < kUnrollD; ++r) {
-            const unsigned long long i = i0 + threadIdx.x + (unsigned long long)r * kBlockD;
-            x[r] = i < end ? (int32_t)loc[i] : -1;
+                for (int r = 0; r < kUnrollD; ++r) {
+                    const long long j = j0 + threadIdx.x + (long long)r * kBlockD;
+                    w[r] = j < nq ? q[j] : make_uint2(0xffffffffu, 0xffffffffu);
+                }
+#pragma unroll
+                for (int r = 0; r < kUnrollD; ++r) {
+                    if (w[r].x == 0xffffffffu && w[r].y == 0xffffffffu) continue;   // past the end
+                    atomicAdd(&cnt[w[r].x & 0xffffu], 1u);
+                    atomicAdd(&cnt[w[r].x >> 16], 1u);
+                    atomicAdd(&cnt[w[r].y & 0xffffu], 1u);
+                    atomicAdd(&cnt[w[r].y >> 16], 1u);
+                }
+            }
         }
-#pragma unroll
-        for (int r = 0; r < kUnrollD; ++r) count_lane(cnt, x[r] >= 0, x[r]);
     }
     __syncthreads();
     unsigned long long best = 0;
@@ -646,12 +683,14 @@ int bucket_plan(int32_t n, int64_t m, BucketPlan* p) {
 template <bool OTHER>
 static void scatter_with(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
                          const BucketBufs& w, hipStream_t s) {
+    const int G = StageCfg<OTHER>::kChunks;
+    const int grid = (p.nblk + G - 1) / G;
     if (p.B <= kStagedMaxB) {
-        bucket_scatter_staged_kernel<OTHER, false><<<p.nblk, kStageThreads, 0, s>>>(
-            u, v, m, n, p.chunk, p.B, w.counts, w.base, w.loc, nullptr, OTHER ? w.other : nullptr);
+        bucket_scatter_staged_kernel<OTHER, false><<<grid, kStageThreads, 0, s>>>(
+            u, v, m, n, p.chunk, p.B, p.nblk, w.counts, w.base, w.loc, nullptr, OTHER ? w.other : nullptr);
     } else {
-        bucket_scatter_staged_kernel<OTHER, true><<<p.nblk, kStageThreads, 0, s>>>(
-            u, v, m, n, p.chunk, p.B, w.counts, w.base, nullptr, w.loc32, OTHER ? w.other32 : nullptr);
+        bucket_scatter_staged_kernel<OTHER, true><<<grid, kStageThreads, 0, s>>>(
+            u, v, m, n, p.chunk, p.B, p.nblk, w.counts, w.base, nullptr, w.loc32, OTHER ? w.other32 : nullptr);
         bucket_split_kernel<OTHER><<<(p.B + kSub - 1) / kSub, kStageThreads, 0, s>>>(
             w.loc32, OTHER ? w.other32 : nullptr, w.base, p.B, w.loc, OTHER ? w.other : nullptr);
     }
@@ -700,7 +739,10 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
                                 unsigned long long* tail_count, unsigned long long* argmax_key, int want_csr,
                                 int64_t* off, int32_t* adj, hipStream_t s) {
     const size_t lds = (size_t)p.B * sizeof(uint32_t);
-    bucket_count_kernel<<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.counts, w.err);
+    if ((((uintptr_t)u | (uintptr_t)v) & 15) == 0)
+        bucket_count_kernel<true><<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.counts, w.err);
+    else
+        bucket_count_kernel<false><<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.counts, w.err);
     bucket_colscan_kernel<<<p.B, kScanThreads, 0, s>>>(w.counts, p.nblk, w.tot);
     bucket_scan_kernel<<<1, 1024, 0, s>>>(w.tot, p.B, w.base);
     hipError_t e = launch_scatter(u, v, m, n, p, w, want_csr != 0, s);

@@ -107,14 +107,27 @@ __global__ __launch_bounds__(kBlock) void sv_shortcut_kernel(int32_t* parent, co
 
 // One block: totals[0] = sum of the per-segment survivor counts, totals[1] =
 // sum of the per-segment hook counts.
-__global__ __launch_bounds__(kBlock) void sv_totals_kernel(const uint32_t* __restrict__ hooked_count,
-                                                           const uint32_t* __restrict__ kept_count, int32_t nseg,
-                                                           unsigned long long* __restrict__ totals) {
-    __shared__ unsigned long long red[2][kWaves];
+constexpr int kTotThreads = 1024;
+__global__ __launch_bounds__(kTotThreads) void sv_totals_kernel(const uint32_t* __restrict__ hooked_count,
+                                                                const uint32_t* __restrict__ kept_count, int32_t nseg,
+                                                                unsigned long long* __restrict__ totals) {
+    constexpr int W = kTotThreads / 64;
+    __shared__ unsigned long long red[2][W];
     unsigned long long sk = 0, sh = 0;
-    for (int i = threadIdx.x; i < nseg; i += kBlock) {
-        sk += kept_count[i];
-        sh += hooked_count[i];
+    // four independent loads in flight per thread
+    for (int i0 = threadIdx.x; i0 < nseg; i0 += 4 * kTotThreads) {
+        uint32_t a[4], c[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + r * kTotThreads;
+            a[r] = i < nseg ? kept_count[i] : 0u;
+            c[r] = i < nseg ? hooked_count[i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            sk += a[r];
+            sh += c[r];
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         sk += __shfl_xor(sk, off);
@@ -127,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void sv_totals_kernel(const uint32_t* __res
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long a = 0, c = 0;
-        for (int w = 0; w < kWaves; ++w) { a += red[0][w]; c += red[1][w]; }
+        for (int w = 0; w < W; ++w) { a += red[0][w]; c += red[1][w]; }
         totals[0] = a;
         totals[1] = c;
     }
@@ -186,7 +199,7 @@ hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint
 
 hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg,
                             unsigned long long* totals, hipStream_t s) {
-    sv_totals_kernel<<<1, kBlock, 0, s>>>(hooked_count, kept_count, nseg, totals);
+    sv_totals_kernel<<<1, kTotThreads, 0, s>>>(hooked_count, kept_count, nseg, totals);
     return hipGetLastError();
 }
 

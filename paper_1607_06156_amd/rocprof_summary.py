@@ -2,7 +2,7 @@
 
     python -m paper_1607_06156_amd.rocprof_summary stats DIR [--title T] [--command C]
     python -m paper_1607_06156_amd.rocprof_summary pmc --fetch DIR --write DIR --kernel NAME
-        --cls CLASS --copy-mib N [--title T] [--command C]
+        --cls CLASS --copy-mib N [--last K] [--title T] [--command C]
 
 `stats` condenses a `--kernel-trace --stats` run (its *_kernel_stats.csv) into
 a table.  `pmc` takes two counter runs (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`,
@@ -96,15 +96,16 @@ def stats_table(dirname: str) -> str:
 
 
 def pmc_per_dispatch(dirname: str, counter: str) -> dict:
-    """kernel (short name) -> list of per-dispatch counter values (KiB)."""
+    """kernel (short name) -> list of per-dispatch counter values (KiB), in
+    dispatch order."""
     path = _find(dirname, "counter_collection.csv")
     per = defaultdict(lambda: defaultdict(float))
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name") != counter:
             continue
         did = r.get("Dispatch_Id") or r.get("Correlation_Id")
-        per[_short(r["Kernel_Name"])][did] += float(r["Counter_Value"])
-    return {k: list(v.values()) for k, v in per.items()}
+        per[_short(r["Kernel_Name"])][int(did)] += float(r["Counter_Value"])
+    return {k: [v[d] for d in sorted(v)] for k, v in per.items()}
 
 
 def main(argv=None):
@@ -121,6 +122,7 @@ def main(argv=None):
     p.add_argument("--cls", required=True, choices=sorted(KERNEL_SOURCES))
     p.add_argument("--copy-mib", type=float, required=True)
     p.add_argument("--sources-rev", default=None, help="git revision the profiled library was built from")
+    p.add_argument("--last", type=int, default=0, help="average only the kernel's last N dispatches")
     p.add_argument("--title", default="HBM traffic")
     p.add_argument("--command", default="")
     a = ap.parse_args(argv)
@@ -142,6 +144,8 @@ def main(argv=None):
     wscale = copy_bytes / cw
     kf = fetch.get(a.kernel, [])
     kw = write.get(a.kernel, [])
+    if a.last > 0:
+        kf, kw = kf[-a.last:], kw[-a.last:]
     if not kf or not kw:
         sys.exit(f"kernel {a.kernel} not found in the counter runs")
     f_avg = sum(kf) / len(kf)

@@ -203,6 +203,26 @@ def test_two_level_buckets_large_n():
         assert_labels_equal(lab, expect, f"large-n/{route}/{kw}")
 
 
+def test_shipped_router_weights():
+    """The trained weights shipped with the package load, pick a route on every
+    workload family, and the labels stay exact (the route changes only time)."""
+    import os
+    path = os.path.join(os.path.dirname(ccmi.__file__), "router_weights.txt")
+    ccmi.router_load(path)
+    try:
+        assert ccmi.router_loaded()
+        for name in SMALL:
+            g = gen.workload(name)
+            for route in ("router", "auto"):
+                lab, st = ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route=route, stats=True)
+                say(f"[gpu] {name} {route}: took {st['route_name']} logits={st['router_logits']}")
+                assert st["route"] == int(np.argmax(st["router_logits"]))
+                assert_labels_equal(lab, oracle_labels(g), f"{name}/{route}")
+    finally:
+        ccmi.router_set(None)
+    assert not ccmi.router_loaded()
+
+
 def test_route_edge_cases():
     for u, v, n in [([], [], 5), ([2], [2], 3), ([0], [1], 2), ([3, 1], [1, 3], 4)]:
         u = np.array(u, np.int32)
