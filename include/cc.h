@@ -147,8 +147,13 @@ int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_
  *  edge_off   device, int64[G+1], edge_off[0] = 0, non-decreasing.
  *  vert_off   device, int64[G+1], vert_off[0] = 0, non-decreasing, total < 2^31.
  *  labels     device, int32[vert_off[G]]: graph-local labels (min local id).
+ * The launch shape (grid size, hook attempts per pass) is timed over a few
+ * candidates on the first call of each size class and remembered; if the
+ * environment variable CC_AUTOTUNE_CACHE names a file, the choices are also
+ * kept there (one "key blocks link" line per class) and read back on start.
  * Errors: CC_EINVAL (G < 0, bad offsets: checked on the device), CC_ERANGE,
- * CC_ENOMEM, CC_EHIP. */
+ * CC_ENOMEM, CC_EHIP, CC_EINTERNAL (the persistent grid's barrier waited more
+ * than ~5 s: not every workgroup became resident). */
 int cc_label_batched(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
                      int32_t G, int32_t* labels, void* stream);
 

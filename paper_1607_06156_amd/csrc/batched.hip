@@ -146,10 +146,13 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     if (load_status(A.status)) return;
     stamp(A.status, 0);
 
-    // ---- relabel: the caller's SoA list -> global (a, c) pairs in buf1, tile
-    // by tile, dropping (and counting) edges with an id outside their graph.
-    // Streaming only, so the graph lookup never sits in front of a gather.
+    // ---- pass 0, straight from the caller's SoA list.  Thread 0 finds each
+    // tile's first graph (one binary search); every thread then walks forward
+    // to the graphs of its own edges (it sees them in increasing order),
+    // shifts the ids to global ones and drops (and counts) edges with an id
+    // outside their graph.
     uint32_t bad = 0;
+    unsigned long long block_kept = 0, block_hooks = 0;
     for (int64_t t = tw.first; t < tw.end; t += tw.step) {
         const int64_t e0 = t * kTileE;
         int64_t len = A.m - e0;
@@ -158,78 +161,35 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
         if (threadIdx.x == 0) sh_g = graph_of(A.edge_off, A.G, e0);
         __syncthreads();
         int32_t g = sh_g;
-        int32_t x[kEPT], y[kEPT];
-        bool ok[kEPT];
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            const int64_t i = threadIdx.x + (int64_t)k * kBlock;
-            ok[k] = i < len;
-            if (ok[k]) {
-                x[k] = A.u[e0 + i];
-                y[k] = A.v[e0 + i];
-            }
-        }
-        int2 pr[kEPT];
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            if (!ok[k]) continue;
-            const int64_t e = e0 + threadIdx.x + (int64_t)k * kBlock;
+        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
+            const int64_t e = e0 + i;
+            const int32_t x = A.u[e], y = A.v[e];
             while (A.edge_off[g + 1] <= e) ++g;
             const int64_t v0 = A.vert_off[g];
             const int64_t nl = A.vert_off[g + 1] - v0;
-            if (x[k] < 0 || y[k] < 0 || (int64_t)x[k] >= nl || (int64_t)y[k] >= nl) {
+            if (x < 0 || y < 0 || (int64_t)x >= nl || (int64_t)y >= nl) {
                 ++bad;
-                ok[k] = false;
-                continue;
+                return false;
             }
-            pr[k] = make_int2((int32_t)(v0 + x[k]), (int32_t)(v0 + y[k]));
-        }
-        uint64_t mk[kEPT];
-        uint32_t pre[kEPT], wk = 0;
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            mk[k] = ballot(ok[k]);
-            pre[k] = wk + lanes_below(mk[k]);
-            wk += (uint32_t)__popcll(mk[k]);
-        }
-        uint32_t tot;
-        const uint32_t woff = block_wave_offset(wk, lds, &tot);
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k)
-            if (ok[k]) A.buf1[e0 + woff + pre[k]] = pr[k];
-        if (threadIdx.x == 0) A.cnt1[t] = tot;
-    }
-    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o);
-    if (lane_id() == 0 && bad) {
-        __hip_atomic_fetch_add(&A.status[2], (unsigned long long)bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_or(&A.status[0], (unsigned long long)kErrRange, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-
-    // ---- pass 0 over the block's own relabelled tiles (no grid barrier needed:
-    // every tile was written by this block).  The block barrier publishes the
-    // per-tile counts thread 0 wrote, so every thread reads the same length.
-    __syncthreads();
-    unsigned long long block_kept = 0, block_hooks = 0;
-    for (int64_t t = tw.first; t < tw.end; t += tw.step) {
-        const uint32_t len = A.cnt1[t];
+            *a = (int32_t)(v0 + x);
+            *c = (int32_t)(v0 + y);
+            return true;
+        };
         uint32_t kept = 0, hk = 0;
-        if (len) {
-            const int2* src = A.buf1 + t * kTileE;
-            auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
-                const int2 e = src[i];
-                *a = e.x;
-                *c = e.y;
-                return true;
-            };
-            sv_segment((int64_t)len, load, A.parent, A.buf0 + t * kTileE, A.hooked + t * kTileE, true, A.max_link,
-                       kept, hk, lds);
-        }
+        if (len > 0)
+            sv_segment(len, load, A.parent, A.buf0 + t * kTileE, A.hooked + t * kTileE, true, A.max_link, kept, hk,
+                       lds);
         if (threadIdx.x == 0) {
             A.cnt0[t] = kept;
             A.hcnt[t] = hk;
         }
         block_kept += kept;
         block_hooks += hk;
+    }
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o);
+    if (lane_id() == 0 && bad) {
+        __hip_atomic_fetch_add(&A.status[2], (unsigned long long)bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(&A.status[0], (unsigned long long)kErrRange, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     unsigned long long* const part_base = A.part;
     unsigned long long* part_rd = part_base;
