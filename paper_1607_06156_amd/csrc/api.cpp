@@ -131,17 +131,18 @@ int choose_nseg(int64_t m) {
     return (int)s;
 }
 
-// Chunks of the first pass.  Within one pass the trees only grow (no
-// shortcut runs while hooks are in flight), so on graphs with many more edges
-// than vertices the finds of late edges walk long chains.  Cutting the first
-// pass into chunks with a full pointer-jumping shortcut after each keeps the
-// trees flat; the shortcut costs O(n), so the chunk count follows m / n.
 // hooked roots are pointer-jumped after a pass only if at most this many per survivor
 constexpr int64_t kLazyJump = 8;
 
+// Chunks of the first pass.  Within one pass the trees only grow (no
+// shortcut runs while hooks are in flight), so the finds of late edges walk
+// long chains.  Cutting the first pass into chunks with a full pointer-jumping
+// shortcut after each keeps the trees flat; the shortcut costs O(n), so the
+// chunk count follows m / n.  Short lists take one chunk: there the extra
+// launches would cost more than the links they save.
 int pass0_chunks(int64_t m, int32_t n) {
-    if (n <= 0) return 1;
-    int64_t k = m / (2 * (int64_t)n);
+    if (n <= 0 || m < ((int64_t)1 << 22)) return 1;
+    int64_t k = (5 * m + 2 * (int64_t)n - 1) / (2 * (int64_t)n);   // ceil(2.5 m / n)
     if (k < 1) k = 1;
     if (k > 8) k = 8;
     return (int)k;
