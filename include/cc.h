@@ -151,6 +151,10 @@ int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_
  * candidates on the first call of each size class and remembered; if the
  * environment variable CC_AUTOTUNE_CACHE names a file, the choices are also
  * kept there (one "key blocks link" line per class) and read back on start.
+ * If the device refuses the cooperative launch (another process using the
+ * same GPU holds its global wave-sync resource), the batch is labelled as one
+ * disjoint-union graph by the single-graph SV loop instead: same labels, one
+ * host round trip per pass; cc_batch_stats.blocks is then 0.
  * Errors: CC_EINVAL (G < 0, bad offsets: checked on the device), CC_ERANGE,
  * CC_ENOMEM, CC_EHIP, CC_EINTERNAL (the persistent grid's barrier waited more
  * than ~5 s: not every workgroup became resident). */
@@ -161,7 +165,7 @@ int cc_label_batched(const int32_t* u, const int32_t* v, const int64_t* edge_off
 typedef struct cc_batch_stats {
     int32_t passes;      /* SV passes of the persistent loop */
     int32_t tile_edges;  /* edges per workgroup segment */
-    int32_t blocks;      /* workgroups of the persistent grid */
+    int32_t blocks;      /* workgroups of the persistent grid (0: disjoint-union fallback) */
     int32_t max_link;    /* hook attempts per edge per pass */
     int64_t total_edges;
     int64_t total_vertices;

@@ -314,6 +314,62 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     }
 }
 
+// ------------------------------------------- fallback without a persistent grid
+// Disjoint-union relabel: edge e of graph g becomes (vert_off[g] + u[e],
+// vert_off[g] + v[e]); an edge with an id outside its graph becomes (-1, -1),
+// which the SV pass counts as out of range.  Offsets that decrease set *bad.
+__global__ __launch_bounds__(kBlock) void union_relabel_kernel(const int32_t* __restrict__ u,
+                                                               const int32_t* __restrict__ v,
+                                                               const int64_t* __restrict__ edge_off,
+                                                               const int64_t* __restrict__ vert_off, int32_t G,
+                                                               int64_t m, int32_t* __restrict__ gu,
+                                                               int32_t* __restrict__ gv,
+                                                               unsigned long long* __restrict__ bad) {
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t g = tid; g < G; g += stride)
+        if (edge_off[g + 1] < edge_off[g] || vert_off[g + 1] < vert_off[g]) atomic_add_agent(bad, 1ull);
+    for (int64_t e = tid; e < m; e += stride) {
+        const int32_t g = graph_of(edge_off, G, e);
+        const int64_t v0 = vert_off[g];
+        const int64_t nl = vert_off[g + 1] - v0;
+        const int32_t x = u[e], y = v[e];
+        const bool ok = x >= 0 && y >= 0 && (int64_t)x < nl && (int64_t)y < nl;
+        gu[e] = ok ? (int32_t)(v0 + x) : -1;
+        gv[e] = ok ? (int32_t)(v0 + y) : -1;
+    }
+}
+
+// labels[x] -= vert_off[graph of x]: global minimum ids -> graph-local labels
+__global__ __launch_bounds__(kBlock) void union_unshift_kernel(int32_t* __restrict__ labels,
+                                                               const int64_t* __restrict__ vert_off, int32_t G,
+                                                               int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n; x += stride)
+        labels[x] = (int32_t)(labels[x] - vert_off[graph_of(vert_off, G, x)]);
+}
+
+static int grid_for_items(int64_t items) {
+    int64_t g = (items + 4 * kBlock - 1) / (4 * kBlock);
+    if (g < 1) g = 1;
+    if (g > 16384) g = 16384;
+    return (int)g;
+}
+
+hipError_t launch_union_relabel(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
+                                int32_t G, int64_t m, int32_t* gu, int32_t* gv, unsigned long long* bad,
+                                hipStream_t s) {
+    union_relabel_kernel<<<grid_for_items(m > G ? m : G), kBlock, 0, s>>>(u, v, edge_off, vert_off, G, m, gu, gv,
+                                                                           bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_union_unshift(int32_t* labels, const int64_t* vert_off, int32_t G, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    union_unshift_kernel<<<grid_for_items(n), kBlock, 0, s>>>(labels, vert_off, G, n);
+    return hipGetLastError();
+}
+
 hipError_t batched_max_blocks(int* blocks) {
     int per_cu = 0, dev = 0, cus = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel, kBlock, 0);

@@ -35,4 +35,12 @@ hipError_t batched_max_blocks(int* blocks);
 // one cooperative launch running the whole SV loop over all graphs
 hipError_t launch_batched(const BatchArgsHost& h, int blocks, hipStream_t s);
 
+// fallback without a persistent grid: the batch as one disjoint-union graph
+// (global ids; -1 for an id outside its graph; *bad counts decreasing offsets)
+hipError_t launch_union_relabel(const int32_t* u, const int32_t* v, const int64_t* edge_off, const int64_t* vert_off,
+                                int32_t G, int64_t m, int32_t* gu, int32_t* gv, unsigned long long* bad,
+                                hipStream_t s);
+// labels[x] -= vert_off[graph of x]
+hipError_t launch_union_unshift(int32_t* labels, const int64_t* vert_off, int32_t G, int64_t n, hipStream_t s);
+
 }  // namespace ccmi

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "batched.hpp"
+#include "common.hpp"
 #include "internal.hpp"
 
 #define CC_API extern "C" __attribute__((visibility("default")))
@@ -70,8 +71,16 @@ static void tune_store(const std::string& key, Tuned t) {
     fclose(f);
 }
 
+// A cooperative launch can be refused although the grid fits: the device's
+// global wave-sync resource is held by another process that made cooperative
+// launches on the same GPU, or the runtime cannot make the grid resident.
+static bool coop_refused(hipError_t e) {
+    return e == hipErrorIllegalState || e == hipErrorCooperativeLaunchTooLarge || e == hipErrorNotSupported;
+}
+
+// *refused (if given) reports a refused cooperative launch instead of an error.
 static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStream_t s,
-                    unsigned long long* status_host, double* ms) {
+                    unsigned long long* status_host, double* ms, bool* refused) {
     const int64_t tiles = h.m > 0 ? (h.m + kBatchTile - 1) / kBatchTile : 1;
     const size_t slots = (size_t)tiles * (size_t)kBatchTile;
     void *p0, *p1, *ph, *pc, *pb;
@@ -100,7 +109,16 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     }
     hipError_t e = hipMemsetAsync(pb, 0, kBatchCtl, s);
     if (e == hipSuccess && ms) e = hipEventRecord(e0, s);
-    if (e == hipSuccess) e = launch_batched(h, blocks, s);
+    if (e == hipSuccess) {
+        e = launch_batched(h, blocks, s);
+        if (e != hipSuccess && refused && coop_refused(e)) {
+            (void)hipGetLastError();   // clear the launch error
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            *refused = true;
+            return CC_OK;
+        }
+    }
     if (e == hipSuccess && ms) e = hipEventRecord(e1, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(status_host, h.status, kStatusWords * sizeof(unsigned long long), hipMemcpyDeviceToHost,
@@ -115,6 +133,80 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
     return CC_OK;
+}
+
+// Fallback without a persistent grid: the batch as one graph on vert_off[G]
+// vertices (graph g's ids shifted by vert_off[g]), labelled by the single-graph
+// SV loop (R1), then shifted back to graph-local labels.  Same labels, one
+// host round trip per pass.
+static int run_union(Workspace& ws, const BatchArgsHost& h, hipStream_t s, unsigned long long* host,
+                     cc_batch_stats* stats) {
+    const int64_t m = h.m, n = h.n;
+    const size_t half = ((size_t)m * sizeof(int32_t) + 255) & ~(size_t)255;
+    void *pg, *pf;
+    int rc;
+    if ((rc = ws.get(WS_ADJ, 2 * half + 256, &pg))) return rc;
+    if ((rc = ws.get(WS_HISTOUT, 64, &pf))) return rc;
+    int32_t* gu = (int32_t*)pg;
+    int32_t* gv = (int32_t*)((char*)pg + half);
+    unsigned long long* bad = (unsigned long long*)pf;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, s);
+    }
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned long long), s);
+    if (e == hipSuccess) e = launch_union_relabel(h.u, h.v, h.edge_off, h.vert_off, h.G, m, gu, gv, bad, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, bad, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "union relabel");
+    else if (host[0]) rc = fail(CC_EINVAL, "edge_off / vert_off are not non-decreasing");
+    cc_stats st;
+    memset(&st, 0, sizeof st);
+    if (rc == CC_OK) {
+        Call c;
+        c.ws = &ws;
+        c.stream = s;
+        c.u = gu;
+        c.v = gv;
+        c.m = m;
+        c.n = (int32_t)n;
+        c.parent = h.labels;
+        cc_default_options(&c.opt);
+        c.stats = &st;
+        Timer tm(false, s);
+        c.timer = &tm;
+        e = launch_sv_init(h.labels, (int32_t)n, s);
+        if (e != hipSuccess) rc = hip_fail(e, "sv_init launch");
+        if (rc == CC_OK && m > 0) {
+            SvInput in;
+            in.soa = true;
+            in.u = gu;
+            in.v = gv;
+            in.m = m;
+            rc = run_sv(c, in, CC_R1_SV, 8.0, 0);
+            if (rc == CC_ERANGE) rc = fail(CC_ERANGE, "edges have an endpoint outside their graph's [0, n_g)");
+        }
+        if (rc == CC_OK && (e = launch_union_unshift(h.labels, h.vert_off, h.G, n, s)) != hipSuccess)
+            rc = hip_fail(e, "union unshift");
+    }
+    if (rc == CC_OK && stats) {
+        float t = 0.f;
+        if ((e = hipEventRecord(e1, s)) == hipSuccess && (e = hipEventSynchronize(e1)) == hipSuccess)
+            (void)hipEventElapsedTime(&t, e0, e1);
+        stats->passes = st.sv_passes;
+        stats->blocks = 0;   // no persistent grid
+        stats->max_link = 1;
+        stats->tile_edges = 0;
+        stats->total_edges = m;
+        stats->total_vertices = n;
+        stats->ms_total = t;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc == CC_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+    return rc;
 }
 
 static int status_code(const unsigned long long* st) {
@@ -205,7 +297,9 @@ CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t
             for (int b : bcand)
                 for (int l : lcand) {
                     double ms = 0;
-                    if ((rc = run_once(*ws, h, b, l, s, host, &ms))) return rc;
+                    bool refused = false;
+                    if ((rc = run_once(*ws, h, b, l, s, host, &ms, &refused))) return rc;
+                    if (refused) return run_union(*ws, h, s, host, stats);
                     if ((rc = status_code(host))) return rc;
                     if (ms < best) {
                         best = ms;
@@ -219,7 +313,9 @@ CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t
         }
     }
     double ms = 0;
-    if ((rc = run_once(*ws, h, cfg.blocks, cfg.link, s, host, stats ? &ms : nullptr))) return rc;
+    bool refused = false;
+    if ((rc = run_once(*ws, h, cfg.blocks, cfg.link, s, host, stats ? &ms : nullptr, &refused))) return rc;
+    if (refused) return run_union(*ws, h, s, host, stats);
     if ((rc = status_code(host))) return rc;
     if (stats) {
         const int passes = (int)host[1];
