@@ -189,23 +189,28 @@ __global__ __launch_bounds__(kStageThreads, StageCfg<OTHER>::kWaves) void bucket
     __shared__ uint32_t stage[StageCfg<OTHER>::kSlots];
     __shared__ int32_t stage_o[OTHER ? StageCfg<OTHER>::kSlots : 1];
     __shared__ uint32_t toff[kStagedMaxB + 1];
-    __shared__ unsigned long long run[kStagedMaxB];   // next output slot of each staging bucket
+    __shared__ uint32_t run[kStagedMaxB];  // next free output slot of each staging bucket
+    __shared__ uint32_t rb[kStagedMaxB];   // per tile: output slot of staged slot 0, per staging bucket
     __shared__ uint32_t wsum[kStageThreads / 64];
     const int t = threadIdx.x;
     const int c0 = blockIdx.x * G;                         // first edge chunk of this block
-    const int NB = SUPER ? (B + kSub - 1) / kSub : B;     // staging buckets
-    for (int k = t; k < NB; k += kStageThreads) {
+    const int NB = SUPER ? (B + kSub - 1) / kSub : B;     // staging buckets (<= 2 * kStageThreads)
+    // Thread t owns staging buckets 2t and 2t+1: it alone reads and advances
+    // their cursors.  Output positions are below 2m < 2^32 (m < 2^31 is
+    // checked by bucket_plan), so 32-bit slot arithmetic is exact.
+    auto first_slot = [&](int k) -> uint32_t {
         if (SUPER) {
             // chunk c0's first slot in super-bucket k: its first bucket's start
             // plus what the chunks before c0 put into each of its buckets
             const int k0 = k * kSub, k1 = k0 + kSub < B ? k0 + kSub : B;
             unsigned long long r = base[k0];
             for (int q = k0; q < k1; ++q) r += prefix[(int64_t)q * nblk + c0];
-            run[k] = r;
-        } else {
-            run[k] = base[k] + prefix[(int64_t)k * nblk + c0];
+            return (uint32_t)r;
         }
-    }
+        return (uint32_t)(base[k] + prefix[(int64_t)k * nblk + c0]);
+    };
+    if (2 * t < NB) run[2 * t] = first_slot(2 * t);
+    if (2 * t + 1 < NB) run[2 * t + 1] = first_slot(2 * t + 1);
     const int64_t beg = (int64_t)c0 * chunk;
     int64_t end = beg + (int64_t)G * chunk;
     if (end > m) end = m;
@@ -239,9 +244,9 @@ __global__ __launch_bounds__(kStageThreads, StageCfg<OTHER>::kWaves) void bucket
         __syncthreads();
         // exclusive scan of the tile's bucket counts (NB <= 2 * 1024 entries)
         {
-            const uint32_t c0 = 2 * t < NB ? toff[2 * t] : 0u;
-            const uint32_t c1 = 2 * t + 1 < NB ? toff[2 * t + 1] : 0u;
-            const uint32_t s = c0 + c1;
+            const uint32_t n0 = 2 * t < NB ? toff[2 * t] : 0u;
+            const uint32_t n1 = 2 * t + 1 < NB ? toff[2 * t + 1] : 0u;
+            const uint32_t s = n0 + n1;
             uint32_t incl = s;
             for (int o = 1; o < 64; o <<= 1) {
                 uint32_t y = __shfl_up(incl, o);
@@ -256,8 +261,19 @@ __global__ __launch_bounds__(kStageThreads, StageCfg<OTHER>::kWaves) void bucket
             }
             __syncthreads();
             const uint32_t ex = wsum[t >> 6] + incl - s;
-            if (2 * t < NB) toff[2 * t] = ex;
-            if (2 * t + 1 < NB) toff[2 * t + 1] = ex + c0;
+            // staged slot i of bucket k goes to output slot rb[k] + i
+            if (2 * t < NB) {
+                const uint32_t r = run[2 * t];
+                toff[2 * t] = ex;
+                rb[2 * t] = r - ex;
+                run[2 * t] = r + n0;
+            }
+            if (2 * t + 1 < NB) {
+                const uint32_t r = run[2 * t + 1];
+                toff[2 * t + 1] = ex + n0;
+                rb[2 * t + 1] = r - (ex + n0);
+                run[2 * t + 1] = r + n1;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -272,14 +288,11 @@ __global__ __launch_bounds__(kStageThreads, StageCfg<OTHER>::kWaves) void bucket
         const uint32_t total = toff[NB];
         for (uint32_t i = t; i < total; i += kStageThreads) {
             const uint32_t q = stage[i];
-            const int k = (int)(q >> kKeyShift);
-            const unsigned long long pos = run[k] + (i - toff[k]);
+            const uint64_t pos = (uint32_t)(rb[q >> kKeyShift] + i);
             if (SUPER) loc32[pos] = q & kLocalMask;
             else loc[pos] = (uint16_t)(q & kLocalMask);
             if (OTHER) other[pos] = stage_o[i];
         }
-        __syncthreads();
-        for (int k = t; k < NB; k += kStageThreads) run[k] += toff[k + 1] - toff[k];
         __syncthreads();
     }
 }
@@ -357,6 +370,27 @@ __global__ __launch_bounds__(kStageThreads) void bucket_split_kernel(const uint3
     }
 }
 
+// h[b] += 1 for every active lane.  Lanes of one wave that share a bin would
+// serialise on its LDS counter (every vertex of a lattice has the same
+// degree; most R-MAT vertices have degree 0 or 1), so equal bins go through
+// one lane: the first lane's bin, then the first remaining lane's bin, then
+// one atomic per lane for the rest.  Works for any set of active lanes.
+__device__ __forceinline__ void lds_inc_agg(uint32_t* h, uint32_t b) {
+    const uint32_t v1 = __builtin_amdgcn_readfirstlane(b);
+    const uint64_t m1 = ballot(b == v1);
+    if (b == v1) {
+        if (lanes_below(m1) == 0) atomicAdd(&h[v1], (uint32_t)__popcll(m1));
+    } else {
+        const uint32_t v2 = __builtin_amdgcn_readfirstlane(b);
+        const uint64_t m2 = ballot(b == v2);
+        if (b == v2) {
+            if (lanes_below(m2) == 0) atomicAdd(&h[v2], (uint32_t)__popcll(m2));
+        } else {
+            atomicAdd(&h[b], 1u);
+        }
+    }
+}
+
 // per-vertex histogram update shared by the bucket pass and the standalone kernel
 struct HistLds {
     uint32_t hx[kExactBins];
@@ -366,12 +400,12 @@ struct HistLds {
 
 __device__ __forceinline__ void hist_vertex(HistLds& L, uint32_t d, int32_t x, int32_t* tail, int64_t tail_cap,
                                             unsigned long long* tail_count, unsigned long long& best) {
-    if (d < (uint32_t)kExactBins) atomicAdd(&L.hx[d], 1u);
+    if (d < (uint32_t)kExactBins) lds_inc_agg(L.hx, d);
     else {
         unsigned long long slot = atomic_add_agent(tail_count, 1ull);
         if ((int64_t)slot < tail_cap) tail[slot] = (int32_t)d;
     }
-    atomicAdd(&L.h64[log_bin(d)], 1u);
+    lds_inc_agg(L.h64, (uint32_t)log_bin(d));
     unsigned long long key = ((unsigned long long)d << 32) | (unsigned long long)(~(uint32_t)x);
     best = key > best ? key : best;
 }
@@ -395,7 +429,47 @@ __device__ __forceinline__ void hist_flush(HistLds& L, unsigned long long best, 
 }
 
 // ------------------------------------------------------------------ pass D
-constexpr int kUnrollD = 4;
+constexpr int kUnrollD = 8;
+
+__device__ __forceinline__ void count8(uint32_t* cnt, uint4 w) {
+    atomicAdd(&cnt[w.x & 0xffffu], 1u);
+    atomicAdd(&cnt[w.x >> 16], 1u);
+    atomicAdd(&cnt[w.y & 0xffffu], 1u);
+    atomicAdd(&cnt[w.y >> 16], 1u);
+    atomicAdd(&cnt[w.z & 0xffffu], 1u);
+    atomicAdd(&cnt[w.z >> 16], 1u);
+    atomicAdd(&cnt[w.w & 0xffffu], 1u);
+    atomicAdd(&cnt[w.w >> 16], 1u);
+}
+
+// One id per lane, all 64 lanes active.  A hub can hold a large share of its
+// bucket's entries (over 40% on R-MAT scale 24), and lanes of one instruction
+// that hit the same LDS counter serialise.  The wave keeps a candidate id
+// `hot` (wave-uniform): lanes holding it add their number through one lane.
+// When fewer than two lanes held it, the candidate moves to the first lane's
+// id, so a hub is picked up within a few instructions and then kept.
+__device__ __forceinline__ void count_hot(uint32_t* cnt, uint32_t x, uint32_t& hot) {
+    const bool h = x == hot;
+    const uint64_t m = ballot(h);
+    const uint32_t c = (uint32_t)__popcll(m);
+    if (c >= 2) {
+        if (!h || lanes_below(m) == 0) atomicAdd(&cnt[x], h ? c : 1u);
+    } else {
+        atomicAdd(&cnt[x], 1u);
+        hot = __builtin_amdgcn_readfirstlane(x);
+    }
+}
+
+__device__ __forceinline__ void count8_hot(uint32_t* cnt, uint4 w, uint32_t& hot) {
+    count_hot(cnt, w.x & 0xffffu, hot);
+    count_hot(cnt, w.x >> 16, hot);
+    count_hot(cnt, w.y & 0xffffu, hot);
+    count_hot(cnt, w.y >> 16, hot);
+    count_hot(cnt, w.z & 0xffffu, hot);
+    count_hot(cnt, w.z >> 16, hot);
+    count_hot(cnt, w.w & 0xffffu, hot);
+    count_hot(cnt, w.w >> 16, hot);
+}
 
 __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     const uint16_t* __restrict__ loc, const unsigned long long* __restrict__ base, int32_t n,
@@ -420,34 +494,32 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
         for (int j = threadIdx.x; j < nv; j += kBlockD) cnt[j] = (uint32_t)deg[x0 + j];
     }
     if (count_pairs) {
-        // 8-byte loads of four ids between the first and last multiple of 4
-        // (loc is 256-byte aligned); the few entries outside one at a time.
-        // Plain LDS atomics: a hub's entries are spread over its bucket's
-        // range, so lanes of one wave rarely share a counter.
-        const unsigned long long a4 = (beg + 3) & ~3ull, e4 = end & ~3ull;
-        if (a4 >= e4) {
+        // 16-byte loads of eight ids between the first and last multiple of 8
+        // (loc is 256-byte aligned), kUnrollD of them in flight per thread:
+        // one block fills a CU, so the loads in flight must cover HBM latency
+        // by themselves.  The few entries outside go one at a time.  Plain LDS
+        // atomics: a hub's entries are spread over its bucket's range, so
+        // lanes of one wave rarely share a counter.
+        const unsigned long long a8 = (beg + 7) & ~7ull, e8 = end & ~7ull;
+        if (a8 >= e8) {
             for (unsigned long long i = beg + threadIdx.x; i < end; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
         } else {
-            for (unsigned long long i = beg + threadIdx.x; i < a4; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
-            for (unsigned long long i = e4 + threadIdx.x; i < end; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
-            const uint2* q = (const uint2*)(loc + a4);
-            const long long nq = (long long)((e4 - a4) >> 2);
-            for (long long j0 = 0; j0 < nq; j0 += (long long)kBlockD * kUnrollD) {
-                uint2 w[kUnrollD];
+            for (unsigned long long i = beg + threadIdx.x; i < a8; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
+            for (unsigned long long i = e8 + threadIdx.x; i < end; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
+            const uint4* q = (const uint4*)(loc + a8);
+            const long long nq = (long long)((e8 - a8) >> 3);
+            constexpr long long kStep = (long long)kBlockD * kUnrollD;
+            long long j0 = 0;
+            uint32_t hot = 0xffffffffu;   // no 16-bit id matches it
+            // every lane of every wave runs these iterations (j0 is uniform)
+            for (; j0 + kStep <= nq; j0 += kStep) {
+                uint4 w[kUnrollD];
 #pragma unroll
-                for (int r = 0; r < kUnrollD; ++r) {
-                    const long long j = j0 + threadIdx.x + (long long)r * kBlockD;
-                    w[r] = j < nq ? q[j] : make_uint2(0xffffffffu, 0xffffffffu);
-                }
+                for (int r = 0; r < kUnrollD; ++r) w[r] = q[j0 + threadIdx.x + (long long)r * kBlockD];
 #pragma unroll
-                for (int r = 0; r < kUnrollD; ++r) {
-                    if (w[r].x == 0xffffffffu && w[r].y == 0xffffffffu) continue;   // past the end
-                    atomicAdd(&cnt[w[r].x & 0xffffu], 1u);
-                    atomicAdd(&cnt[w[r].x >> 16], 1u);
-                    atomicAdd(&cnt[w[r].y & 0xffffu], 1u);
-                    atomicAdd(&cnt[w[r].y >> 16], 1u);
-                }
+                for (int r = 0; r < kUnrollD; ++r) count8_hot(cnt, w[r], hot);
             }
+            for (long long j = j0 + threadIdx.x; j < nq; j += kBlockD) count8(cnt, q[j]);
         }
     }
     __syncthreads();
@@ -671,6 +743,7 @@ int bucket_plan(int32_t n, int64_t m, BucketPlan* p) {
     p->B = (int32_t)(((int64_t)n + kBsz - 1) >> kShift);
     if (p->B < 1) p->B = 1;
     if (p->B > kMaxBuckets) return -1;
+    if (m < 0 || m >= ((int64_t)1 << 31)) return -1;   // 32-bit prefixes and output slots
     int64_t nblk = (m + 65535) / 65536;   // ~64K edges per block chunk
     if (nblk < 1) nblk = 1;
     if (nblk > kScanThreads) nblk = kScanThreads;

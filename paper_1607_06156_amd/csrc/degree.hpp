@@ -32,8 +32,8 @@ struct BucketBufs {
     bool other_written = false;
 };
 
-// returns -1 if n is too large for the bucketed pass (m must be < 2^31: the
-// per-bucket prefixes are 32-bit)
+// returns -1 if n is too large for the bucketed pass or m >= 2^31 (the
+// per-bucket prefixes and the scatter's output slots are 32-bit)
 int bucket_plan(int32_t n, int64_t m, BucketPlan* p);
 
 // deg[n] (+ histograms when want_hist, + CSR off[n+1]/adj[2m] when want_csr).

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "degree.hpp"
@@ -50,29 +51,44 @@ int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* ta
     const int32_t C = (int32_t)cand.size();
     out->candidates = C;
     if (C == 0) return CC_OK;
-    // device copies: vals, tail_n, tail_s (V doubles each), cand, D, alpha
-    size_t bytes = (size_t)V * 3 * sizeof(double) + (size_t)C * (sizeof(int32_t) + 2 * sizeof(double)) + 64;
+    // device copies: vals, tail_n, tail_s (V doubles each), cand (C int32),
+    // then (8-byte aligned) the results D, alpha (C doubles each).  The inputs
+    // go up in one copy and the results come back in one, both through the
+    // pinned staging buffer when they fit in it.
+    const size_t in_bytes = (size_t)V * 3 * sizeof(double) + (size_t)C * sizeof(int32_t);
+    const size_t res_off = (in_bytes + 7) & ~(size_t)7;
+    const size_t res_bytes = (size_t)C * 2 * sizeof(double);
     void* dbuf;
-    int rc = ws.get(WS_KS, bytes, &dbuf);
+    int rc = ws.get(WS_KS, res_off + res_bytes, &dbuf);
     if (rc) return rc;
     double* dv = (double*)dbuf;
-    double* dn = dv + V;
-    double* dsum = dn + V;
-    double* dD = dsum + V;
+    int32_t* dc = (int32_t*)(dv + 3 * (size_t)V);
+    double* dD = (double*)((char*)dbuf + res_off);
     double* dA = dD + C;
-    int32_t* dc = (int32_t*)(dA + C);
+    std::vector<char> pageable;
+    char* h;
+    if (res_off + res_bytes <= Workspace::kHostBytes) {
+        void* hp;
+        if ((rc = ws.pinned(&hp))) return rc;
+        h = (char*)hp;
+    } else {
+        pageable.resize(res_off + res_bytes);
+        h = pageable.data();
+    }
+    std::memcpy(h, vals.data(), V * sizeof(double));
+    std::memcpy(h + V * sizeof(double), tn.data(), V * sizeof(double));
+    std::memcpy(h + 2 * V * sizeof(double), ts.data(), V * sizeof(double));
+    std::memcpy(h + 3 * V * sizeof(double), cand.data(), C * sizeof(int32_t));
     hipError_t e;
-    if ((e = hipMemcpyAsync(dv, vals.data(), V * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(dn, tn.data(), V * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(dsum, ts.data(), V * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(dc, cand.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(dbuf, h, in_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(ks inputs)");
-    if ((e = launch_ks_fit(dv, dn, dsum, V, dc, C, dD, dA, s)) != hipSuccess) return hip_fail(e, "ks_fit launch");
-    std::vector<double> hD(C), hA(C);
-    if ((e = hipMemcpyAsync(hD.data(), dD, C * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(hA.data(), dA, C * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    if ((e = launch_ks_fit(dv, dv + V, dv + 2 * (size_t)V, V, dc, C, dD, dA, s)) != hipSuccess)
+        return hip_fail(e, "ks_fit launch");
+    if ((e = hipMemcpyAsync(h + res_off, dD, res_bytes, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(ks results)");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const double* hD = (const double*)(h + res_off);
+    const double* hA = hD + C;
     int best = -1;
     for (int c = 0; c < C; ++c)
         if (best < 0 || hD[c] < hD[best]) best = c;

@@ -46,8 +46,8 @@ static void set_cursor_bufs(BucketBufs* w, void* po, int64_t m, bool csr) {
 int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     Workspace& ws = *c.ws;
     BucketPlan p;
-    if (bucket_plan(c.n, c.m, &p)) return fail(CC_EINVAL, "n too large for the degree pass");
     if (c.m >= (int64_t)1 << 31) return fail(CC_EINVAL, "m too large for the degree pass (m < 2^31)");
+    if (bucket_plan(c.n, c.m, &p)) return fail(CC_EINVAL, "n too large for the degree pass");
     r->plan = p;
     const int64_t m = c.m;
     void *pc, *po, *pp, *pdeg, *ptail;
