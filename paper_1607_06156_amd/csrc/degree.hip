@@ -159,33 +159,37 @@ __global__ __launch_bounds__(1024) void bucket_scan_kernel(const unsigned long l
 // buckets' ranges -- which bucket_split_kernel then splits.  A staged entry
 // packs (staging bucket << kKeyShift | local id).
 constexpr int kStageThreads = 1024;
+constexpr int kCUs = 256;   // compute units of one MI355X (launch sizing only)
 constexpr int kSub = 8;
 constexpr int kSuperShift = kShift + 3;
-// Tile sizes (measured on MI355X).  Ids alone (4 bytes of LDS per entry):
-// two blocks per CU, one edge chunk each.  With the other ends (8 bytes per
-// entry, CSR builds) one block per CU walks kChunks consecutive edge chunks
-// -- their runs are consecutive in the prefix layout, so the cursors simply
-// continue -- with a tile twice as long as two blocks could stage, which
-// makes the runs per bucket longer (2.7 ms instead of 3.1 ms on R-MAT scale
-// 24; the same change made the ids-only scatter slower, 1.5 ms against 1.3).
+// Tile size (measured on MI355X, R-MAT scale 24): one 1024-thread block per
+// CU with the longest tile its LDS holds.  Every tile extends each of the
+// block's runs (one per bucket) by 2E * 1024 / B entries on average, and with
+// a single block per CU the partly written cache lines at the ends of its
+// runs stay in the XCD's L2 until the next tiles complete them.  Ids only,
+// B = 512: 1.33 ms with 5 edges per thread and two blocks per CU, 1.20 ms
+// with 8, 1.13 ms with 12, 1.06 ms with 16 (one block per CU, all three).
+// With the other ends (8 bytes of LDS per entry) 8 edges per thread fit.
 template <bool OTHER>
 struct StageCfg {
-    static constexpr int kEdges = OTHER ? 6 : 5;   // edges per thread per tile
-    static constexpr int kWaves = OTHER ? 4 : 8;   // waves per SIMD (LDS, VGPRs)
-    static constexpr int kChunks = OTHER ? 4 : 1;  // edge chunks per block
+    static constexpr int kEdges = OTHER ? 8 : 16;   // edges per thread per tile
     static constexpr int kSlots = kStageThreads * kEdges * 2;
 };
+static_assert(StageCfg<false>::kSlots <= 65536 && StageCfg<true>::kSlots <= 65536, "ranks are packed in 16 bits");
 
+// Each block walks G consecutive edge chunks (their runs are consecutive in
+// the prefix layout, so the cursors simply continue).  The next tile's edges
+// are loaded while the current tile is staged and written out.
 template <bool OTHER, bool SUPER>
-__global__ __launch_bounds__(kStageThreads, StageCfg<OTHER>::kWaves) void bucket_scatter_staged_kernel(
-    const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m, int32_t n, int64_t chunk, int32_t B,
-    int32_t nblk, const uint32_t* __restrict__ prefix, const unsigned long long* __restrict__ base,
+__global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
+    const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m, int32_t n, int64_t chunk, int32_t G,
+    int32_t B, int32_t nblk, const uint32_t* __restrict__ prefix, const unsigned long long* __restrict__ base,
     uint16_t* __restrict__ loc, uint32_t* __restrict__ loc32, int32_t* __restrict__ other) {
     constexpr int E = StageCfg<OTHER>::kEdges;
-    constexpr int G = StageCfg<OTHER>::kChunks;
     constexpr int kSh = SUPER ? kSuperShift : kShift;      // staging bucket = id >> kSh
     constexpr int kKeyShift = SUPER ? kSuperShift : 16;    // key = staging bucket << kKeyShift | local
     constexpr uint32_t kLocalMask = (1u << kSh) - 1u;
+    constexpr int64_t kTile = (int64_t)kStageThreads * E;
     __shared__ uint32_t stage[StageCfg<OTHER>::kSlots];
     __shared__ int32_t stage_o[OTHER ? StageCfg<OTHER>::kSlots : 1];
     __shared__ uint32_t toff[kStagedMaxB + 1];
@@ -214,31 +218,27 @@ __global__ __launch_bounds__(kStageThreads, StageCfg<OTHER>::kWaves) void bucket
     const int64_t beg = (int64_t)c0 * chunk;
     int64_t end = beg + (int64_t)G * chunk;
     if (end > m) end = m;
-    for (int64_t t0 = beg; t0 < end; t0 += (int64_t)kStageThreads * E) {
+    // the thread's edges of the current tile (-1: past the end)
+    int32_t a[E], c[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int64_t i = beg + t + (int64_t)j * kStageThreads;
+        a[j] = i < end ? u[i] : -1;
+        c[j] = i < end ? v[i] : -1;
+    }
+    for (int64_t t0 = beg; t0 < end; t0 += kTile) {
         for (int k = t; k <= NB; k += kStageThreads) toff[k] = 0;
         __syncthreads();
-        uint32_t key[2 * E];
-        int32_t oth[2 * E];
-        uint32_t rank[2 * E];
-        bool ok[2 * E];
+        // rank of each endpoint within its bucket's part of the tile (16 bits
+        // each, both ends of edge j packed in r[j])
+        uint32_t r[E];
+        uint32_t okm = 0;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
-            const int64_t i = t0 + t + (int64_t)j * kStageThreads;
-            bool val = false;
-            int32_t a = 0, c = 0;
-            if (i < end) {
-                a = u[i];
-                c = v[i];
-                val = (uint32_t)a < (uint32_t)n && (uint32_t)c < (uint32_t)n;
-            }
-            ok[2 * j] = ok[2 * j + 1] = val;
-            key[2 * j] = ((uint32_t)(a >> kSh) << kKeyShift) | ((uint32_t)a & kLocalMask);
-            key[2 * j + 1] = ((uint32_t)(c >> kSh) << kKeyShift) | ((uint32_t)c & kLocalMask);
-            oth[2 * j] = c;
-            oth[2 * j + 1] = a;
-            if (val) {
-                rank[2 * j] = atomicAdd(&toff[a >> kSh], 1u);
-                rank[2 * j + 1] = atomicAdd(&toff[c >> kSh], 1u);
+            r[j] = 0;
+            if ((uint32_t)a[j] < (uint32_t)n && (uint32_t)c[j] < (uint32_t)n) {
+                okm |= 1u << j;
+                r[j] = atomicAdd(&toff[a[j] >> kSh], 1u) | (atomicAdd(&toff[c[j] >> kSh], 1u) << 16);
             }
         }
         __syncthreads();
@@ -263,26 +263,40 @@ __global__ __launch_bounds__(kStageThreads, StageCfg<OTHER>::kWaves) void bucket
             const uint32_t ex = wsum[t >> 6] + incl - s;
             // staged slot i of bucket k goes to output slot rb[k] + i
             if (2 * t < NB) {
-                const uint32_t r = run[2 * t];
+                const uint32_t q = run[2 * t];
                 toff[2 * t] = ex;
-                rb[2 * t] = r - ex;
-                run[2 * t] = r + n0;
+                rb[2 * t] = q - ex;
+                run[2 * t] = q + n0;
             }
             if (2 * t + 1 < NB) {
-                const uint32_t r = run[2 * t + 1];
+                const uint32_t q = run[2 * t + 1];
                 toff[2 * t + 1] = ex + n0;
-                rb[2 * t + 1] = r - (ex + n0);
-                run[2 * t + 1] = r + n1;
+                rb[2 * t + 1] = q - (ex + n0);
+                run[2 * t + 1] = q + n1;
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 2 * E; ++j)
-            if (ok[j]) {
-                const uint32_t slot = toff[key[j] >> kKeyShift] + rank[j];
-                stage[slot] = key[j];
-                if (OTHER) stage_o[slot] = oth[j];
+        for (int j = 0; j < E; ++j)
+            if (okm & (1u << j)) {
+                const uint32_t ka = ((uint32_t)(a[j] >> kSh) << kKeyShift) | ((uint32_t)a[j] & kLocalMask);
+                const uint32_t kc = ((uint32_t)(c[j] >> kSh) << kKeyShift) | ((uint32_t)c[j] & kLocalMask);
+                const uint32_t sa = toff[a[j] >> kSh] + (r[j] & 0xffffu);
+                const uint32_t sc = toff[c[j] >> kSh] + (r[j] >> 16);
+                stage[sa] = ka;
+                stage[sc] = kc;
+                if (OTHER) {
+                    stage_o[sa] = c[j];
+                    stage_o[sc] = a[j];
+                }
             }
+        // the next tile's edges: in flight during the barrier and the write-out
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int64_t i = t0 + kTile + t + (int64_t)j * kStageThreads;
+            a[j] = i < end ? u[i] : -1;
+            c[j] = i < end ? v[i] : -1;
+        }
         __syncthreads();
         // contiguous runs per bucket: staged slot i -> its bucket's next free slot
         const uint32_t total = toff[NB];
@@ -756,14 +770,15 @@ int bucket_plan(int32_t n, int64_t m, BucketPlan* p) {
 template <bool OTHER>
 static void scatter_with(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
                          const BucketBufs& w, hipStream_t s) {
-    const int G = StageCfg<OTHER>::kChunks;
+    // chunks per block: about one block per CU once there are enough chunks
+    const int G = p.nblk >= 2 * kCUs ? p.nblk / kCUs : 1;
     const int grid = (p.nblk + G - 1) / G;
     if (p.B <= kStagedMaxB) {
         bucket_scatter_staged_kernel<OTHER, false><<<grid, kStageThreads, 0, s>>>(
-            u, v, m, n, p.chunk, p.B, p.nblk, w.counts, w.base, w.loc, nullptr, OTHER ? w.other : nullptr);
+            u, v, m, n, p.chunk, G, p.B, p.nblk, w.counts, w.base, w.loc, nullptr, OTHER ? w.other : nullptr);
     } else {
         bucket_scatter_staged_kernel<OTHER, true><<<grid, kStageThreads, 0, s>>>(
-            u, v, m, n, p.chunk, p.B, p.nblk, w.counts, w.base, nullptr, w.loc32, OTHER ? w.other32 : nullptr);
+            u, v, m, n, p.chunk, G, p.B, p.nblk, w.counts, w.base, nullptr, w.loc32, OTHER ? w.other32 : nullptr);
         bucket_split_kernel<OTHER><<<(p.B + kSub - 1) / kSub, kStageThreads, 0, s>>>(
             w.loc32, OTHER ? w.other32 : nullptr, w.base, p.B, w.loc, OTHER ? w.other : nullptr);
     }
