@@ -313,17 +313,25 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
 
 // Second level for n > 2^26: block S splits super-bucket S (its range is the
 // concatenation of buckets 8S .. 8S+7) into those buckets.  A tile of entries
-// is grouped by bucket in LDS (wave ballots rank the entries, one LDS atomic
-// per wave and bucket) and each bucket's part leaves as one contiguous run.
-constexpr int kSplitE = 4;
+// is grouped by bucket in LDS and each bucket's part leaves as one contiguous
+// run.  Ranking is a wave multisplit over the 3-bit bucket index: three
+// ballots give every lane the mask of lanes with its bucket, the lowest of
+// them reserves the wave's slots with one LDS atomic, and the rank is the
+// number of such lanes below.  The next tile is loaded during the write-out.
+template <bool OTHER>
+struct SplitCfg {
+    static constexpr int kE = OTHER ? 8 : 16;   // entries per thread per tile
+};
 template <bool OTHER>
 __global__ __launch_bounds__(kStageThreads) void bucket_split_kernel(const uint32_t* __restrict__ loc32,
                                                                      const int32_t* __restrict__ other32,
                                                                      const unsigned long long* __restrict__ base,
                                                                      int32_t B, uint16_t* __restrict__ loc,
                                                                      int32_t* __restrict__ other) {
-    __shared__ uint32_t stage[kStageThreads * kSplitE];
-    __shared__ int32_t stage_o[OTHER ? kStageThreads * kSplitE : 1];
+    constexpr int E = SplitCfg<OTHER>::kE;
+    constexpr uint32_t kNone = 0xffffffffu;   // past the end (local ids have 18 bits)
+    __shared__ uint32_t stage[kStageThreads * E];
+    __shared__ int32_t stage_o[OTHER ? kStageThreads * E : 1];
     __shared__ uint32_t cnt[kSub + 1];
     __shared__ unsigned long long cur[kSub];
     const int t = threadIdx.x;
@@ -331,29 +339,30 @@ __global__ __launch_bounds__(kStageThreads) void bucket_split_kernel(const uint3
     const int k1 = k0 + kSub < B ? k0 + kSub : B;
     const unsigned long long beg = base[k0], end = base[k1];
     if (t < kSub) cur[t] = k0 + t < k1 ? base[k0 + t] : 0ull;
-    for (unsigned long long t0 = beg; t0 < end; t0 += (unsigned long long)kStageThreads * kSplitE) {
+    uint32_t q[E];
+    int32_t o[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const unsigned long long i = beg + t + (unsigned long long)j * kStageThreads;
+        q[j] = i < end ? loc32[i] : kNone;
+        o[j] = (OTHER && i < end) ? other32[i] : 0;
+    }
+    for (unsigned long long t0 = beg; t0 < end; t0 += (unsigned long long)kStageThreads * E) {
         if (t <= kSub) cnt[t] = 0;
         __syncthreads();
-        uint32_t q[kSplitE], rank[kSplitE];
-        int32_t o[kSplitE];
-        bool ok[kSplitE];
+        uint32_t rank[E];
 #pragma unroll
-        for (int j = 0; j < kSplitE; ++j) {
-            const unsigned long long i = t0 + t + (unsigned long long)j * kStageThreads;
-            ok[j] = i < end;
-            q[j] = ok[j] ? loc32[i] : 0u;
-            o[j] = (OTHER && ok[j]) ? other32[i] : 0;
-            const int sub = ok[j] ? (int)(q[j] >> kShift) : -1;
-            rank[j] = 0;
-            for (int s = 0; s < kSub; ++s) {
-                const uint64_t mk = ballot(sub == s);
-                if (mk) {
-                    uint32_t b0 = 0;
-                    if (lane_id() == 0) b0 = atomicAdd(&cnt[s], (uint32_t)__popcll(mk));
-                    b0 = __shfl(b0, 0);
-                    if (sub == s) rank[j] = b0 + lanes_below(mk);
-                }
-            }
+        for (int j = 0; j < E; ++j) {
+            const bool ok = q[j] != kNone;
+            const uint32_t sub = ok ? q[j] >> kShift : 0u;
+            const uint64_t b0 = ballot(sub & 1u), b1 = ballot(sub & 2u), b2 = ballot(sub & 4u);
+            const uint64_t same = ballot(ok) & ((sub & 1u) ? b0 : ~b0) & ((sub & 2u) ? b1 : ~b1) &
+                                  ((sub & 4u) ? b2 : ~b2);
+            const uint32_t below = lanes_below(same);
+            uint32_t r0 = 0;
+            if (ok && below == 0) r0 = atomicAdd(&cnt[sub], (uint32_t)__popcll(same));
+            r0 = __shfl(r0, __builtin_ctzll(same | (1ull << 63)) & 63);
+            rank[j] = r0 + below;
         }
         __syncthreads();
         if (t == 0) {
@@ -363,12 +372,19 @@ __global__ __launch_bounds__(kStageThreads) void bucket_split_kernel(const uint3
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < kSplitE; ++j)
-            if (ok[j]) {
+        for (int j = 0; j < E; ++j)
+            if (q[j] != kNone) {
                 const uint32_t slot = cnt[q[j] >> kShift] + rank[j];
                 stage[slot] = q[j];
                 if (OTHER) stage_o[slot] = o[j];
             }
+        // the next tile's entries: in flight during the barrier and the write-out
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const unsigned long long i = t0 + (unsigned long long)kStageThreads * E + t + (unsigned long long)j * kStageThreads;
+            q[j] = i < end ? loc32[i] : kNone;
+            o[j] = (OTHER && i < end) ? other32[i] : 0;
+        }
         __syncthreads();
         const uint32_t total = cnt[kSub];
         for (uint32_t i = t; i < total; i += kStageThreads) {
@@ -490,7 +506,7 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     int32_t* __restrict__ deg, int count_pairs, int want_hist, unsigned long long* __restrict__ hist64,
     unsigned long long* __restrict__ histx, int32_t* __restrict__ tail, int64_t tail_cap,
     unsigned long long* __restrict__ tail_count, unsigned long long* __restrict__ argmax_key, int want_off,
-    int64_t* __restrict__ off) {
+    int64_t* __restrict__ off, uint32_t* __restrict__ gcnt) {
     __shared__ uint32_t cnt[kBsz];
     __shared__ HistLds L;
     __shared__ uint32_t wsum[kBlockD / 64];
@@ -574,66 +590,151 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     __syncthreads();
     for (int j = t; j < nv; j += kBlockD) off[x0 + j] = (int64_t)(beg + cnt[j]);
     if (x0 + nv == n && t == 0) off[n] = (int64_t)end;
+    // the CSR fill's per-group counters of this bucket start at zero
+    if (gcnt)
+        for (int g = t; g < kGroups; g += kBlockD) gcnt[(int64_t)k * kGroups + g] = 0;
 }
 
 // ------------------------------------------------------------ CSR fill
 // The CSR's rows are filled in two steps, so that every write to adj[] lands
 // in a window small enough to assemble in LDS:
-//  S. one block per bucket regroups the bucket's entries by group of
-//     2^kGrpShift vertices into tmp arrays indexed like adj[] (a group's
-//     entries take exactly its rows' slots, [off[x_g], off[x_g + 256]));
+//  S. the bucket's entries are regrouped by group of 2^kGrpShift vertices
+//     into tmp arrays indexed like adj[] (a group's entries take exactly its
+//     rows' slots, [off[x_g], off[x_g + 256]));
 //  F. one block per run of groups places each group's entries into an LDS
 //     copy of the group's rows and writes the copy out contiguously (groups
 //     whose rows exceed the window write straight to adj[]).
-constexpr int kGrpShift = 8;
 constexpr int kGrpV = 1 << kGrpShift;            // vertices per group
-constexpr int kGroups = kBsz >> kGrpShift;       // groups per bucket
-constexpr int kGrpE = 4;                         // entries per thread per tile (S)
+constexpr int kGrpE = 8;                         // entries per thread per tile (S)
+constexpr int kGrpSlice = 1 << 17;               // about this many entries per block (S)
+constexpr int kWcStride = kStageThreads / 64 + 1;   // per-wave group counters, padded against bank conflicts
 constexpr int kFillThreads = 1024;
 constexpr int kWin = 16384;                      // adjacency entries assembled in LDS (F)
 constexpr int kFillU = 4;                        // entries per thread per step (F)
 
+// Rank of this lane's entry among the wave's entries of group g so far (the
+// wave's counter for g is wc[g * kWcStride + w]).  Lanes holding the wave's
+// candidate group `hot` (wave-uniform; it follows the first valid lane when
+// fewer than two lanes held it) reserve together through one lane: a hub can
+// put over 40% of its bucket's entries into one group.  Called by all lanes.
+__device__ __forceinline__ uint32_t group_rank(uint32_t* wc, int w, uint32_t g, bool ok, uint32_t& hot) {
+    const bool h = ok && g == hot;
+    const uint64_t m = ballot(h);
+    const uint32_t c = (uint32_t)__popcll(m);
+    uint32_t r = 0;
+    if (c >= 2) {
+        const uint32_t below = lanes_below(m);
+        if (h && below == 0) r = atomicAdd(&wc[hot * kWcStride + w], c);
+        r = __shfl(r, __builtin_ctzll(m));
+        if (h) r += below;
+        else if (ok) r = atomicAdd(&wc[g * kWcStride + w], 1u);
+    } else {
+        if (ok) r = atomicAdd(&wc[g * kWcStride + w], 1u);
+        const uint64_t am = ballot(ok);
+        if (am) hot = __shfl(g, __builtin_ctzll(am));
+    }
+    return r;
+}
+
+// S. Block (k, s) regroups slice s of bucket k (S slices per bucket).  It
+// counts the slice's entries per group, reserves that many slots of each
+// group's range with one global atomic per group (so slices finish in any
+// order and a row's entries are in no fixed order), then places the slice
+// tile by tile: entries grouped by (group, wave) in LDS, each group's part of
+// the tile written as one run.
 __global__ __launch_bounds__(kStageThreads) void csr_group_kernel(const uint16_t* __restrict__ loc,
                                                                   const int32_t* __restrict__ other,
                                                                   const unsigned long long* __restrict__ base,
-                                                                  const int64_t* __restrict__ off, int32_t n,
+                                                                  const int64_t* __restrict__ off, int32_t n, int32_t S,
+                                                                  uint32_t* __restrict__ gcnt,
                                                                   uint16_t* __restrict__ tloc,
                                                                   int32_t* __restrict__ tother) {
     constexpr int kW = kStageThreads / 64;   // waves
     __shared__ uint16_t sl[kStageThreads * kGrpE];
     __shared__ int32_t so[kStageThreads * kGrpE];
-    // per-wave counts, group-major ([g][w]), turned into slot offsets by one scan
-    __shared__ uint32_t wc[kGroups * kW];
+    __shared__ uint32_t wc[kGroups * kWcStride];
     __shared__ uint32_t gstart[kGroups + 1];
     __shared__ uint32_t wsum[kStageThreads / 64];
     __shared__ unsigned long long cur[kGroups];
     const int t = threadIdx.x, w = t >> 6;
-    const int k = blockIdx.x;
+    const int k = blockIdx.x / S, sidx = blockIdx.x % S;
     const int64_t x0 = (int64_t)k << kShift;
-    const unsigned long long beg = base[k], end = base[k + 1];
-    for (int g = t; g < kGroups; g += kStageThreads) {
-        const int64_t x = x0 + ((int64_t)g << kGrpShift);
-        cur[g] = x < n ? (unsigned long long)off[x] : end;
+    const unsigned long long bb = base[k], be = base[k + 1];
+    const unsigned long long len = (be - bb + S - 1) / S;
+    unsigned long long beg = bb + (unsigned long long)sidx * len;
+    if (beg > be) beg = be;
+    const unsigned long long end = beg + len < be ? beg + len : be;
+    uint32_t hot = 0xffffffffu;   // no group index matches it
+    // 1. the slice's entries per group: 16-byte loads of eight ids between the
+    //    first and last multiple of 8 (loc is 256-byte aligned), the rest one by one
+    for (int i = t; i < kGroups * kWcStride; i += kStageThreads) wc[i] = 0;
+    __syncthreads();
+    {
+        const unsigned long long a8 = (beg + 7) & ~7ull, e8 = end & ~7ull;
+        if (a8 >= e8) {
+            for (unsigned long long i = beg + t; i < end; i += kStageThreads)
+                atomicAdd(&wc[(loc[i] >> kGrpShift) * kWcStride + w], 1u);
+        } else {
+            for (unsigned long long i = beg + t; i < a8; i += kStageThreads)
+                atomicAdd(&wc[(loc[i] >> kGrpShift) * kWcStride + w], 1u);
+            for (unsigned long long i = e8 + t; i < end; i += kStageThreads)
+                atomicAdd(&wc[(loc[i] >> kGrpShift) * kWcStride + w], 1u);
+            const uint4* q4 = (const uint4*)(loc + a8);
+            const long long nq = (long long)((e8 - a8) >> 3);
+            for (long long j0 = 0; j0 < nq; j0 += 2 * kStageThreads) {   // uniform trip count
+                uint4 x[2];
+                bool okx[2];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const long long j = j0 + t + (long long)r * kStageThreads;
+                    okx[r] = j < nq;
+                    x[r] = okx[r] ? q4[j] : make_uint4(0, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const uint32_t wv[4] = {x[r].x, x[r].y, x[r].z, x[r].w};
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        (void)group_rank(wc, w, (wv[h] & 0xffffu) >> kGrpShift, okx[r], hot);
+                        (void)group_rank(wc, w, wv[h] >> (16 + kGrpShift), okx[r], hot);
+                    }
+                }
+            }
+        }
     }
+    __syncthreads();
+    // 2. reserve the slice's slots in each group's range
+    if (t < kGroups) {
+        uint32_t c = 0;
+        for (int q = 0; q < kW; ++q) c += wc[t * kWcStride + q];
+        const int64_t x = x0 + ((int64_t)t << kGrpShift);
+        unsigned long long r = 0;
+        if (c) r = __hip_atomic_fetch_add(&gcnt[(int64_t)k * kGroups + t], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        cur[t] = (x < n ? (unsigned long long)off[x] : be) + r;
+    }
+    __syncthreads();
+    // 3. place the slice
     for (unsigned long long t0 = beg; t0 < end; t0 += (unsigned long long)kStageThreads * kGrpE) {
-        for (int i = t; i < kGroups * kW; i += kStageThreads) wc[i] = 0;
+        for (int i = t; i < kGroups * kWcStride; i += kStageThreads) wc[i] = 0;
         __syncthreads();
-        uint16_t q[kGrpE];
+        uint32_t q[kGrpE], rank[kGrpE];
         int32_t o[kGrpE];
-        uint32_t rank[kGrpE];
         bool ok[kGrpE];
 #pragma unroll
         for (int j = 0; j < kGrpE; ++j) {
             const unsigned long long i = t0 + t + (unsigned long long)j * kStageThreads;
             ok[j] = i < end;
-            q[j] = ok[j] ? loc[i] : (uint16_t)0;
+            q[j] = ok[j] ? loc[i] : 0u;
             o[j] = ok[j] ? other[i] : 0;
-            rank[j] = ok[j] ? atomicAdd(&wc[(q[j] >> kGrpShift) * kW + w], 1u) : 0u;
         }
+#pragma unroll
+        for (int j = 0; j < kGrpE; ++j) rank[j] = group_rank(wc, w, q[j] >> kGrpShift, ok[j], hot);
         __syncthreads();
-        // exclusive scan of wc[0 .. kGroups * kW) (2 entries per thread)
+        // exclusive scan of the (group, wave) counts in group-major order
+        // (2 entries per thread, both of one group)
         {
-            const uint32_t c0 = wc[2 * t], c1 = wc[2 * t + 1], sm = c0 + c1;
+            const int g = (2 * t) / kW, wv = (2 * t) % kW;
+            const uint32_t c0 = wc[g * kWcStride + wv], c1 = wc[g * kWcStride + wv + 1], sm = c0 + c1;
             uint32_t incl = sm;
             for (int d = 1; d < 64; d <<= 1) {
                 const uint32_t y = __shfl_up(incl, d);
@@ -648,16 +749,16 @@ __global__ __launch_bounds__(kStageThreads) void csr_group_kernel(const uint16_t
             }
             __syncthreads();
             const uint32_t ex = wsum[w] + incl - sm;
-            wc[2 * t] = ex;
-            wc[2 * t + 1] = ex + c0;
+            wc[g * kWcStride + wv] = ex;
+            wc[g * kWcStride + wv + 1] = ex + c0;
         }
         __syncthreads();
-        if (t < kGroups) gstart[t] = wc[t * kW];
+        if (t < kGroups) gstart[t] = wc[t * kWcStride];
 #pragma unroll
         for (int j = 0; j < kGrpE; ++j)
             if (ok[j]) {
-                const uint32_t slot = wc[(q[j] >> kGrpShift) * kW + w] + rank[j];
-                sl[slot] = q[j];
+                const uint32_t slot = wc[(q[j] >> kGrpShift) * kWcStride + w] + rank[j];
+                sl[slot] = (uint16_t)q[j];
                 so[slot] = o[j];
             }
         __syncthreads();
@@ -794,7 +895,12 @@ static hipError_t launch_scatter(const int32_t* u, const int32_t* v, int64_t m, 
 // steps S and F of the CSR fill (offsets already in off[])
 static hipError_t launch_csr_fill(int64_t m, int32_t n, const BucketPlan& p, const BucketBufs& w, const int64_t* off,
                                   int32_t* adj, hipStream_t s) {
-    csr_group_kernel<<<p.B, kStageThreads, 0, s>>>(w.loc, w.other, w.base, off, n, w.tloc, w.tother);
+    // slices per bucket: about kGrpSlice entries each
+    int64_t S = (2 * m / p.B + kGrpSlice - 1) / kGrpSlice;
+    if (S < 1) S = 1;
+    if (S > 64) S = 64;
+    csr_group_kernel<<<(unsigned)(p.B * S), kStageThreads, 0, s>>>(w.loc, w.other, w.base, off, n, (int32_t)S, w.gcnt,
+                                                                   w.tloc, w.tother);
     const int64_t ngroups = ((int64_t)n + kGrpV - 1) >> kGrpShift;
     // runs of groups per block: about one LDS window of entries each
     const int64_t avg = ngroups > 0 ? (2 * m) / ngroups : 0;
@@ -816,7 +922,7 @@ hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_
         w.other_written = true;
     }
     bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, w.base, n, deg, 0, 0, nullptr, nullptr, nullptr, 0, nullptr,
-                                                  nullptr, 1, off);
+                                                  nullptr, 1, off, w.gcnt);
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : launch_csr_fill(m, n, p, w, off, adj, s);
 }
@@ -837,7 +943,7 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
     if (e != hipSuccess) return e;
     w.other_written = want_csr != 0;
     bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, w.base, n, deg, 1, want_hist, hist64, histx, tail, tail_cap,
-                                                  tail_count, argmax_key, want_csr, off);
+                                                  tail_count, argmax_key, want_csr, off, want_csr ? w.gcnt : nullptr);
     e = hipGetLastError();
     if (e != hipSuccess || !want_csr) return e;
     return launch_csr_fill(m, n, p, w, off, adj, s);

@@ -11,6 +11,8 @@ constexpr int kMaxBuckets = 16384;    // n <= 2^29 for the bucketed degree pass
 constexpr int kExactBins = 4096;      // exact degree histogram below this
 constexpr int kBlockD = 1024;         // threads of the per-bucket kernel
 constexpr int kStagedMaxB = 2048;     // one-level scatter up to this many buckets (n <= 2^26), else two levels
+constexpr int kGrpShift = 8;          // CSR fill: vertices per group = 2^kGrpShift
+constexpr int kGroups = 1 << (kBucketShift - kGrpShift);   // groups per bucket
 
 struct BucketPlan {
     int32_t B;       // vertex buckets
@@ -29,6 +31,7 @@ struct BucketBufs {
     uint16_t* tloc;              // [2m] CSR fill: entries regrouped by 256-vertex group
     int32_t* tother;             // [2m]
     unsigned long long* err;     // range errors
+    uint32_t* gcnt;              // [B * kGroups] CSR fill: entries of each group placed so far
     bool other_written = false;
 };
 

@@ -52,9 +52,11 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     const int64_t m = c.m;
     void *pc, *po, *pp, *pdeg, *ptail;
     int rc;
-    // WS_HIST: per-block bucket counts, then (8-byte aligned) totals, bases, error counter
+    // WS_HIST: per-block bucket counts, then (8-byte aligned) totals, bases,
+    // error counter, then the CSR fill's per-group counters
     const size_t counts_bytes = ((size_t)p.nblk * p.B * sizeof(uint32_t) + 255) & ~(size_t)255;
-    if ((rc = ws.get(WS_HIST, counts_bytes + (size_t)(2 * p.B + 2) * sizeof(unsigned long long), &pc))) return rc;
+    const size_t tot_bytes = (size_t)(2 * p.B + 2) * sizeof(unsigned long long);
+    if ((rc = ws.get(WS_HIST, counts_bytes + tot_bytes + (size_t)p.B * kGroups * sizeof(uint32_t), &pc))) return rc;
     if (p.B > kStagedMaxB || want_csr) {
         // the first level of the two-level scatter (32-bit ids, + other ends
         // for a CSR) and, later, the CSR fill's regrouped entries share it
@@ -73,6 +75,7 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     w.tot = (unsigned long long*)((char*)pc + counts_bytes);
     w.base = w.tot + p.B;
     w.err = w.base + p.B + 1;
+    w.gcnt = (uint32_t*)((char*)pc + counts_bytes + tot_bytes);
     set_cursor_bufs(&w, po, m, want_csr);
     w.loc = (uint16_t*)pp;
     w.other = (int32_t*)((char*)pp + loc_bytes);
