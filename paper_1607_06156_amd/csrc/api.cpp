@@ -232,11 +232,26 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                 rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)(e1 - e0));
             }
         } else {
-            int k0 = c.kbeg();
-            e = launch_sv_pass_seg(in, c.parent, out, write ? 1 : 0, max_link, (int32_t*)phook, hooked_count,
-                                   totals, c.stream);
-            if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
-            rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)m_in);
+            // a long list handed over by an earlier step (the edges a BFS left)
+            // gets the same chunked first pass as the caller's list
+            const int segchunks = pass == 0 ? pass0_chunks(m_in, c.n) : 1;
+            const int per = (nseg + segchunks - 1) / segchunks;
+            for (int s0 = 0; s0 < nseg; s0 += per) {
+                if (s0 > 0) {
+                    int kf = c.kbeg();
+                    e = launch_sv_finalize(c.parent, c.n, c.stream);
+                    if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
+                    c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n);
+                    flat_bytes += 12.0 * c.n;
+                }
+                const int nb = std::min(per, nseg - s0);
+                int k0 = c.kbeg();
+                e = launch_sv_pass_seg(in, s0, nb, c.parent, out, write ? 1 : 0, max_link, (int32_t*)phook,
+                                       hooked_count, totals, c.stream);
+                if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
+                // this chunk's share of the edges (segments hold about equal counts)
+                rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)m_in * nb / nseg);
+            }
         }
         e = launch_sv_totals(hooked_count, out.count, nseg, totals, c.stream);
         if (e != hipSuccess) return hip_fail(e, "sv_totals launch");

@@ -89,9 +89,11 @@ hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s);
 hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
                               SegList out, int32_t seg0, int32_t nblocks, int write_out, int max_link,
                               int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals, hipStream_t s);
-// later passes over a segmented list
-hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int max_link, int32_t* hooked,
-                              uint32_t* hooked_count, unsigned long long* totals, hipStream_t s);
+// passes over a segmented list: segments [seg0, seg0 + nblocks) of in, each
+// one block, survivors to the same segments of out
+hipError_t launch_sv_pass_seg(SegList in, int32_t seg0, int32_t nblocks, int32_t* parent, SegList out, int write_out,
+                              int max_link, int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
+                              hipStream_t s);
 // pointer-jumps the hooked roots of each segment (no hook may run concurrently)
 hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count, int64_t cap,
                               int32_t nseg, hipStream_t s);

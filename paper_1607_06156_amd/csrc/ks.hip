@@ -9,7 +9,8 @@
 //     derivative of E_alpha[ln d] is -Var_alpha[ln d]);
 //   * all threads then evaluate the model CDF 1 - zeta(alpha, d+1)/zeta(alpha,
 //     d_min) at every observed degree and just before the next one, and the
-//     block reduces the largest gap to the empirical CDF.
+//     block reduces the largest gap to the empirical CDF (stopping early once
+//     the candidate cannot be the best one).
 // The Hurwitz zeta function and its first two s-derivatives come from the
 // Euler-Maclaurin formula (direct terms up to argument 20, 7 Bernoulli
 // corrections), in fp64.
@@ -124,35 +125,63 @@ __device__ double solve_alpha(double dmin, double target) {
     return a;
 }
 
-// one block per candidate index c: tail starts at distinct value i0 = cand[c]
+// One block per candidate c (tail starts at distinct value i0 = cand[c]).
+// The statistic is a maximum over the observed degrees, and only the smallest
+// one is wanted, so a candidate can stop as soon as its running maximum
+// exceeds the smallest complete statistic found so far (*best, an fp64 bit
+// pattern: non-negative doubles order like their bits).  Phase 0 evaluates
+// every stride-th candidate in full to set *best; phase 1 evaluates the rest
+// and drops those that exceed it (reported as +inf).  The minimising
+// candidates, ties included, never exceed *best, so they are evaluated in
+// full: the result is the same as without the cut.
 __global__ __launch_bounds__(kKsBlock) void ks_fit_kernel(const double* __restrict__ vals,
                                                           const double* __restrict__ tail_n,
                                                           const double* __restrict__ tail_s, int32_t V,
-                                                          const int32_t* __restrict__ cand,
+                                                          const int32_t* __restrict__ cand, int32_t C,
+                                                          int32_t stride, int32_t phase,
+                                                          unsigned long long* __restrict__ best,
                                                           double* __restrict__ outD, double* __restrict__ outA) {
     __shared__ double sh_alpha, sh_z0;
     __shared__ double red[kKsBlock / 64];
-    const int i0 = cand[blockIdx.x];
+    __shared__ int stop;
+    const int c = phase == 0 ? blockIdx.x * stride : blockIdx.x;
+    if (c >= C || (phase == 1 && c % stride == 0)) return;   // block-uniform
+    const int i0 = cand[c];
     const double dmin = vals[i0];
     const double N = tail_n[i0];
     if (threadIdx.x == 0) {
         double a = solve_alpha(dmin, tail_s[i0] / N);
         sh_alpha = a;
         sh_z0 = hurwitz(a, dmin);
+        stop = 0;
     }
     __syncthreads();
     const double a = sh_alpha, z0 = sh_z0;
     double dev = 0.0;
-    for (int j = i0 + threadIdx.x; j < V; j += kKsBlock) {
-        // empirical CDF at vals[j]: share of the tail with degree <= vals[j]
-        const double S = (N - (j + 1 < V ? tail_n[j + 1] : 0.0)) / N;
-        const double Fat = 1.0 - hurwitz(a, vals[j] + 1.0) / z0;
-        double d = fabs(S - Fat);
-        if (j + 1 < V) {
-            const double Fb = 1.0 - hurwitz(a, vals[j + 1]) / z0;
-            d = fmax(d, fabs(S - Fb));
+    for (int j0 = i0; j0 < V; j0 += kKsBlock) {
+        // the bound is loaded first: its latency hides behind the evaluation
+        const double bound = phase == 1 ? __longlong_as_double((long long)__hip_atomic_load(
+                                              best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                                        : INFINITY;
+        const int j = j0 + threadIdx.x;
+        if (j < V) {
+            // empirical CDF at vals[j]: share of the tail with degree <= vals[j]
+            const double S = (N - (j + 1 < V ? tail_n[j + 1] : 0.0)) / N;
+            const double Fat = 1.0 - hurwitz(a, vals[j] + 1.0) / z0;
+            double d = fabs(S - Fat);
+            if (j + 1 < V) {
+                const double Fb = 1.0 - hurwitz(a, vals[j + 1]) / z0;
+                d = fmax(d, fabs(S - Fb));
+            }
+            dev = fmax(dev, d);
         }
-        dev = fmax(dev, d);
+        if (phase == 1) {
+            double w = dev;
+            for (int o = 32; o > 0; o >>= 1) w = fmax(w, __shfl_xor(w, o));
+            if (w > bound) __hip_atomic_store(&stop, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(&stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)))
+                break;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o));
     if (lane_id() == 0) red[threadIdx.x >> 6] = dev;
@@ -160,15 +189,27 @@ __global__ __launch_bounds__(kKsBlock) void ks_fit_kernel(const double* __restri
     if (threadIdx.x == 0) {
         double b = 0.0;
         for (int w = 0; w < kKsBlock / 64; ++w) b = fmax(b, red[w]);
-        outD[blockIdx.x] = b;
-        outA[blockIdx.x] = a;
+        const bool cut = __hip_atomic_load(&stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+        outD[c] = cut ? INFINITY : b;
+        outA[c] = a;
+        if (!cut)
+            __hip_atomic_fetch_min(best, (unsigned long long)__double_as_longlong(b), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
+// about this many candidates are evaluated in full first
+constexpr int32_t kKsSample = 256;
+
 hipError_t launch_ks_fit(const double* vals, const double* tail_n, const double* tail_s, int32_t V,
-                         const int32_t* cand, int32_t C, double* outD, double* outA, hipStream_t s) {
+                         const int32_t* cand, int32_t C, unsigned long long* best, double* outD, double* outA,
+                         hipStream_t s) {
     if (C <= 0) return hipSuccess;
-    ks_fit_kernel<<<C, kKsBlock, 0, s>>>(vals, tail_n, tail_s, V, cand, outD, outA);
+    const int32_t stride = C > kKsSample ? (C + kKsSample - 1) / kKsSample : 1;
+    ks_fit_kernel<<<(C + stride - 1) / stride, kKsBlock, 0, s>>>(vals, tail_n, tail_s, V, cand, C, stride, 0, best,
+                                                                 outD, outA);
+    if (stride > 1)
+        ks_fit_kernel<<<C, kKsBlock, 0, s>>>(vals, tail_n, tail_s, V, cand, C, stride, 1, best, outD, outA);
     return hipGetLastError();
 }
 

@@ -51,18 +51,19 @@ int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* ta
     const int32_t C = (int32_t)cand.size();
     out->candidates = C;
     if (C == 0) return CC_OK;
-    // device copies: vals, tail_n, tail_s (V doubles each), cand (C int32),
-    // then (8-byte aligned) the results D, alpha (C doubles each).  The inputs
-    // go up in one copy and the results come back in one, both through the
-    // pinned staging buffer when they fit in it.
-    const size_t in_bytes = (size_t)V * 3 * sizeof(double) + (size_t)C * sizeof(int32_t);
+    // device copies: vals, tail_n, tail_s (V doubles each), the running best
+    // statistic (+inf bits), cand (C int32), then (8-byte aligned) the results
+    // D, alpha (C doubles each).  The inputs go up in one copy and the results
+    // come back in one, both through the pinned staging buffer when they fit.
+    const size_t in_bytes = ((size_t)V * 3 + 1) * sizeof(double) + (size_t)C * sizeof(int32_t);
     const size_t res_off = (in_bytes + 7) & ~(size_t)7;
     const size_t res_bytes = (size_t)C * 2 * sizeof(double);
     void* dbuf;
     int rc = ws.get(WS_KS, res_off + res_bytes, &dbuf);
     if (rc) return rc;
     double* dv = (double*)dbuf;
-    int32_t* dc = (int32_t*)(dv + 3 * (size_t)V);
+    unsigned long long* dbest = (unsigned long long*)(dv + 3 * (size_t)V);
+    int32_t* dc = (int32_t*)(dbest + 1);
     double* dD = (double*)((char*)dbuf + res_off);
     double* dA = dD + C;
     std::vector<char> pageable;
@@ -78,11 +79,13 @@ int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* ta
     std::memcpy(h, vals.data(), V * sizeof(double));
     std::memcpy(h + V * sizeof(double), tn.data(), V * sizeof(double));
     std::memcpy(h + 2 * V * sizeof(double), ts.data(), V * sizeof(double));
-    std::memcpy(h + 3 * V * sizeof(double), cand.data(), C * sizeof(int32_t));
+    const double inf = INFINITY;
+    std::memcpy(h + 3 * V * sizeof(double), &inf, sizeof(double));
+    std::memcpy(h + (3 * V + 1) * sizeof(double), cand.data(), C * sizeof(int32_t));
     hipError_t e;
     if ((e = hipMemcpyAsync(dbuf, h, in_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(ks inputs)");
-    if ((e = launch_ks_fit(dv, dv + V, dv + 2 * (size_t)V, V, dc, C, dD, dA, s)) != hipSuccess)
+    if ((e = launch_ks_fit(dv, dv + V, dv + 2 * (size_t)V, V, dc, C, dbest, dD, dA, s)) != hipSuccess)
         return hip_fail(e, "ks_fit launch");
     if ((e = hipMemcpyAsync(h + res_off, dD, res_bytes, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(ks results)");

@@ -184,9 +184,11 @@ hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int
     return hipGetLastError();
 }
 
-hipError_t launch_sv_pass_seg(SegList in, int32_t* parent, SegList out, int write_out, int max_link, int32_t* hooked,
-                              uint32_t* hooked_count, unsigned long long* totals, hipStream_t s) {
-    sv_pass_kernel<false><<<in.nseg, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, 0, in, parent, out, write_out,
+hipError_t launch_sv_pass_seg(SegList in, int32_t seg0, int32_t nblocks, int32_t* parent, SegList out, int write_out,
+                              int max_link, int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
+                              hipStream_t s) {
+    if (seg0 < 0 || nblocks < 1 || seg0 + nblocks > in.nseg || in.nseg > out.nseg) return hipErrorInvalidValue;
+    sv_pass_kernel<false><<<nblocks, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, seg0, in, parent, out, write_out,
                                                      max_link, hooked, hooked_count, totals);
     return hipGetLastError();
 }

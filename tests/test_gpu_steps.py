@@ -108,6 +108,26 @@ def test_powerlaw_fit_exact_law_and_edge_cases():
     assert math.isinf(ccmi.powerlaw_ks(hx, np.zeros(0, np.int32))["ks"])
 
 
+def test_powerlaw_fit_interior_cutoff_many_candidates():
+    """More than 256 candidate cutoffs, so a strided sample is fitted in full
+    first and the other candidates stop once they cannot be the best; the best
+    cutoff lies inside the range (a bell-shaped body, then a noisy power-law
+    tail), and degrees above 4096 go through the tail list."""
+    rng = np.random.default_rng(1607)
+    d = np.arange(1, 6000)
+    body = np.exp(-0.5 * ((np.log(d) - np.log(12.0)) / 0.5) ** 2)
+    tail = (d / 40.0) ** -2.3 * (d >= 40)
+    pmf = (body + 0.6 * tail) * rng.lognormal(0.0, 0.05, d.size)
+    cnt = np.round(2e9 * pmf / pmf.sum()).astype(np.int64)
+    hx = np.zeros(4096, np.int64)
+    hx[d[d < 4096]] = cnt[d < 4096]
+    big = d[d >= 4096]
+    tail_list = np.repeat(big, cnt[d >= 4096]).astype(np.int32)
+    got = _ks_compare(hx, rng.permutation(tail_list))
+    assert got["candidates"] > 256
+    assert 10 < got["dmin"] < 4000
+
+
 def test_csr_exact(graph):
     say(f"[gpu] csr {graph.name}")
     off, adj, deg = ccmi.csr(to_dev(graph.u), to_dev(graph.v), graph.n)
