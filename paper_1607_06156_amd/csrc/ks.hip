@@ -200,12 +200,15 @@ __global__ __launch_bounds__(kKsBlock) void ks_fit_kernel(const double* __restri
 
 // about this many candidates are evaluated in full first
 constexpr int32_t kKsSample = 256;
+// below this many CDF evaluations in all (sum over candidates of V - i0) one
+// launch without the cut is faster than two (each pays the exponent solves)
+constexpr int64_t kKsCutWork = (int64_t)8 << 20;
 
 hipError_t launch_ks_fit(const double* vals, const double* tail_n, const double* tail_s, int32_t V,
-                         const int32_t* cand, int32_t C, unsigned long long* best, double* outD, double* outA,
-                         hipStream_t s) {
+                         const int32_t* cand, int32_t C, int64_t work, unsigned long long* best, double* outD,
+                         double* outA, hipStream_t s) {
     if (C <= 0) return hipSuccess;
-    const int32_t stride = C > kKsSample ? (C + kKsSample - 1) / kKsSample : 1;
+    const int32_t stride = (C > kKsSample && work > kKsCutWork) ? (C + kKsSample - 1) / kKsSample : 1;
     ks_fit_kernel<<<(C + stride - 1) / stride, kKsBlock, 0, s>>>(vals, tail_n, tail_s, V, cand, C, stride, 0, best,
                                                                  outD, outA);
     if (stride > 1)

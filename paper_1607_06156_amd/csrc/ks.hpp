@@ -13,10 +13,11 @@ constexpr int64_t kMinTail = 50;   // vertices at or above a candidate cutoff
 
 // outD[c], outA[c]: statistic and exponent of candidate c; a candidate that
 // cannot have the smallest statistic may report +inf.  *best must hold the bits
-// of +inf on entry; it ends as the bits of the smallest statistic.
+// of +inf on entry; it ends as the bits of the smallest statistic.  work: the
+// number of CDF evaluations, sum over candidates of V - cand[c].
 hipError_t launch_ks_fit(const double* vals, const double* tail_n, const double* tail_s, int32_t V,
-                         const int32_t* cand, int32_t C, unsigned long long* best, double* outD, double* outA,
-                         hipStream_t s);
+                         const int32_t* cand, int32_t C, int64_t work, unsigned long long* best, double* outD,
+                         double* outA, hipStream_t s);
 
 struct KsResult {
     double ks = INFINITY;

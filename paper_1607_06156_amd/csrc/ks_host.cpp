@@ -85,7 +85,9 @@ int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* ta
     hipError_t e;
     if ((e = hipMemcpyAsync(dbuf, h, in_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(ks inputs)");
-    if ((e = launch_ks_fit(dv, dv + V, dv + 2 * (size_t)V, V, dc, C, dbest, dD, dA, s)) != hipSuccess)
+    int64_t work = 0;
+    for (int32_t c = 0; c < C; ++c) work += V - cand[c];
+    if ((e = launch_ks_fit(dv, dv + V, dv + 2 * (size_t)V, V, dc, C, work, dbest, dD, dA, s)) != hipSuccess)
         return hip_fail(e, "ks_fit launch");
     if ((e = hipMemcpyAsync(h + res_off, dD, res_bytes, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(ks results)");
