@@ -217,7 +217,8 @@ int cc_degree_histograms(const int32_t* deg, int32_t n, int64_t* hist64, int64_t
 
 /* Discrete power-law fit and K-S statistic of a degree distribution given as
  * host arrays histx[4096] (counts of degrees below 4096) and tail[ntail] (the
- * degrees >= 4096).  Clauset-Shalizi-Newman: for each candidate cutoff d_min
+ * degrees >= 4096, any order; CC_EINVAL if one is smaller).
+ * Clauset-Shalizi-Newman: for each candidate cutoff d_min
  * (distinct degree with >= 50 vertices and >= 2 distinct values at or above
  * it) alpha is the maximum-likelihood exponent on (1, 10] and D the largest
  * CDF gap; the result is the smallest D (the first such d_min on ties).

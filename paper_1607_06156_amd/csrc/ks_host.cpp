@@ -13,6 +13,26 @@
 
 namespace ccmi {
 
+// ascending LSD radix sort, 11-bit digits, only as many passes as the largest
+// value needs (a tail of ~13 000 degrees: about 0.1 ms, std::sort 0.7 ms)
+static void radix_sort_u32(std::vector<uint32_t>& a) {
+    uint32_t mx = 0;
+    for (uint32_t x : a) mx = x > mx ? x : mx;
+    std::vector<uint32_t> tmp(a.size());
+    for (int shift = 0; shift < 32 && (mx >> shift) != 0; shift += 11) {
+        uint32_t cnt[2048] = {0};
+        for (uint32_t x : a) ++cnt[(x >> shift) & 2047u];
+        uint32_t sum = 0;
+        for (int i = 0; i < 2048; ++i) {
+            const uint32_t c = cnt[i];
+            cnt[i] = sum;
+            sum += c;
+        }
+        for (uint32_t x : a) tmp[cnt[(x >> shift) & 2047u]++] = x;
+        a.swap(tmp);
+    }
+}
+
 int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* tail, int64_t ntail, KsResult* out) {
     *out = KsResult{};
     // distinct positive degrees (ascending) and their vertex counts
@@ -24,8 +44,9 @@ int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* ta
             cnts.push_back((double)histx[d]);
         }
     if (ntail > 0) {
-        std::vector<int32_t> t(tail, tail + ntail);
-        std::sort(t.begin(), t.end());
+        // degrees >= 4096 (positive): sorted as unsigned
+        std::vector<uint32_t> t((const uint32_t*)tail, (const uint32_t*)tail + ntail);
+        radix_sort_u32(t);
         for (size_t i = 0; i < t.size();) {
             size_t j = i;
             while (j < t.size() && t[j] == t[i]) ++j;

@@ -144,17 +144,31 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
 }
 
 int decide_heuristic(Call& c, DegreeResult& r, int* route) {
-    std::vector<int32_t> tail;
+    // the tail list comes back through the pinned staging buffer when it fits
+    // (ks_fit copies it before it reuses that buffer)
+    std::vector<int32_t> pageable;
+    const int32_t* tail = nullptr;
+    int64_t ntail = 0;
     if (r.ntail > 0) {
-        const int64_t k = std::min(r.ntail, r.tail_cap);
-        tail.resize(k);
-        hipError_t e = hipMemcpyAsync(tail.data(), r.tail, k * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream);
+        ntail = std::min(r.ntail, r.tail_cap);
+        int32_t* dst;
+        if ((size_t)ntail * sizeof(int32_t) <= Workspace::kHostBytes) {
+            void* hp;
+            int rc = c.ws->pinned(&hp);
+            if (rc) return rc;
+            dst = (int32_t*)hp;
+        } else {
+            pageable.resize(ntail);
+            dst = pageable.data();
+        }
+        hipError_t e = hipMemcpyAsync(dst, r.tail, ntail * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tail)");
         e = hipStreamSynchronize(c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        tail = dst;
     }
     KsResult k;
-    int rc = ks_fit(*c.ws, c.stream, r.histx.data(), tail.data(), (int64_t)tail.size(), &k);
+    int rc = ks_fit(*c.ws, c.stream, r.histx.data(), tail, ntail, &k);
     if (rc) return rc;
     if (c.stats) {
         c.stats->ks_statistic = k.ks;

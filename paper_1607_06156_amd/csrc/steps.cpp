@@ -97,6 +97,8 @@ CC_API int cc_degree_histograms(const int32_t* deg, int32_t n, int64_t* hist64, 
 
 CC_API int cc_powerlaw_ks(const int64_t* histx, const int32_t* tail, int64_t ntail, double* out) {
     if (!histx || !out || ntail < 0 || (ntail > 0 && !tail)) return fail(CC_EINVAL, "bad arguments");
+    for (int64_t i = 0; i < ntail; ++i)
+        if (tail[i] < kExactBins) return fail(CC_EINVAL, "tail[%lld] = %d is below %d", (long long)i, tail[i], kExactBins);
     Locked L;
     if (L.rc) return L.rc;
     KsResult k;

@@ -70,6 +70,11 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.cc_label_batched(None, None, None, None, 0, None, None) == 0
     lib.cc_powerlaw_ks.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     assert lib.cc_powerlaw_ks(None, None, 0, None) == -1
+    hx = (ctypes.c_int64 * 4096)()
+    bad_tail = (ctypes.c_int32 * 2)(5000, 4095)                  # 4095 belongs in histx, not the tail
+    res = (ctypes.c_double * 5)()
+    assert lib.cc_powerlaw_ks(hx, bad_tail, 2, res) == -1
+    assert b"below 4096" in lib.cc_last_error()
     lib.cc_router_load.argtypes = [ctypes.c_char_p]
     assert lib.cc_router_load(b"/nonexistent/weights.txt") == -1
 
