@@ -253,26 +253,32 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                 rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)m_in * nb / nseg);
             }
         }
-        e = launch_sv_totals(hooked_count, out.count, nseg, totals, c.stream);
+        // After a chunked first pass, the full flatten after each chunk has
+        // already jumped every root hooked before the last chunk: only the
+        // last chunk's segments hold roots still to jump.
+        const int jump_lo = in_soa && chunks > 1 ? (chunks - 1) * nseg_chunk : 0;
+        e = launch_sv_totals(hooked_count, out.count, nseg, jump_lo, totals, c.stream);
         if (e != hipSuccess) return hip_fail(e, "sv_totals launch");
-        e = hipMemcpyAsync(htot, totals, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
+        e = hipMemcpyAsync(htot, totals, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(totals)");
         e = hipStreamSynchronize(c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
         if (htot[2]) return fail(CC_ERANGE, "%llu edge endpoints outside [0, n)", (unsigned long long)htot[2]);
         const int64_t kept = (int64_t)htot[0];
         const int64_t hooks = (int64_t)htot[1];
-        // Shortcut: point the roots hooked in this pass at their roots, unless
-        // nothing survives or they far outnumber the survivors (typically after
-        // the first pass, when nearly every vertex was hooked): then the few
-        // survivors' finds walk the extra links, and the final labelling
-        // flattens everything once.
-        const bool jump = kept > 0 && hooks <= kLazyJump * kept;
+        const int64_t fresh = (int64_t)htot[3];   // hooked since the last full flatten
+        // Shortcut: point the roots hooked since the last full flatten at
+        // their roots, unless nothing survives or the pass's hooks far
+        // outnumber the survivors (typically after the first pass, when nearly
+        // every vertex was hooked): then the few survivors' finds walk the
+        // extra links, and the final labelling flattens everything once.
+        const bool jump = kept > 0 && fresh > 0 && hooks <= kLazyJump * kept;
         if (jump) {
             int k1 = c.kbeg();
-            e = launch_sv_shortcut(c.parent, (const int32_t*)phook, hooked_count, cap, nseg, c.stream);
+            e = launch_sv_shortcut(c.parent, (const int32_t*)phook + (int64_t)jump_lo * cap, hooked_count + jump_lo,
+                                   cap, nseg - jump_lo, c.stream);
             if (e != hipSuccess) return hip_fail(e, "sv_shortcut launch");
-            c.kend(CC_K_SV_SHORTCUT, k1, 12.0 * hooks);
+            c.kend(CC_K_SV_SHORTCUT, k1, 12.0 * fresh);
         }
         if (c.stats) {
             if (c.stats->sv_passes < 64) c.stats->active_edges[c.stats->sv_passes] = m_in;
@@ -281,7 +287,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             // edges read (8 B) + two 4 B gathers + one 8 B atomic per unfinished edge
             // + survivors written (8 B); shortcut: read, gather, write per hooked root
             const double pass_bytes = 16.0 * m_in + 8.0 * kept + (write ? 8.0 * kept : 0.0);
-            c.bytes += pass_bytes + (jump ? 12.0 * hooks : 0.0) + flat_bytes;
+            c.bytes += pass_bytes + (jump ? 12.0 * fresh : 0.0) + flat_bytes;
             c.kadd(rec_pass, 8.0 * kept + (write ? 8.0 * kept : 0.0));
         }
         ++pass;

@@ -97,8 +97,9 @@ hipError_t launch_sv_pass_seg(SegList in, int32_t seg0, int32_t nblocks, int32_t
 // pointer-jumps the hooked roots of each segment (no hook may run concurrently)
 hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count, int64_t cap,
                               int32_t nseg, hipStream_t s);
-// totals[0] = sum(kept_count), totals[1] = sum(hooked_count) over nseg segments
-hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg,
+// totals[0] = sum(kept_count), totals[1] = sum(hooked_count) over nseg
+// segments, totals[3] = sum(hooked_count) over segments seg_lo .. nseg-1
+hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg, int32_t seg_lo,
                             unsigned long long* totals, hipStream_t s);
 // parent[x] = root(x) for every x (no hook may run concurrently)
 hipError_t launch_sv_finalize(int32_t* parent, int32_t n, hipStream_t s);

@@ -106,14 +106,15 @@ __global__ __launch_bounds__(kBlock) void sv_shortcut_kernel(int32_t* parent, co
 }
 
 // One block: totals[0] = sum of the per-segment survivor counts, totals[1] =
-// sum of the per-segment hook counts.
+// sum of the per-segment hook counts, totals[3] = the hook counts of segments
+// seg_lo .. nseg-1 only (the roots hooked after the last full flatten).
 constexpr int kTotThreads = 1024;
 __global__ __launch_bounds__(kTotThreads) void sv_totals_kernel(const uint32_t* __restrict__ hooked_count,
                                                                 const uint32_t* __restrict__ kept_count, int32_t nseg,
-                                                                unsigned long long* __restrict__ totals) {
+                                                                int32_t seg_lo, unsigned long long* __restrict__ totals) {
     constexpr int W = kTotThreads / 64;
-    __shared__ unsigned long long red[2][W];
-    unsigned long long sk = 0, sh = 0;
+    __shared__ unsigned long long red[3][W];
+    unsigned long long sk = 0, sh = 0, sf = 0;
     // four independent loads in flight per thread
     for (int i0 = threadIdx.x; i0 < nseg; i0 += 4 * kTotThreads) {
         uint32_t a[4], c[4];
@@ -127,22 +128,26 @@ __global__ __launch_bounds__(kTotThreads) void sv_totals_kernel(const uint32_t* 
         for (int r = 0; r < 4; ++r) {
             sk += a[r];
             sh += c[r];
+            if (i0 + r * kTotThreads >= seg_lo) sf += c[r];
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
         sk += __shfl_xor(sk, off);
         sh += __shfl_xor(sh, off);
+        sf += __shfl_xor(sf, off);
     }
     if (lane_id() == 0) {
         red[0][threadIdx.x >> 6] = sk;
         red[1][threadIdx.x >> 6] = sh;
+        red[2][threadIdx.x >> 6] = sf;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long a = 0, c = 0;
-        for (int w = 0; w < W; ++w) { a += red[0][w]; c += red[1][w]; }
+        unsigned long long a = 0, c = 0, f = 0;
+        for (int w = 0; w < W; ++w) { a += red[0][w]; c += red[1][w]; f += red[2][w]; }
         totals[0] = a;
         totals[1] = c;
+        totals[3] = f;
     }
 }
 
@@ -199,9 +204,9 @@ hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg,
+hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg, int32_t seg_lo,
                             unsigned long long* totals, hipStream_t s) {
-    sv_totals_kernel<<<1, kTotThreads, 0, s>>>(hooked_count, kept_count, nseg, totals);
+    sv_totals_kernel<<<1, kTotThreads, 0, s>>>(hooked_count, kept_count, nseg, seg_lo, totals);
     return hipGetLastError();
 }
 
