@@ -133,6 +133,15 @@ int choose_nseg(int64_t m) {
 
 // hooked roots are pointer-jumped after a pass only if at most this many per survivor
 constexpr int64_t kLazyJump = 8;
+// The first chunk of the first pass, where the trees grow from single
+// vertices, runs as kFirstSplit launches with a full flatten between them
+// when the graph has at least kSplitDegree edges per vertex (a flatten costs
+// O(n); on sparse graphs it costs more than the shorter finds save).
+// Measured on MI355X (forced SV): noisy R-MAT scale 24 10.7 -> 9.7 ms, R-MAT
+// scale 24 unchanged; 4 launches helped the noisy graph more (8.4 ms) but
+// slowed the plain one by 0.35 ms.
+constexpr int kFirstSplit = 2;
+constexpr int64_t kSplitDegree = 8;
 
 // Chunks of the first pass.  Within one pass the trees only grow (no
 // shortcut runs while hooks are in flight), so the finds of late edges walk
@@ -213,23 +222,31 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         int rec_pass = -1;
         double flat_bytes = 0.0;
         if (in_soa) {
+            // chunk k covers segments [k * nseg_chunk, (k + 1) * nseg_chunk);
+            // the first chunk, where the trees grow from single vertices, is
+            // launched in kFirstSplit parts with a flatten between them
+            const int split = chunks > 1 && m0 >= kSplitDegree * (int64_t)c.n ? std::min(kFirstSplit, nseg_chunk) : 1;
             for (int k = 0; k < chunks; ++k) {
-                if (k > 0) {
-                    int kf = c.kbeg();
-                    e = launch_sv_finalize(c.parent, c.n, c.stream);
-                    if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
-                    // parent read + one gather per vertex, at most one write
-                    c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n);
-                    flat_bytes += 12.0 * c.n;
+                for (int part = 0; part < (k == 0 ? split : 1); ++part) {
+                    const int s0 = k == 0 ? (int)((int64_t)part * nseg_chunk / split) : k * nseg_chunk;
+                    const int s1 = k == 0 ? (int)((int64_t)(part + 1) * nseg_chunk / split) : (k + 1) * nseg_chunk;
+                    if (s0 > 0) {
+                        int kf = c.kbeg();
+                        e = launch_sv_finalize(c.parent, c.n, c.stream);
+                        if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
+                        // parent read + one gather per vertex, at most one write
+                        c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n);
+                        flat_bytes += 12.0 * c.n;
+                    }
+                    int k0 = c.kbeg();
+                    e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, s0, s1 - s0, write ? 1 : 0, max_link,
+                                           (int32_t*)phook, hooked_count, totals, c.stream);
+                    if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
+                    // this launch's edges; the survivors' bytes go to the last one below
+                    const int64_t e0 = std::min<int64_t>(m0, (int64_t)s0 * cap);
+                    const int64_t e1 = std::min<int64_t>(m0, (int64_t)s1 * cap);
+                    rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)(e1 - e0));
                 }
-                int k0 = c.kbeg();
-                e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, k * nseg_chunk, nseg_chunk,
-                                       write ? 1 : 0, max_link, (int32_t*)phook, hooked_count, totals, c.stream);
-                if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
-                // this chunk's edges; the survivors' bytes go to the last chunk below
-                const int64_t e0 = std::min<int64_t>(m0, (int64_t)k * nseg_chunk * cap);
-                const int64_t e1 = std::min<int64_t>(m0, (int64_t)(k + 1) * nseg_chunk * cap);
-                rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)(e1 - e0));
             }
         } else {
             // a long list handed over by an earlier step (the edges a BFS left)
