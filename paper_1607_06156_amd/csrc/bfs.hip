@@ -366,6 +366,103 @@ __global__ __launch_bounds__(kBlock) void sum_counts_kernel(const uint32_t* __re
     }
 }
 
+// ------------------------------------------------------ rest from the CSR
+// The edges a BFS leaves are those between unvisited vertices.  When the
+// unvisited rows are short in total they are read from the CSR instead of
+// probing the visited bitmap for every edge of the list: an edge lies in the
+// rows of both of its ends and is taken from the row of its smaller end; a
+// self-loop has two entries in its vertex's row and is taken once per pair.
+// Each wave walks 64 consecutive vertices at a time: a row of up to
+// kRestShort entries by its lane, a longer one by the whole wave.  COUNT:
+// the number of edges per wave; else the edges, written as (smaller, larger)
+// from the wave's offset (an exclusive prefix of the counts).
+constexpr int kRestShort = 16;
+constexpr int kRestV = 4096;   // vertices per block
+
+__device__ __forceinline__ int64_t shfl_i64(int64_t x, int l) {
+    const int32_t lo = __shfl((int32_t)(x & 0xffffffff), l);
+    const int32_t hi = __shfl((int32_t)(x >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void rest_kernel(const uint32_t* __restrict__ vis, const int64_t* __restrict__ off,
+                                                      const int32_t* __restrict__ adj, int32_t n,
+                                                      int64_t* __restrict__ wcount, int32_t* __restrict__ fu,
+                                                      int32_t* __restrict__ fv) {
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const int64_t gw = (int64_t)blockIdx.x * kWaves + w;
+    const int64_t x0 = (int64_t)blockIdx.x * kRestV + (int64_t)w * (kRestV / kWaves);
+    int64_t pos = COUNT ? 0 : wcount[gw];   // wave-uniform
+    for (int step = 0; step < kRestV / kWaves / 64; ++step) {
+        const int64_t xi = x0 + (int64_t)step * 64 + lane;
+        const int32_t x = (int32_t)xi;
+        const bool un = xi < n && !test_bit(vis, x);
+        const int64_t o0 = un ? off[xi] : 0, o1 = un ? off[xi + 1] : 0;
+        const bool shortrow = o1 - o0 <= kRestShort;
+        // rows of up to kRestShort entries: this lane
+        int32_t mine = 0, self = 0;
+        if (shortrow)
+            for (int64_t j = o0; j < o1; ++j) {
+                const int32_t y = adj[j];
+                mine += x < y;
+                self += x == y;
+            }
+        mine += self >> 1;
+        int32_t incl = mine;   // wave inclusive scan
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t t = __shfl_up(incl, d);
+            if (lane >= d) incl += t;
+        }
+        const int32_t wtot = __shfl(incl, 63);
+        if (!COUNT && mine > 0) {
+            int64_t p = pos + incl - mine;
+            for (int64_t j = o0; j < o1; ++j) {
+                const int32_t y = adj[j];
+                if (x < y) {
+                    fu[p] = x;
+                    fv[p] = y;
+                    ++p;
+                }
+            }
+            for (int32_t k = 0; k < (self >> 1); ++k, ++p) {
+                fu[p] = x;
+                fv[p] = x;
+            }
+        }
+        pos += wtot;
+        // longer rows: the whole wave walks each in turn
+        uint64_t lm = ballot(!shortrow);
+        while (lm) {
+            const int l = __builtin_ctzll(lm);
+            lm &= lm - 1;
+            const int32_t xl = __shfl(x, l);
+            const int64_t a0 = shfl_i64(o0, l), a1 = shfl_i64(o1, l);
+            int64_t selfw = 0;
+            for (int64_t j0 = a0; j0 < a1; j0 += 64) {
+                const int64_t j = j0 + lane;
+                const int32_t y = j < a1 ? adj[j] : -1;   // ids are >= 0: -1 matches nothing
+                const uint64_t km = ballot(xl < y);
+                selfw += __popcll(ballot(y == xl));
+                if (!COUNT && xl < y) {
+                    const int64_t p = pos + lanes_below(km);
+                    fu[p] = xl;
+                    fv[p] = y;
+                }
+                pos += __popcll(km);
+            }
+            const int64_t half = selfw >> 1;
+            if (!COUNT)
+                for (int64_t k = lane; k < half; k += 64) {
+                    fu[pos + k] = xl;
+                    fv[pos + k] = xl;
+                }
+            pos += half;
+        }
+    }
+    if (COUNT && lane == 0) wcount[gw] = pos;
+}
+
 // segmented int2 list -> dense SoA (segment b starts at prefix[b])
 __global__ __launch_bounds__(kBlock) void seg_to_soa_kernel(SegList in, const int64_t* __restrict__ prefix,
                                                             int32_t* __restrict__ fu, int32_t* __restrict__ fv) {
@@ -454,6 +551,25 @@ hipError_t launch_filter(const int32_t* u, const int32_t* v, int64_t m, int32_t 
                          unsigned long long* total, unsigned long long* bad, hipStream_t s) {
     filter_kernel<<<out.nseg, kBlock, 0, s>>>(u, v, m, n, vis, out, bad);
     sum_counts_kernel<<<1, kBlock, 0, s>>>(out.count, out.nseg, total);
+    return hipGetLastError();
+}
+
+int64_t rest_waves(int32_t n) { return ((int64_t)n + kRestV - 1) / kRestV * kWaves; }
+
+hipError_t launch_rest_count(const uint32_t* vis, const int64_t* off, const int32_t* adj, int32_t n, int64_t* wcount,
+                             int64_t* total, hipStream_t s) {
+    const int64_t blocks = ((int64_t)n + kRestV - 1) / kRestV;
+    if (blocks < 1) return hipSuccess;
+    rest_kernel<true><<<(unsigned)blocks, kBlock, 0, s>>>(vis, off, adj, n, wcount, nullptr, nullptr);
+    scan_small_i64_kernel<<<1, 1024, 0, s>>>(wcount, blocks * kWaves, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_rest_emit(const uint32_t* vis, const int64_t* off, const int32_t* adj, int32_t n,
+                            const int64_t* woff, int32_t* fu, int32_t* fv, hipStream_t s) {
+    const int64_t blocks = ((int64_t)n + kRestV - 1) / kRestV;
+    if (blocks < 1) return hipSuccess;
+    rest_kernel<false><<<(unsigned)blocks, kBlock, 0, s>>>(vis, off, adj, n, (int64_t*)woff, fu, fv);
     return hipGetLastError();
 }
 

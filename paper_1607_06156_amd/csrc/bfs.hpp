@@ -33,6 +33,16 @@ hipError_t launch_bfs_label(const uint32_t* vis, int32_t n, int32_t* label, int3
 hipError_t launch_filter(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const uint32_t* vis, SegList out,
                          unsigned long long* total, unsigned long long* bad, hipStream_t s);
 // *bad += violations of the CSR contract (offsets, entry range)
+// The edges between unvisited vertices from the CSR rows of the unvisited
+// vertices, as (smaller, larger) pairs (a self-loop once per two entries).
+// Count: per-wave counts into wcount[rest_waves(n)], turned into an exclusive
+// prefix in place, *total = their sum.  Emit: the edges into fu, fv (room for
+// *total each) at those offsets.
+int64_t rest_waves(int32_t n);
+hipError_t launch_rest_count(const uint32_t* vis, const int64_t* off, const int32_t* adj, int32_t n, int64_t* wcount,
+                             int64_t* total, hipStream_t s);
+hipError_t launch_rest_emit(const uint32_t* vis, const int64_t* off, const int32_t* adj, int32_t n,
+                            const int64_t* woff, int32_t* fu, int32_t* fv, hipStream_t s);
 hipError_t launch_csr_check(const int64_t* off, int32_t n, const int32_t* adj, int64_t nadj,
                             unsigned long long* bad, hipStream_t s);
 hipError_t launch_seg_to_soa(SegList in, int64_t* prefix_scratch, int64_t* total_scratch, int32_t* fu, int32_t* fv,

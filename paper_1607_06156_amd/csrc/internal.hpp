@@ -140,6 +140,7 @@ struct DegreeResult {
 struct BfsResult {
     int levels = 0, bottom_up = 0;
     int64_t visited = 0, examined = 0;
+    int64_t unvisited_entries = 0;   // adjacency entries in the rows of unvisited vertices
 };
 
 int run_degree_pass(Call& c, bool want_csr, DegreeResult* r);

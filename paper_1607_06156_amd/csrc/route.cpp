@@ -318,18 +318,29 @@ int run_bfs_route(Call& c, DegreeResult& r) {
     int32_t* dlabel = (int32_t*)((unsigned long long*)ptot + 28);
     const int nseg = choose_nseg(c.m);
     const int64_t cap = (c.m + nseg - 1) / nseg;
-    if ((rc = ws.get(WS_EDGES0, (size_t)nseg * cap * sizeof(int2), &pe0))) return rc;
     if ((rc = ws.get(WS_SEGCOUNT, std::max((size_t)nseg * 4 * sizeof(uint32_t),
                                            (size_t)(c.n + 1 + c.n / 1024 + 3) * sizeof(int64_t)),
                      &pcnt)))
         return rc;
-    uint32_t* fcnt = (uint32_t*)pcnt + (size_t)2 * nseg;
-    SegList out{(int2*)pe0, cap, nseg, fcnt};
+    // The rest is read from the CSR rows of the unvisited vertices when they
+    // hold no more entries than the edge list has edges (typically a few
+    // percent after a giant component): half the bytes at most, and no bitmap
+    // probe per edge.  Otherwise every edge of the list is tested.
+    const bool from_csr = br.unvisited_entries <= c.m;
     int k0 = c.kbeg();
     hipError_t e = hipMemsetAsync(dlabel, 0x7f, sizeof(int32_t), c.stream);
     if (e == hipSuccess) e = hipMemsetAsync(tot + 1, 0, sizeof(unsigned long long), c.stream);
     if (e == hipSuccess) e = launch_bfs_label(vis, c.n, dlabel, c.parent, c.stream);
-    if (e == hipSuccess) e = launch_filter(c.u, c.v, c.m, c.n, vis, out, tot, tot + 1, c.stream);
+    SegList out{};
+    int64_t* wcount = (int64_t*)pcnt;
+    if (from_csr) {
+        if (e == hipSuccess) e = launch_rest_count(vis, r.off, r.adj, c.n, wcount, (int64_t*)tot, c.stream);
+    } else {
+        if ((rc = ws.get(WS_EDGES0, (size_t)nseg * cap * sizeof(int2), &pe0))) return rc;
+        uint32_t* fcnt = (uint32_t*)pcnt + (size_t)2 * nseg;
+        out = SegList{(int2*)pe0, cap, nseg, fcnt};
+        if (e == hipSuccess) e = launch_filter(c.u, c.v, c.m, c.n, vis, out, tot, tot + 1, c.stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "label/filter launch");
     int rec = c.kend(CC_K_FILTER, k0, 0.0);
     unsigned long long* host;
@@ -340,11 +351,33 @@ int run_bfs_route(Call& c, DegreeResult& r) {
     if (e != hipSuccess) return hip_fail(e, "filter readback");
     const int64_t kept = (int64_t)host[0];
     const int32_t label = *(int32_t*)(host + 1);
-    // labels (4 B per vertex) + bitmap probe per vertex and per edge, edges read, survivors written
-    const double fbytes = 4.0 * c.n + 0.125 * c.n + 8.0 * c.m + 4.0 * c.m + 8.0 * kept;
+    int32_t* fu = nullptr;
+    int32_t* fv = nullptr;
+    double fbytes;
+    if (from_csr) {
+        // the rest as dense arrays in the CSR fill's scratch (free by now)
+        void* pf;
+        if ((rc = ws.get(WS_CURSOR, (size_t)std::max<int64_t>(kept, 1) * 2 * sizeof(int32_t), &pf))) return rc;
+        fu = (int32_t*)pf;
+        fv = fu + kept;
+        if (kept > 0) {
+            int k1 = c.kbeg();
+            e = launch_rest_emit(vis, r.off, r.adj, c.n, wcount, fu, fv, c.stream);
+            if (e != hipSuccess) return hip_fail(e, "rest launch");
+            c.kend(CC_K_FILTER, k1, 0.125 * c.n + 16.0 * (c.n - br.visited) + 4.0 * br.unvisited_entries +
+                                        8.0 * kept);
+        }
+        // labels (4 B per vertex), bitmap, offsets of the unvisited vertices, their rows (counted)
+        fbytes = 4.0 * c.n + 0.25 * c.n + 16.0 * (c.n - br.visited) + 4.0 * br.unvisited_entries;
+    } else {
+        // labels (4 B per vertex) + bitmap probe per vertex and per edge, edges read, survivors written
+        fbytes = 4.0 * c.n + 0.125 * c.n + 8.0 * c.m + 4.0 * c.m + 8.0 * kept;
+    }
     c.kbytes(rec, fbytes);
     if (c.stats) {
-        c.bytes += fbytes;
+        c.bytes += fbytes + (from_csr && kept > 0 ? 0.125 * c.n + 16.0 * (c.n - br.visited) +
+                                                         4.0 * br.unvisited_entries + 8.0 * kept
+                                                   : 0.0);
         c.stats->bfs_levels = br.levels;
         c.stats->bfs_bottom_up_levels = br.bottom_up;
         c.stats->bfs_seed = r.argmax;
@@ -361,9 +394,16 @@ int run_bfs_route(Call& c, DegreeResult& r) {
     }
     if (kept == 0) return CC_OK;
     SvInput in;
-    in.soa = false;
-    in.m = kept;
-    in.seg = SegList{(int2*)pe0, cap, nseg, fcnt};
+    if (from_csr) {
+        in.soa = true;
+        in.u = fu;
+        in.v = fv;
+        in.m = kept;
+    } else {
+        in.soa = false;
+        in.m = kept;
+        in.seg = out;
+    }
     int t4 = c.timer->mark();
     rc = run_sv(c, in, CC_R1_SV, c.opt.theta, c.opt.max_passes);
     int t5 = c.timer->mark();

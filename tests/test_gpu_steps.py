@@ -189,6 +189,45 @@ def test_routes_exact(graph, route):
         assert st["edges_after_filter"] == r["u"].shape[0]
 
 
+def _star_and_lattice(leaves, side, rng):
+    """A star (the largest degree) beside a side x side lattice with self-loops
+    and repeated edges; ids shuffled."""
+    n = 1 + leaves + side * side
+    u = [np.zeros(leaves, np.int64)]
+    v = [np.arange(1, leaves + 1)]
+    g = 1 + leaves + np.arange(side * side).reshape(side, side)
+    u += [g[:, :-1].ravel(), g[:-1, :].ravel()]
+    v += [g[:, 1:].ravel(), g[1:, :].ravel()]
+    loops = rng.choice(g.ravel(), 300, replace=False)
+    u.append(loops)
+    v.append(loops)
+    u = np.concatenate(u)
+    v = np.concatenate(v)
+    rep = rng.choice(u.shape[0], 500, replace=False)
+    u = np.concatenate([u, v[rep]])
+    v = np.concatenate([v, u[rep]])
+    perm = rng.permutation(n)
+    return perm[u].astype(np.int32), perm[v].astype(np.int32), n
+
+
+@pytest.mark.parametrize("leaves,side", [(2000, 300), (200000, 60)])
+def test_bfs_route_rest_from_list_and_from_csr(leaves, side):
+    """The BFS starts at the star's hub.  With the lattice holding most edges,
+    the rows of the unvisited vertices hold more entries than the list has
+    edges and the rest is taken from the edge list; with a big star and a
+    small lattice it is read from the CSR rows (self-loops once, repeated
+    edges as often as given).  Labels, the filtered count and the BFS against
+    the oracle."""
+    rng = np.random.default_rng(leaves + side)
+    u, v, n = _star_and_lattice(leaves, side, rng)
+    say(f"[gpu] bfs route rest: star {leaves} + lattice {side}^2, n={n} m={u.shape[0]}")
+    lab, st = ccmi.label(to_dev(u), to_dev(v), n, route="bfs+sv", stats=True)
+    assert_labels_equal(lab, oracle.labels_uf(u, v, n), f"star{leaves}+lattice{side}")
+    r = hybrid.bfs_route(u, v, n)
+    assert st["bfs_seed"] == r["seed"] and st["bfs_visited"] == leaves + 1
+    assert st["edges_after_filter"] == r["u"].shape[0]
+
+
 def test_two_level_buckets_large_n():
     """n > 2^26, i.e. more than 2048 vertex buckets: the degree pass scatters
     through super-buckets first.  Degrees, the CSR and the routes that build
