@@ -1,7 +1,9 @@
 """Full-size workloads on the GPU, checked against the oracle: the near-critical
-G(n,m), R-MAT scale 24, the 8192^2 thinned lattice and the 200M-vertex
-component forest label-for-label; the 4096-graph batch on sampled graphs plus
-invariants over every graph."""
+G(n,m), R-MAT scale 24 (plain, and with per-level noise: the heuristic takes
+the BFS route), the 8192^2 thinned lattice and the 200M-vertex component
+forest (also through the BFS route, whose remaining list is long) label for
+label; the 4096-graph batch on sampled graphs plus invariants over every
+graph."""
 import numpy as np
 import pytest
 import torch
@@ -29,8 +31,9 @@ def workload(name):
 @pytest.mark.parametrize("name,routes", [
     ("gnm64k", ["sv", "sv-theta", "bfs+sv", "heuristic"]),
     ("rmat24", ["heuristic", "sv", "bfs+sv", "sv-theta"]),
+    ("rmat24noisy", ["heuristic", "sv"]),
     ("grid8192", ["sv", "sv-theta"]),
-    ("plcomp200m", ["sv", "heuristic"]),
+    ("plcomp200m", ["sv", "heuristic", "bfs+sv"]),
 ])
 def test_full_workload(name, routes):
     g, expect = workload(name)
