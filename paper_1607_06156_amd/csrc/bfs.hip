@@ -248,14 +248,6 @@ __global__ __launch_bounds__(kBlock) void bits_to_queue_kernel(const uint32_t* _
     }
 }
 
-// front = vis & ~prev (vertices claimed during the last top-down level)
-__global__ __launch_bounds__(kBlock) void diff_bits_kernel(const uint32_t* __restrict__ vis,
-                                                           const uint32_t* __restrict__ prev,
-                                                           uint32_t* __restrict__ front, int64_t words) {
-    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < words; w += (int64_t)gridDim.x * kBlock)
-        front[w] = vis[w] & ~prev[w];
-}
-
 // ------------------------------------------------------ label and filter
 // *label = smallest visited id (int32 max if none)
 __global__ __launch_bounds__(kBlock) void first_bit_kernel(const uint32_t* __restrict__ vis, int64_t words,
@@ -534,11 +526,6 @@ hipError_t launch_bits_to_queue(const uint32_t* bits, int64_t words, int32_t* q,
     return hipGetLastError();
 }
 
-hipError_t launch_diff_bits(const uint32_t* vis, const uint32_t* prev, uint32_t* front, int64_t words,
-                            hipStream_t s) {
-    diff_bits_kernel<<<grid_cap(words, kBlock, 4096), kBlock, 0, s>>>(vis, prev, front, words);
-    return hipGetLastError();
-}
 
 hipError_t launch_bfs_label(const uint32_t* vis, int32_t n, int32_t* label, int32_t* labels, hipStream_t s) {
     int64_t words = ((int64_t)n + 31) >> 5;

@@ -24,8 +24,6 @@ hipError_t launch_bottomup(int32_t n, const int64_t* off, const int32_t* adj, ui
 hipError_t launch_queue_to_bits(const int32_t* q, int64_t qn, uint32_t* bits, hipStream_t s);
 hipError_t launch_bits_to_queue(const uint32_t* bits, int64_t words, int32_t* q, unsigned long long* qn,
                                 hipStream_t s);
-hipError_t launch_diff_bits(const uint32_t* vis, const uint32_t* prev, uint32_t* front, int64_t words,
-                            hipStream_t s);
 // *label (pre-set to INT32_MAX) = min visited id; labels[x] = visited ? *label : x
 hipError_t launch_bfs_label(const uint32_t* vis, int32_t n, int32_t* label, int32_t* labels, hipStream_t s);
 // edges whose first endpoint is unvisited -> segments of out; *total = their count

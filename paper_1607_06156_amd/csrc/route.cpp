@@ -187,7 +187,7 @@ int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32
     const int64_t words = ((int64_t)n + 31) >> 5;
     void *pbits, *pq, *ppre, *ptot;
     int rc;
-    if ((rc = ws.get(WS_BITS, (size_t)words * 4 * sizeof(uint32_t), &pbits))) return rc;
+    if ((rc = ws.get(WS_BITS, (size_t)words * 3 * sizeof(uint32_t), &pbits))) return rc;
     if ((rc = ws.get(WS_HOOKED, (size_t)n * 2 * sizeof(int32_t), &pq))) return rc;
     const int64_t nb = ((int64_t)n + 1023) / 1024 + 1;
     if ((rc = ws.get(WS_SEGCOUNT, (size_t)(n + 1 + nb + 1) * sizeof(int64_t), &ppre))) return rc;
@@ -195,7 +195,6 @@ int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32
     uint32_t* vis = (uint32_t*)pbits;
     uint32_t* front = vis + words;
     uint32_t* next = front + words;
-    uint32_t* prev = next + words;
     int32_t* q = (int32_t*)pq;
     int32_t* nq = q + n;
     int64_t* pre = (int64_t*)ppre;
@@ -271,7 +270,6 @@ int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32
             topdown = true;
         }
     }
-    (void)prev;
     (void)nadj;
     br->levels = levels;
     br->bottom_up = bu_levels;

@@ -188,6 +188,16 @@ def evaluate(w, count, seed0, lg_lo, lg_hi, log=None):
     return out, rows
 
 
+def load(path):
+    """Weights written by save(): the parameters in order, comments skipped."""
+    with open(path) as f:
+        vals = [float(x) for line in f if not line.lstrip().startswith("#") for x in line.split()]
+    w = np.asarray(vals, dtype=np.float32)
+    if w.size != ccmi.ROUTER_NPARAMS:
+        raise ValueError(f"{path}: {w.size} parameters, expected {ccmi.ROUTER_NPARAMS}")
+    return w
+
+
 def save(w, path, note):
     with open(path, "w") as f:
         f.write("# route-selection MLP 66-64-64-3, FP32, row-major [out][in]: W1 b1 W2 b2 W3 b3\n")
@@ -210,12 +220,25 @@ def main():
     ap.add_argument("--dataset-in", action="append", default=[], help="earlier dataset (.npz) to prepend")
     ap.add_argument("--dataset-out", default=None, help="save the dataset built here (.npz)")
     ap.add_argument("--build-only", action="store_true", help="build (and save) the dataset, do not train")
+    ap.add_argument("--eval-weights", default=None,
+                    help="only evaluate these saved weights on the held-out graphs (no training)")
     args = ap.parse_args()
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
     t0 = time.time()
+    if args.eval_weights:
+        w = load(args.eval_weights)
+        rep, rows = evaluate(w, args.n_eval, 20_000_000, args.lg_lo, args.lg_hi, log)
+        rep.update({"weights": args.eval_weights, "seconds": time.time() - t0})
+        log(f"[router] evaluation: router {rep['router_s'] * 1e3:.1f} ms vs heuristic "
+            f"{rep['heuristic_s'] * 1e3:.1f} ms (best forced {rep['best_forced_s'] * 1e3:.1f} ms) "
+            f"over {rep['graphs']} graphs")
+        with open(args.report, "w") as f:
+            json.dump({"summary": rep, "rows": rows}, f, indent=1)
+        print(json.dumps(rep))
+        return
     X, T, meta = build_dataset(args.n_train, 10_000_000, args.lg_lo, args.lg_hi, FAMILIES, log, start=args.start)
     if args.dataset_out:
         np.savez(args.dataset_out, X=X, T=T, n=np.array([r["n"] for r in meta], np.int64),

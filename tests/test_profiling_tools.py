@@ -87,3 +87,20 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_router_weights_save_load_roundtrip(tmp_path):
+    """The router tool's text format keeps every float32 parameter exactly and
+    refuses a file with the wrong parameter count."""
+    import numpy as np
+    from paper_1607_06156_amd import router_train as rt
+    import paper_1607_06156_amd as ccmi
+    w = np.random.default_rng(7).standard_normal(ccmi.ROUTER_NPARAMS).astype(np.float32)
+    p = tmp_path / "w.txt"
+    rt.save(w, str(p), "test weights\nsecond line")
+    assert np.array_equal(rt.load(str(p)), w)
+    shipped = rt.load(os.path.join(ROOT, "paper_1607_06156_amd", "router_weights.txt"))
+    assert shipped.shape == (ccmi.ROUTER_NPARAMS,) and np.isfinite(shipped).all()
+    (tmp_path / "short.txt").write_text("# two\n1 2\n")
+    with pytest.raises(ValueError):
+        rt.load(str(tmp_path / "short.txt"))
