@@ -134,13 +134,18 @@ int choose_nseg(int64_t m) {
 // hooked roots are pointer-jumped after a pass only if at most this many per survivor
 constexpr int64_t kLazyJump = 8;
 // The first chunk of the first pass, where the trees grow from single
-// vertices, runs as kFirstSplit launches with a full flatten between them
-// when the graph has at least kSplitDegree edges per vertex (a flatten costs
-// O(n); on sparse graphs it costs more than the shorter finds save).
-// Measured on MI355X (forced SV): noisy R-MAT scale 24 10.7 -> 9.7 ms, R-MAT
-// scale 24 unchanged; 4 launches helped the noisy graph more (8.4 ms) but
-// slowed the plain one by 0.35 ms.
-constexpr int kFirstSplit = 2;
+// vertices, runs as two launches with a full flatten between them when the
+// graph has at least kSplitDegree edges per vertex (a flatten costs O(n); on
+// sparse graphs it costs more than the shorter finds save): first a small
+// one over 1/kFirstLaunch of its segments, then the rest.  Nearly every edge
+// of that first launch hooks, many of them onto the same few hub roots, and
+// same-address device atomics serialise: the fewer workgroups in flight, the
+// shorter those queues.  Measured on MI355X (forced SV, R-MAT scale 24 /
+// noisy R-MAT scale 24): one launch 9.0 / 10.7 ms; halves 9.2 / 9.6 ms;
+// first 1/4: 9.1 / 8.4 ms; first 1/8: 8.6 / 7.8 ms; first 1/16: 8.8 / 8.2 ms;
+// giving each half its own 2048 workgroups (more in flight) made the first
+// launch 2.5x slower.
+constexpr int kFirstLaunch = 8;
 constexpr int64_t kSplitDegree = 8;
 
 // Chunks of the first pass.  Within one pass the trees only grow (no
@@ -223,13 +228,13 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         double flat_bytes = 0.0;
         if (in_soa) {
             // chunk k covers segments [k * nseg_chunk, (k + 1) * nseg_chunk);
-            // the first chunk, where the trees grow from single vertices, is
-            // launched in kFirstSplit parts with a flatten between them
-            const int split = chunks > 1 && m0 >= kSplitDegree * (int64_t)c.n ? std::min(kFirstSplit, nseg_chunk) : 1;
+            // on dense graphs the first chunk is launched as [0, cut), [cut, nseg_chunk)
+            const int split = chunks > 1 && m0 >= kSplitDegree * (int64_t)c.n && nseg_chunk >= 2 ? 2 : 1;
+            const int cut = std::max(1, nseg_chunk / kFirstLaunch);
             for (int k = 0; k < chunks; ++k) {
                 for (int part = 0; part < (k == 0 ? split : 1); ++part) {
-                    const int s0 = k == 0 ? (int)((int64_t)part * nseg_chunk / split) : k * nseg_chunk;
-                    const int s1 = k == 0 ? (int)((int64_t)(part + 1) * nseg_chunk / split) : (k + 1) * nseg_chunk;
+                    const int s0 = k > 0 ? k * nseg_chunk : (part == 0 ? 0 : cut);
+                    const int s1 = k > 0 ? (k + 1) * nseg_chunk : (split == 1 || part == 1 ? nseg_chunk : cut);
                     if (s0 > 0) {
                         int kf = c.kbeg();
                         e = launch_sv_finalize(c.parent, c.n, c.stream);
