@@ -102,7 +102,8 @@ typedef struct cc_stats {
     double ks_alpha;              /* fitted power-law exponent, else NaN */
     int64_t ks_dmin;              /* fitted lower cutoff, else 0 */
     float router_logits[3];       /* when the router ran, else 0 */
-    int32_t reserved0;
+    int32_t sv_deep_rounds;       /* flatten rounds forced by chains deeper than the
+                                     64-link walk bound (0 on shallow forests) */
     int64_t active_edges[64];     /* active edges entering SV pass i (first 64 passes) */
     int64_t hooks_total;          /* successful hooks over all passes */
     double ms_predict;            /* degree pass + histograms + decision */

@@ -49,7 +49,7 @@ class Stats(ctypes.Structure):
                 ("bfs_label", ctypes.c_int32), ("bfs_visited", ctypes.c_int64),
                 ("bfs_edges_examined", ctypes.c_int64), ("edges_after_filter", ctypes.c_int64),
                 ("max_degree", ctypes.c_int64), ("ks_statistic", ctypes.c_double), ("ks_alpha", ctypes.c_double),
-                ("ks_dmin", ctypes.c_int64), ("router_logits", ctypes.c_float * 3), ("reserved0", ctypes.c_int32),
+                ("ks_dmin", ctypes.c_int64), ("router_logits", ctypes.c_float * 3), ("sv_deep_rounds", ctypes.c_int32),
                 ("active_edges", ctypes.c_int64 * 64), ("hooks_total", ctypes.c_int64),
                 ("ms_predict", ctypes.c_double), ("ms_csr", ctypes.c_double), ("ms_bfs", ctypes.c_double),
                 ("ms_filter", ctypes.c_double), ("ms_sv", ctypes.c_double), ("ms_total", ctypes.c_double),

@@ -162,6 +162,30 @@ int pass0_chunks(int64_t m, int32_t n) {
     return (int)k;
 }
 
+// Flatten rounds until every vertex points at its root.  A round leaves *open
+// set when some root lay more than kMaxHops links up; each round divides the
+// depth of the forest by at least kMaxHops, so a forest of depth below n takes
+// at most log(n) / log(kMaxHops) + 1 rounds.  *extra counts the rounds after
+// the first.  hpin: pinned host word.
+constexpr int kMaxFlattenRounds = 16;
+static int flatten_all(Call& c, unsigned long long* open, unsigned long long* hpin, int* extra) {
+    for (int r = 0;; ++r) {
+        hipError_t e = hipSuccess;
+        if (r > 0) e = hipMemsetAsync(open, 0, sizeof(*open), c.stream);   // round 0 starts clear
+        int k0 = c.kbeg();
+        if (e == hipSuccess) e = launch_sv_finalize(c.parent, c.n, open, c.stream);
+        if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
+        c.kend(CC_K_SV_FINALIZE, k0, 8.0 * c.n);
+        if (c.stats) c.bytes += 8.0 * c.n;
+        e = hipMemcpyAsync(hpin, open, sizeof(*open), hipMemcpyDeviceToHost, c.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+        if (e != hipSuccess) return hip_fail(e, "flatten readback");
+        if (!*hpin) return CC_OK;
+        ++*extra;
+        if (r + 1 >= kMaxFlattenRounds) return fail(CC_EINTERNAL, "flatten did not finish in %d rounds", r + 1);
+    }
+}
+
 int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes) {
     Workspace& ws = *c.ws;
     const int64_t m0 = in0.soa ? in0.m : 0;
@@ -203,6 +227,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
     bool in_soa = in0.soa;
     SegList in{nullptr, cap, nseg, nullptr};
     int in_buf = 0, in_cnt = 0;
+    int deep_rounds = 0;   // flatten rounds forced by deep chains
     if (!in_soa) {
         // caller placed the list in WS_EDGES0 with counts in cnt[0]
         if (in0.seg.buf != bufs[0]) return fail(CC_EINTERNAL, "segment list not in workspace");
@@ -237,7 +262,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                     const int s1 = k > 0 ? (k + 1) * nseg_chunk : (split == 1 || part == 1 ? nseg_chunk : cut);
                     if (s0 > 0) {
                         int kf = c.kbeg();
-                        e = launch_sv_finalize(c.parent, c.n, c.stream);
+                        e = launch_sv_finalize(c.parent, c.n, totals + 6, c.stream);
                         if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
                         // parent read + one gather per vertex, at most one write
                         c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n);
@@ -261,7 +286,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             for (int s0 = 0; s0 < nseg; s0 += per) {
                 if (s0 > 0) {
                     int kf = c.kbeg();
-                    e = launch_sv_finalize(c.parent, c.n, c.stream);
+                    e = launch_sv_finalize(c.parent, c.n, totals + 6, c.stream);
                     if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
                     c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n);
                     flat_bytes += 12.0 * c.n;
@@ -281,7 +306,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         const int jump_lo = in_soa && chunks > 1 ? (chunks - 1) * nseg_chunk : 0;
         e = launch_sv_totals(hooked_count, out.count, nseg, jump_lo, totals, c.stream);
         if (e != hipSuccess) return hip_fail(e, "sv_totals launch");
-        e = hipMemcpyAsync(htot, totals, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
+        e = hipMemcpyAsync(htot, totals, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(totals)");
         e = hipStreamSynchronize(c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -289,12 +314,21 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         const int64_t kept = (int64_t)htot[0];
         const int64_t hooks = (int64_t)htot[1];
         const int64_t fresh = (int64_t)htot[3];   // hooked since the last full flatten
+        // Finds that stopped at the hop bound: the pass left deep chains, so
+        // the forest is flattened completely before the next pass.
+        const bool deep = kept > 0 && htot[4] > 0;
+        if (deep) {
+            if ((rc = flatten_all(c, totals + 5, htot + 8, &deep_rounds))) return rc;
+            ++deep_rounds;
+            e = hipMemsetAsync(totals + 4, 0, sizeof(unsigned long long), c.stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+        }
         // Shortcut: point the roots hooked since the last full flatten at
         // their roots, unless nothing survives or the pass's hooks far
         // outnumber the survivors (typically after the first pass, when nearly
         // every vertex was hooked): then the few survivors' finds walk the
         // extra links, and the final labelling flattens everything once.
-        const bool jump = kept > 0 && fresh > 0 && hooks <= kLazyJump * kept;
+        const bool jump = !deep && kept > 0 && fresh > 0 && hooks <= kLazyJump * kept;
         if (jump) {
             int k1 = c.kbeg();
             e = launch_sv_shortcut(c.parent, (const int32_t*)phook + (int64_t)jump_lo * cap, hooked_count + jump_lo,
@@ -320,11 +354,8 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         in_cnt = out_cnt;
         m_in = kept;
     }
-    int k2 = c.kbeg();
-    e = launch_sv_finalize(c.parent, c.n, c.stream);
-    if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
-    c.kend(CC_K_SV_FINALIZE, k2, 8.0 * c.n);
-    if (c.stats) c.bytes += 8.0 * c.n;
+    if ((rc = flatten_all(c, totals + 5, htot + 8, &deep_rounds))) return rc;
+    if (c.stats) c.stats->sv_deep_rounds = deep_rounds;
     return CC_OK;
 }
 

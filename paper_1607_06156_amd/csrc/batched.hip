@@ -39,16 +39,20 @@ struct BatchArgs {
     uint32_t* hcnt;       // per-tile hooked counts
     int32_t* hooked;      // per-tile hooked roots
     unsigned int* bar;    // [0] arrivals, [1] generation
-    unsigned long long* status;  // [0] error bits, [1] passes, [2] range errors
+    unsigned long long* status;  // [0] error bits, [1] passes, [2] range errors, [4] labels left unshifted
     int32_t max_passes;
     int32_t max_link;     // hook attempts per edge per pass (see sv_segment)
-    unsigned long long* part;   // per-block partials: survivors (2 x gridDim), then hooks (2 x gridDim)
+    unsigned long long* part;   // per-block partials: survivors, hooks, finds stopped at the hop
+                                // bound (2 x gridDim each)
 };
 
 constexpr int64_t kTileE = (int64_t)kBlock * kEPT;   // edges (or vertices) per tile
 
 enum : unsigned long long { kErrRange = 1, kErrOffsets = 2, kErrBarrier = 4, kErrPasses = 8 };
 constexpr int kStampBase = 8;    // status[8 + i]: wall clock when barrier i was passed
+// status[kDeep] = 1: the final compression left a root beyond the walk bound;
+// the labels stay global and unflattened, and the host finishes them
+constexpr int kDeep = 4;
 constexpr unsigned long long kLazyJump = 8;   // jump hooked roots only if hooks <= 8 x survivors
 constexpr int kMaxStamps = 40;
 
@@ -118,9 +122,14 @@ struct TileWalk {
     }
 };
 
-__global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
+// At most 80 VGPRs, so that 6 waves per SIMD stay resident (the persistent
+// grid is sized to what is co-resident); 7 would spill.
+__global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
     __shared__ uint32_t lds[kWaves + 1];
-    __shared__ unsigned long long sh_total, sh_hooks;
+    // sh_total / sh_hooks / sh_long: grid-wide sums, written and read only at
+    // the top of a pass; sh_blong: this workgroup's count of finds stopped at
+    // the hop bound, summed at the end of a pass and read by thread 0 only
+    __shared__ unsigned long long sh_total, sh_hooks, sh_long, sh_blong;
     __shared__ int32_t sh_g;
     const int b = blockIdx.x;
     const int nb = gridDim.x;
@@ -134,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
         return;
     }
     const TileWalk tw(T, b, nb);
+    const int64_t TV = ((int64_t)A.n + kTileE - 1) / kTileE;   // vertex tiles
 
     // ---- init: identity forest, offset checks
     for (int64_t x = gtid; x < A.n; x += gstride) A.parent[x] = (int32_t)x;
@@ -151,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     // to the graphs of its own edges (it sees them in increasing order),
     // shifts the ids to global ones and drops (and counts) edges with an id
     // outside their graph.
-    uint32_t bad = 0;
+    uint32_t bad = 0, nlong = 0;
     unsigned long long block_kept = 0, block_hooks = 0;
     for (int64_t t = tw.first; t < tw.end; t += tw.step) {
         const int64_t e0 = t * kTileE;
@@ -178,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
         uint32_t kept = 0, hk = 0;
         if (len > 0)
             sv_segment(len, load, A.parent, A.buf0 + t * kTileE, A.hooked + t * kTileE, true, A.max_link, kept, hk,
-                       lds);
+                       nlong, lds);
         if (threadIdx.x == 0) {
             A.cnt0[t] = kept;
             A.hcnt[t] = hk;
@@ -193,9 +203,15 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     }
     unsigned long long* const part_base = A.part;
     unsigned long long* part_rd = part_base;
+    for (int o = 32; o > 0; o >>= 1) nlong += __shfl_xor(nlong, o);
+    if (threadIdx.x == 0) sh_blong = 0;
+    __syncthreads();
+    if (lane_id() == 0 && nlong) atomicAdd(&sh_blong, (unsigned long long)nlong);
+    __syncthreads();
     if (threadIdx.x == 0) {
         part_base[b] = block_kept;
         part_base[2 * nb + b] = block_hooks;
+        part_base[4 * nb + b] = sh_blong;
     }
 
     int pass = 1;
@@ -208,39 +224,58 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
         if (load_status(A.status)) return;
         stamp(A.status, pass);
         // every block sums the same partials and takes the same decisions
-        unsigned long long s = 0, sh = 0;
+        unsigned long long s = 0, sh = 0, sl = 0;
         for (int i = threadIdx.x; i < nb; i += kBlock) {
             s += part_rd[i];
             sh += part_rd[2 * nb + i];
+            sl += part_rd[4 * nb + i];
         }
         for (int o = 32; o > 0; o >>= 1) {
             s += __shfl_xor(s, o);
             sh += __shfl_xor(sh, o);
+            sl += __shfl_xor(sl, o);
         }
         if (threadIdx.x == 0) {
             sh_total = 0;
             sh_hooks = 0;
+            sh_long = 0;
         }
         __syncthreads();
         if (lane_id() == 0) {
             atomicAdd(&sh_total, s);
             atomicAdd(&sh_hooks, sh);
+            atomicAdd(&sh_long, sl);
         }
         __syncthreads();
-        const unsigned long long total = sh_total, hooks = sh_hooks;
+        const unsigned long long total = sh_total, hooks = sh_hooks, deep = sh_long;
         if (total == 0) break;   // the final compression resolves every link
         // Pointer jumping of the roots hooked in this block's tiles, unless
         // they far outnumber the surviving edges (typically after the first
         // pass, when nearly every vertex was hooked): then the next pass's
         // finds walk the extra links of the few survivors instead, and the
-        // final compression flattens everything once.
-        if (hooks <= kLazyJump * total) {
+        // final compression flattens everything once.  If some find of the
+        // pass stopped at the hop bound, every vertex of this block's tiles is
+        // moved up instead (at most kMaxHops links), so deep chains shrink by
+        // that factor per pass.  Either way only vertices that were no longer
+        // roots at the barrier are written, and a hook of the next pass only
+        // ever lands on a root, so the next pass may start beside these stores.
+        if (deep > 0) {
+            const TileWalk vw(TV, b, nb);
+            for (int64_t t = vw.first; t < vw.end; t += vw.step) {
+                for (int64_t x = t * kTileE + threadIdx.x; x < (t + 1) * kTileE && x < A.n; x += kBlock) {
+                    const int32_t p = A.parent[x];
+                    bool root;
+                    if (p != (int32_t)x) A.parent[x] = find_bounded(A.parent, p, &root);
+                }
+            }
+        } else if (hooks <= kLazyJump * total) {
             for (int64_t t = tw.first; t < tw.end; t += tw.step) {
                 const uint32_t hc = A.hcnt[t];
                 const int32_t* h = A.hooked + t * kTileE;
                 for (uint32_t j = threadIdx.x; j < hc; j += kBlock) {
                     const int32_t x = h[j];
-                    A.parent[x] = find_root(A.parent, x);
+                    bool root;
+                    A.parent[x] = find_bounded(A.parent, x, &root);
                 }
             }
         }
@@ -257,6 +292,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
         unsigned long long* part_out = part_base + (pass & 1) * nb;
         block_kept = 0;
         block_hooks = 0;
+        nlong = 0;
         for (int64_t t = tw.first; t < tw.end; t += tw.step) {
             const uint32_t len = cin[t];
             uint32_t kept = 0, hk = 0;
@@ -269,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
                     return true;
                 };
                 sv_segment((int64_t)len, load, A.parent, out + t * kTileE, A.hooked + t * kTileE, true, A.max_link,
-                           kept, hk, lds);
+                           kept, hk, nlong, lds);
             }
             if (threadIdx.x == 0) {
                 cout[t] = kept;
@@ -278,9 +314,15 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
             block_kept += kept;
             block_hooks += hk;
         }
+        for (int o = 32; o > 0; o >>= 1) nlong += __shfl_xor(nlong, o);
+        if (threadIdx.x == 0) sh_blong = 0;
+        __syncthreads();
+        if (lane_id() == 0 && nlong) atomicAdd(&sh_blong, (unsigned long long)nlong);
+        __syncthreads();
         if (threadIdx.x == 0) {
             part_out[b] = block_kept;
             part_out[2 * nb + b] = block_hooks;
+            part_out[4 * nb + b] = sh_blong;
         }
         part_rd = part_out;
         ++pass;
@@ -289,17 +331,25 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A) {
     }
     if (b == 0 && threadIdx.x == 0) A.status[1] = (unsigned long long)pass;
 
-    // ---- final labels: compress to roots, then shift to graph-local ids
-    const int64_t TV = ((int64_t)A.n + kTileE - 1) / kTileE;   // vertex tiles
+    // ---- final labels: compress to roots, then shift to graph-local ids.
+    // A root beyond the walk bound (a chain deeper than kMaxHops links) leaves
+    // the labels global; the host then finishes the flatten and the shift.
     const TileWalk vw(TV, b, nb);
+    bool left = false;
     for (int64_t t = vw.first; t < vw.end; t += vw.step) {
         for (int64_t x = t * kTileE + threadIdx.x; x < (t + 1) * kTileE && x < A.n; x += kBlock) {
             const int32_t p = A.parent[x];
-            if (p != (int32_t)x) A.parent[x] = find_root(A.parent, p);
+            if (p == (int32_t)x) continue;
+            bool root;
+            const int32_t q = find_bounded(A.parent, p, &root);
+            if (q != p) A.parent[x] = q;
+            left |= !root;
         }
     }
+    if (ballot(left) && lane_id() == 0)
+        __hip_atomic_store(&A.status[kDeep], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     grid_barrier(A.bar, A.status);
-    if (load_status(A.status)) return;
+    if (load_status(A.status) || load_status(&A.status[kDeep])) return;
     stamp(A.status, pass + 1);
     for (int64_t t = vw.first; t < vw.end; t += vw.step) {
         const int64_t x0 = t * kTileE;

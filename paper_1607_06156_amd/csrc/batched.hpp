@@ -17,7 +17,7 @@ struct BatchArgsHost {
     int32_t* labels;
     int2* buf0;
     int2* buf1;
-    unsigned long long* part;   // 2 x blocks survivor partials
+    unsigned long long* part;   // 6 x blocks partials (survivors, hooks, bounded finds; 2 arrays each)
     uint32_t* cnt0;
     uint32_t* cnt1;
     uint32_t* hcnt;

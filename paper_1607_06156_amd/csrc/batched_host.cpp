@@ -20,7 +20,29 @@
 namespace ccmi {
 
 constexpr size_t kBatchCtl = 1024;      // barrier words + status block
-constexpr int kStatusWords = 48;        // status[0..3) codes, status[8..48) pass stamps
+constexpr int kStatusWords = 48;        // status[0..3) codes, [4] deep chains left, status[8..48) pass stamps
+constexpr int kStatusDeep = 4;
+
+// The persistent kernel's final compression met a chain deeper than one walk
+// (kMaxHops links) and left the labels as global, unflattened parents: flatten
+// rounds until every vertex points at its root, then shift to graph-local
+// labels.  ctl: the kernel's control block (the round flag sits at +512);
+// hw: pinned host words (hw[kStatusWords] is used).
+static int finish_deep(const BatchArgsHost& h, void* ctl, unsigned long long* hw, hipStream_t s) {
+    unsigned long long* open = (unsigned long long*)((char*)ctl + 512);
+    for (int r = 0;; ++r) {
+        if (r >= 16) return fail(CC_EINTERNAL, "flatten did not finish");
+        hipError_t e = hipMemsetAsync(open, 0, sizeof(*open), s);
+        if (e == hipSuccess) e = launch_sv_finalize(h.labels, h.n, open, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hw + kStatusWords, open, sizeof(*open), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "batched flatten");
+        if (!hw[kStatusWords]) break;
+    }
+    hipError_t e = launch_union_unshift(h.labels, h.vert_off, h.G, h.n, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? CC_OK : hip_fail(e, "union unshift");
+}
 
 // ------------------------------------------------------------ autotuner
 // Chooses the persistent grid size (edges per workgroup segment) and the hook
@@ -89,8 +111,9 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     if ((rc = ws.get(WS_EDGES1, slots * sizeof(int2), &p1))) return rc;
     if ((rc = ws.get(WS_HOOKED, slots * sizeof(int32_t), &ph))) return rc;
     const size_t cnt_bytes = ((size_t)tiles * 3 * sizeof(uint32_t) + 255) & ~(size_t)255;
-    // per-tile counts, then per-block partials (survivors and hooks, two arrays each)
-    if ((rc = ws.get(WS_SEGCOUNT, cnt_bytes + (size_t)blocks * 4 * sizeof(unsigned long long), &pc))) return rc;
+    // per-tile counts, then per-block partials (survivors, hooks and finds
+    // stopped at the hop bound, two arrays each)
+    if ((rc = ws.get(WS_SEGCOUNT, cnt_bytes + (size_t)blocks * 6 * sizeof(unsigned long long), &pc))) return rc;
     if ((rc = ws.get(WS_BATCH, kBatchCtl, &pb))) return rc;
     h.buf0 = (int2*)p0;
     h.buf1 = (int2*)p1;
@@ -132,6 +155,7 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
+    if (status_host[0] == 0 && status_host[kStatusDeep]) return finish_deep(h, pb, status_host, s);
     return CC_OK;
 }
 
@@ -214,6 +238,7 @@ static int status_code(const unsigned long long* st) {
     if (st[0] & 2) return fail(CC_EINVAL, "edge_off / vert_off are not non-decreasing");
     if (st[0] & 4) return fail(CC_EINTERNAL, "grid barrier timed out");
     if (st[0] & 8) return fail(CC_EINTERNAL, "pass cap reached");
+    if (st[0] & 16) return fail(CC_EINTERNAL, "flatten did not finish");
     return CC_OK;
 }
 

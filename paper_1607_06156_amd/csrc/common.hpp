@@ -30,17 +30,28 @@ __device__ __forceinline__ uint32_t atomic_or_agent(uint32_t* p, uint32_t v) {
     return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Root of x in the parent forest.  parent[] may change concurrently (hooks by
-// other lanes) and a plain load may return an older value, but every value
-// parent[x] ever holds is an id <= x of a vertex connected to x, so the walk
-// strictly descends, terminates, and ends at a vertex that was a root when
-// read.
-__device__ __forceinline__ int32_t find_root(const int32_t* parent, int32_t x) {
+// Longest walk up the parent forest taken in one go.  Trees are shallow on
+// the workloads of Section V, but one pass can link a long run of vertices
+// at once (a path whose ids and edge order both follow it hooks every vertex
+// onto its predecessor concurrently), and an unbounded walk from each vertex
+// of such a chain costs time quadratic in its length.  A walk that reaches
+// this bound stops at the ancestor it reached; the flatten rounds (each
+// moves every vertex at least this far up) finish the chain.
+constexpr int kMaxHops = 64;
+
+// Walk from x towards its root, at most kMaxHops links; returns the vertex
+// reached and sets *root when it is a root.  parent[] may change concurrently
+// (hooks by other lanes) and a plain load may return an older value, but
+// every value parent[x] ever holds is an id <= x of a vertex connected to x,
+// so the walk strictly descends and ends at an ancestor of x (a root when
+// *root, as it was when read).
+__device__ __forceinline__ int32_t find_bounded(const int32_t* parent, int32_t x, bool* root) {
     int32_t p = parent[x];
-    while (p != x) {
+    for (int h = 0; h < kMaxHops && p != x; ++h) {
         x = p;
         p = parent[x];
     }
+    *root = p == x;
     return x;
 }
 
@@ -85,7 +96,8 @@ hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s);
 // out.nseg segments of out.cap edges; this launch covers segments
 // [seg0, seg0 + nblocks), one block each.  Writes survivors into out (if
 // write_out), hooked roots into hooked (segments of the same cap), per-segment
-// counts, and accumulates totals[2] (range errors).
+// counts, and accumulates totals[2] (range errors) and totals[4] (edges whose
+// find stopped at the hop bound: the forest needs flatten rounds).
 hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
                               SegList out, int32_t seg0, int32_t nblocks, int write_out, int max_link,
                               int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals, hipStream_t s);
@@ -94,14 +106,17 @@ hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int
 hipError_t launch_sv_pass_seg(SegList in, int32_t seg0, int32_t nblocks, int32_t* parent, SegList out, int write_out,
                               int max_link, int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
                               hipStream_t s);
-// pointer-jumps the hooked roots of each segment (no hook may run concurrently)
+// pointer-jumps the hooked roots of each segment, at most kMaxHops links each
+// (no hook may run concurrently)
 hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count, int64_t cap,
                               int32_t nseg, hipStream_t s);
 // totals[0] = sum(kept_count), totals[1] = sum(hooked_count) over nseg
 // segments, totals[3] = sum(hooked_count) over segments seg_lo .. nseg-1
 hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg, int32_t seg_lo,
                             unsigned long long* totals, hipStream_t s);
-// parent[x] = root(x) for every x (no hook may run concurrently)
-hipError_t launch_sv_finalize(int32_t* parent, int32_t n, hipStream_t s);
+// one flatten round: parent[x] = root(x) for every x whose root lies at most
+// kMaxHops links up, else the ancestor that far up, and then *open = 1 (set
+// only, never cleared here).  No hook may run concurrently.
+hipError_t launch_sv_finalize(int32_t* parent, int32_t n, unsigned long long* open, hipStream_t s);
 
 }  // namespace ccmi

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
     const int b = seg0 + blockIdx.x;
     int2* dst = out.buf + (int64_t)b * out.cap;
     int32_t* hdst = hooked + (int64_t)b * out.cap;
-    uint32_t kept_off = 0, hook_off = 0, bad = 0;
+    uint32_t kept_off = 0, hook_off = 0, bad = 0, nlong = 0;
     if (SOA) {
         const int64_t base = (int64_t)b * out.cap;
         int64_t len = m - base;
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
             }
             return true;
         };
-        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, lds);
+        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds);
     } else {
         const int2* src = in.buf + (int64_t)b * in.cap;
         const int64_t len = in.count[b];
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
             *c = e.y;
             return true;
         };
-        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, lds);
+        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds);
     }
     // per-block results (no global atomics on the fast path)
     if (threadIdx.x == 0) {
@@ -89,10 +89,14 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
         for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off);
         if (lane_id() == 0 && bad) atomic_add_agent(&totals[2], bad);
     }
+    // so are finds stopped at the hop bound (totals[4])
+    for (int off = 32; off > 0; off >>= 1) nlong += __shfl_xor(nlong, off);
+    if (lane_id() == 0 && nlong) atomic_add_agent(&totals[4], nlong);
 }
 
-// Pointer jumping for the roots hooked in the last pass: each is pointed
-// straight at its current root.  Runs between passes (no hook in flight).
+// Pointer jumping for the roots hooked in the last pass: each is pointed at
+// its current root (or, past kMaxHops links, at the ancestor reached).  Runs
+// between passes (no hook in flight).
 __global__ __launch_bounds__(kBlock) void sv_shortcut_kernel(int32_t* parent, const int32_t* __restrict__ hooked,
                                                              const uint32_t* __restrict__ hooked_count, int64_t cap) {
     const int b = blockIdx.x;
@@ -100,8 +104,8 @@ __global__ __launch_bounds__(kBlock) void sv_shortcut_kernel(int32_t* parent, co
     const int32_t* h = hooked + (int64_t)b * cap;
     for (uint32_t j = threadIdx.x; j < cnt; j += kBlock) {
         int32_t x = h[j];
-        int32_t r = find_root(parent, x);
-        parent[x] = r;
+        bool root;
+        parent[x] = find_bounded(parent, x, &root);
     }
 }
 
@@ -155,15 +159,25 @@ __global__ __launch_bounds__(kTotThreads) void sv_totals_kernel(const uint32_t* 
 // alone (no hook in flight), so the plain stores cannot undo an atomicMin.
 // Serves as the final labelling and as the shortcut between the chunks of the
 // first pass.
-__global__ __launch_bounds__(kBlock) void sv_finalize_kernel(int32_t* parent, int32_t n) {
+// Flatten round: every vertex is pointed at its root, or, when the root lies
+// more than kMaxHops links up, at the ancestor reached, and then *open is set
+// (one store per wave).  No hook may run concurrently.  Each round moves every
+// vertex of a deep chain at least kMaxHops links up, so depth d takes about
+// log(d) / log(kMaxHops) rounds; shallow forests finish in one.
+__global__ __launch_bounds__(kBlock) void sv_finalize_kernel(int32_t* parent, int32_t n,
+                                                             unsigned long long* open) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * kBlock;
+    bool left = false;
     for (; i < n; i += stride) {
         int32_t p = parent[i];
         if (p == (int32_t)i) continue;
-        int32_t r = find_root(parent, p);
+        bool root;
+        int32_t r = find_bounded(parent, p, &root);
         if (r != p) parent[i] = r;
+        left |= !root;
     }
+    if (ballot(left) && lane_id() == 0) __hip_atomic_store(open, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 static int grid_for(int64_t n, int per_thread = 1) {
@@ -210,9 +224,9 @@ hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_c
     return hipGetLastError();
 }
 
-hipError_t launch_sv_finalize(int32_t* parent, int32_t n, hipStream_t s) {
+hipError_t launch_sv_finalize(int32_t* parent, int32_t n, unsigned long long* open, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    sv_finalize_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(parent, n);
+    sv_finalize_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(parent, n, open);
     return hipGetLastError();
 }
 

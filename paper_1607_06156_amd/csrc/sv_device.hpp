@@ -21,12 +21,18 @@ constexpr int kEPT = 4;   // edges per thread per tile
 // finished by then is kept as that pair.  max_link = 1 is the plain SV pass
 // (one hook per edge per pass, the rest waits for the next pass).
 //
+// A find stops after kMaxHops links.  An edge whose find stopped short of a
+// root is kept as the pair of vertices reached (each is an ancestor of its
+// endpoint, so the pair carries the edge's connection) and counted in nlong
+// (per thread); its caller then flattens the forest before the next pass.
+//
 // Survivors go to dst[kept_off ...] (if write_out), roots hooked in this pass
 // to hdst[hook_off ...].  Offsets are block-uniform running counts.
 template <class Load>
 __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* parent, int2* __restrict__ dst,
                                            int32_t* __restrict__ hdst, bool write_out, int max_link,
-                                           uint32_t& kept_off, uint32_t& hook_off, uint32_t* lds) {
+                                           uint32_t& kept_off, uint32_t& hook_off, uint32_t& nlong,
+                                           uint32_t* lds) {
     for (int64_t t0 = 0; t0 < len; t0 += kBlock * kEPT) {
         int32_t a[kEPT], c[kEPT], pa[kEPT], pc[kEPT];
         bool valid[kEPT];
@@ -46,18 +52,28 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
         // Walk the 2 * kEPT root chains of this thread in lockstep: every
         // step issues the next load of each unfinished chain before using
         // any, so the dependent loads of different chains overlap instead of
-        // queueing behind each other.  a[k] / c[k] become the roots.
-        for (;;) {
+        // queueing behind each other.  a[k] / c[k] become the roots; after
+        // kMaxHops steps (cut) a chain still moving stops where it is, and
+        // is recognised below by pa[k] != a[k] (or pc[k] != c[k]).
+        bool cut = false;
+        for (int hop = 0;; ++hop) {
             bool more = false, mva[kEPT], mvc[kEPT];
 #pragma unroll
             for (int k = 0; k < kEPT; ++k) {
                 mva[k] = valid[k] && pa[k] != a[k];
                 mvc[k] = valid[k] && pc[k] != c[k];
-                if (mva[k]) a[k] = pa[k];
-                if (mvc[k]) c[k] = pc[k];
                 more |= mva[k] | mvc[k];
             }
             if (!more) break;
+            if (hop == kMaxHops) {
+                cut = true;
+                break;
+            }
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                if (mva[k]) a[k] = pa[k];
+                if (mvc[k]) c[k] = pc[k];
+            }
 #pragma unroll
             for (int k = 0; k < kEPT; ++k) {
                 if (mva[k]) pa[k] = parent[a[k]];
@@ -75,6 +91,14 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
             if (!valid[k]) continue;
             int32_t ra = a[k];
             int32_t rc = c[k];
+            if (cut && (pa[k] != ra || pc[k] != rc)) {   // a find stopped short of a root
+                ++nlong;
+                if (ra != rc) {
+                    keep[k] = true;
+                    e[k] = make_int2(ra, rc);
+                }
+                continue;
+            }
             for (int tries = 0; ra != rc;) {
                 const int32_t lo = ra < rc ? ra : rc;
                 const int32_t hi = ra < rc ? rc : ra;
@@ -89,8 +113,17 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
                     e[k] = old > lo ? make_int2(old, hi) : make_int2(lo, hi);
                     break;
                 }
-                ra = find_root(parent, old);
-                rc = find_root(parent, lo);
+                bool root_a, root_c;
+                ra = find_bounded(parent, old, &root_a);
+                rc = find_bounded(parent, lo, &root_c);
+                if (!(root_a && root_c)) {   // keep the pair still to be joined, as ancestors
+                    ++nlong;
+                    if (ra != rc) {
+                        keep[k] = true;
+                        e[k] = make_int2(ra, rc);
+                    }
+                    break;
+                }
             }
         }
         // wave ballots -> slot prefixes; one block scan of packed (kept | hooks << 16)
