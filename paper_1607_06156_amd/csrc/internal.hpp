@@ -141,10 +141,13 @@ struct BfsResult {
     int levels = 0, bottom_up = 0;
     int64_t visited = 0, examined = 0;
     int64_t unvisited_entries = 0;   // adjacency entries in the rows of unvisited vertices
+    bool abandoned = false;          // stopped at the level budget with the frontier not empty
 };
 
 int run_degree_pass(Call& c, bool want_csr, DegreeResult* r);
+// max_levels > 0: stop after that many levels if the frontier is not empty yet
+// (br->abandoned; the visited set is then incomplete)
 int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32_t seed, int64_t seed_deg,
-            uint32_t** vis_out, BfsResult* br);
+            int max_levels, uint32_t** vis_out, BfsResult* br);
 
 }  // namespace ccmi

@@ -181,7 +181,7 @@ int decide_heuristic(Call& c, DegreeResult& r, int* route) {
 
 // ------------------------------------------------------------------- BFS
 int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32_t seed, int64_t seed_deg,
-            uint32_t** vis_out, BfsResult* br) {
+            int max_levels, uint32_t** vis_out, BfsResult* br) {
     Workspace& ws = *c.ws;
     const int32_t n = c.n;
     const int64_t words = ((int64_t)n + 31) >> 5;
@@ -269,8 +269,13 @@ int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32
             qn = (int64_t)host[0];
             topdown = true;
         }
+        if (max_levels > 0 && levels >= max_levels && nf > 0) {
+            br->abandoned = true;
+            break;
+        }
     }
     (void)nadj;
+    br->unvisited_entries = mu;   // 2m minus the degrees of the visited vertices
     br->levels = levels;
     br->bottom_up = bu_levels;
     br->visited = visited;
@@ -278,6 +283,12 @@ int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32
     *vis_out = vis;
     return CC_OK;
 }
+
+// The BFS step is meant for a short-diameter component (Section III-B): each
+// level costs a launch and a host round trip, so a long path would cost one per
+// hop.  A BFS still running after this many levels is abandoned before any
+// label is written, and SV labels the whole graph instead.
+constexpr int kMaxBfsLevels = 1024;
 
 // R0: CSR (if not built yet), BFS, label, filter, then SV on the rest
 int run_bfs_route(Call& c, DegreeResult& r) {
@@ -306,9 +317,30 @@ int run_bfs_route(Call& c, DegreeResult& r) {
     int t1 = c.timer->mark();
     uint32_t* vis = nullptr;
     BfsResult br{};
-    rc = run_bfs(c, r.off, r.adj, 2 * c.m, r.argmax, r.max_degree, &vis, &br);
+    rc = run_bfs(c, r.off, r.adj, 2 * c.m, r.argmax, r.max_degree, kMaxBfsLevels, &vis, &br);
     if (rc) return rc;
     int t2 = c.timer->mark();
+    if (br.abandoned) {
+        if (c.stats) {
+            c.stats->route = CC_R1_SV;
+            c.stats->bfs_levels = br.levels;
+            c.stats->bfs_bottom_up_levels = br.bottom_up;
+            c.stats->bfs_seed = r.argmax;
+            c.stats->bfs_visited = br.visited;
+            c.stats->bfs_edges_examined = br.examined;
+            c.stats->ms_csr = c.timer->ms(t0, t1);
+            c.stats->ms_bfs = c.timer->ms(t1, t2);
+        }
+        SvInput in;
+        in.soa = true;
+        in.u = c.u;
+        in.v = c.v;
+        in.m = c.m;
+        int t4 = c.timer->mark();
+        rc = run_sv(c, in, CC_R1_SV, c.opt.theta, c.opt.max_passes);
+        if (c.stats) c.stats->ms_sv = c.timer->ms(t4, c.timer->mark());
+        return rc;
+    }
     // label + filter
     void *ptot, *pe0, *pcnt;
     if ((rc = ws.get(WS_TOTALS, 64 * sizeof(unsigned long long), &ptot))) return rc;

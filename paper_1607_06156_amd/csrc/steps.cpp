@@ -172,7 +172,7 @@ CC_API int cc_bfs(const int64_t* off, const int32_t* adj, int32_t n, int64_t nad
     c.timer = &tm;
     uint32_t* vis = nullptr;
     BfsResult br;
-    rc = run_bfs(c, off, adj, nadj, seed, sdeg, &vis, &br);
+    rc = run_bfs(c, off, adj, nadj, seed, sdeg, 0, &vis, &br);
     if (rc) return rc;
     e = hipMemcpyAsync(visited, vis, (size_t)(((int64_t)n + 31) >> 5) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(visited)");

@@ -16,7 +16,7 @@ from gpu_util import assert_labels_equal, oracle_labels, say, to_dev
 pytestmark = pytest.mark.gpu
 ccmi = pytest.importorskip("paper_1607_06156_amd")
 
-ROUTES = ["sv", "sv-theta", "heuristic"]   # the forced BFS route on a path would walk its whole diameter
+ROUTES = ["sv", "sv-theta", "heuristic"]   # the forced BFS route on a long path: test_forced_bfs_on_a_long_path
 CAP = 200                                  # SV passes: a runaway loop fails fast instead of spinning
 
 
@@ -95,3 +95,18 @@ def test_ordered_paths_batched():
     lab, st = ccmi.label_batched(*args, stats=True)
     assert np.array_equal(lab.cpu().numpy(), np.concatenate(exp))
     say(f"   passes={st['passes']} blocks={st['blocks']}")
+
+
+@pytest.mark.parametrize("permute", [False, True])
+def test_forced_bfs_on_a_long_path(permute):
+    """The BFS step is for short-diameter components: on a 3M-vertex path it
+    stops after 1024 levels, before writing any label, and SV labels the
+    whole graph (route reported R1)."""
+    n = 3_000_000
+    order = gen.permutation(n, seed=12) if permute else np.arange(n, dtype=np.int32)
+    u, v = order[:-1].astype(np.int32), order[1:].astype(np.int32)
+    say(f"[gpu] forced bfs+sv on a {'permuted' if permute else 'ordered'} path n={n}")
+    lab, st = _label(u, v, n, "bfs+sv")
+    assert torch.all(lab == 0)
+    assert st["route"] == ccmi.R1_SV and st["bfs_levels"] == 1024
+    say(f"   bfs_visited={st['bfs_visited']} ms={st['ms_total']:.1f}")

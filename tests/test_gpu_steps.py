@@ -221,11 +221,16 @@ def test_bfs_route_rest_from_list_and_from_csr(leaves, side):
     rng = np.random.default_rng(leaves + side)
     u, v, n = _star_and_lattice(leaves, side, rng)
     say(f"[gpu] bfs route rest: star {leaves} + lattice {side}^2, n={n} m={u.shape[0]}")
-    lab, st = ccmi.label(to_dev(u), to_dev(v), n, route="bfs+sv", stats=True)
+    lab, st = ccmi.label(to_dev(u), to_dev(v), n, route="bfs+sv", stats=True, profile=True)
     assert_labels_equal(lab, oracle.labels_uf(u, v, n), f"star{leaves}+lattice{side}")
     r = hybrid.bfs_route(u, v, n)
     assert st["bfs_seed"] == r["seed"] and st["bfs_visited"] == leaves + 1
     assert st["edges_after_filter"] == r["u"].shape[0]
+    # which path read the rest: the rows of the unvisited vertices hold
+    # 4 side (side - 1) entries against m edges; from the CSR rows it takes a
+    # count and an emit launch, from the edge list one filter launch
+    from_csr = 4 * side * (side - 1) <= u.shape[0]
+    assert st["kernel_launches"][ccmi.KERNEL_CLASSES.index("filter")] == (2 if from_csr else 1)
 
 
 def test_two_level_buckets_large_n():
