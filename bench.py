@@ -173,9 +173,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
-        "stats": {k: st[k] for k in ["sv_passes", "active_edges", "ks_statistic", "ks_alpha", "ks_dmin",
-                                      "bfs_levels", "bfs_visited", "edges_after_filter", "ms_predict", "ms_csr",
-                                      "ms_bfs", "ms_filter", "ms_sv", "ms_total"]},
+        "stats": {k: st[k] for k in ["sv_passes", "sv_deep_rounds", "active_edges", "ks_statistic", "ks_alpha",
+                                      "ks_dmin", "bfs_levels", "bfs_visited", "edges_after_filter", "ms_predict",
+                                      "ms_csr", "ms_bfs", "ms_filter", "ms_sv", "ms_total"]},
         "forced_routes": extra,
     }
     print(json.dumps(rec), flush=True)
