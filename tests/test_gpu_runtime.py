@@ -95,3 +95,45 @@ def test_batched_from_a_second_process():
     assert r.returncode == 0, r.stderr[-2000:]
     line = [ln for ln in r.stdout.splitlines() if ln.startswith("ok")][-1]
     say(f"   child: {line} ({'fallback' if line.split()[2] == '0' else 'persistent grid'})")
+
+
+def test_concurrent_calls_from_threads():
+    """Four host threads, each on its own stream, call the library at once:
+    three label single graphs (a different route each call), one labels a
+    batch.  The calls share each device's workspace under its lock; every
+    result is exact and each thread's error slot stays its own."""
+    import threading
+    graphs = [gen.workload("rmat16"), gen.gnm(200_000, 300_000, seed=3), gen.grid(400, 0.6, seed=4)]
+    expects = [oracle_labels(g) for g in graphs]
+    b = gen.batch(20, 99, lg_hi=12.0)
+    bexp = _expected(b)
+    errors = []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for rep, route in enumerate(("sv", "heuristic", "bfs+sv")):
+                    if k == 3:
+                        lab = ccmi.label_batched(*_batch_args(b))
+                        exp = bexp
+                    else:
+                        g = graphs[k]
+                        lab = ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route=route)
+                        exp = expects[k]
+                    s.synchronize()
+                    if not np.array_equal(lab.cpu().numpy(), exp):
+                        errors.append(f"thread {k} call {rep}: labels differ")
+            if ccmi.lib().cc_last_error() not in (b"", None):
+                errors.append(f"thread {k}: error slot not empty")
+        except Exception as e:   # noqa: BLE001 -- reported below
+            errors.append(f"thread {k}: {e!r}")
+
+    say("[gpu] 4 threads calling at once")
+    ts = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in ts)
+    assert not errors, errors
