@@ -56,6 +56,35 @@ def test_struct_layouts_match_header(lib):
     assert ccmi.Stats.active_edges.offset % 8 == 0
 
 
+def test_struct_layouts_match_compiled_header(tmp_path):
+    """Every field of the Python mirrors of cc_options, cc_stats and
+    cc_batch_stats sits at the offset a C compiler gives it in include/cc.h,
+    and the sizes agree."""
+    import shutil
+    import subprocess
+    import paper_1607_06156_amd as ccmi
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"cc_options": ccmi.Options, "cc_stats": ccmi.Stats, "cc_batch_stats": ccmi.BatchStats}
+    lines = []
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "cc.h"\nint main(void) {\n'
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, f"{cname}.{fname}"
+
+
 def test_invalid_arguments_rejected_on_host(lib):
     lib.cc_label.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                              ctypes.c_void_p]
