@@ -12,7 +12,9 @@
 //               that reaches it in this pass (the atomic keeps the minimum of
 //               all candidates, as p_min = min C(p) does);
 //  * shortcut-- each root hooked in the pass is pointed straight at its new
-//               root (pointer jumping, Fig. "doubling");
+//               root (pointer jumping, Fig. "doubling"); every walk up the
+//               forest stops after kMaxHops links, and flatten rounds finish
+//               a deeper chain;
 //  * compact -- an edge whose endpoints already share a root is finished and
 //               dropped; survivors are rewritten as (root, root), so the next
 //               pass starts from roots.  This is the exclusion of completed
