@@ -61,6 +61,12 @@ extern "C" {
 #define CC_ROUTE_BFS_SV 4     /* force R0: BFS from the max-degree vertex, then SV on the rest */
 #define CC_ROUTE_SV_THETA 5   /* force R2: SV with up to theta hook attempts per edge per pass */
 
+/* Whatever the route requested, the BFS step (R0) is taken only where it
+ * applies: n <= 2^29 and m < 2^31 (the bucketed degree pass), and a BFS that
+ * is still running after 1024 levels (a component of long diameter, which
+ * Section III-B does not intend it for) is abandoned before it writes any
+ * label.  SV then labels the whole graph and cc_stats.route reports R1. */
+
 /* route ids reported in cc_stats.route and used as router classes */
 #define CC_R0_BFS_SV 0
 #define CC_R1_SV 1
