@@ -63,7 +63,7 @@ extern "C" {
 
 /* Whatever the route requested, the BFS step (R0) is taken only where it
  * applies: n <= 2^29 and m < 2^31 (the bucketed degree pass), and a BFS that
- * is still running after 1024 levels (a component of long diameter, which
+ * is still running after 256 levels (a component of long diameter, which
  * Section III-B does not intend it for) is abandoned before it writes any
  * label.  SV then labels the whole graph and cc_stats.route reports R1. */
 

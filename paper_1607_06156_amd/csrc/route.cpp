@@ -288,7 +288,7 @@ int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32
 // level costs a launch and a host round trip, so a long path would cost one per
 // hop.  A BFS still running after this many levels is abandoned before any
 // label is written, and SV labels the whole graph instead.
-constexpr int kMaxBfsLevels = 1024;
+constexpr int kMaxBfsLevels = 256;
 
 // R0: CSR (if not built yet), BFS, label, filter, then SV on the rest
 int run_bfs_route(Call& c, DegreeResult& r) {

@@ -100,7 +100,7 @@ def test_ordered_paths_batched():
 @pytest.mark.parametrize("permute", [False, True])
 def test_forced_bfs_on_a_long_path(permute):
     """The BFS step is for short-diameter components: on a 3M-vertex path it
-    stops after 1024 levels, before writing any label, and SV labels the
+    stops after 256 levels, before writing any label, and SV labels the
     whole graph (route reported R1)."""
     n = 3_000_000
     order = gen.permutation(n, seed=12) if permute else np.arange(n, dtype=np.int32)
@@ -108,5 +108,5 @@ def test_forced_bfs_on_a_long_path(permute):
     say(f"[gpu] forced bfs+sv on a {'permuted' if permute else 'ordered'} path n={n}")
     lab, st = _label(u, v, n, "bfs+sv")
     assert torch.all(lab == 0)
-    assert st["route"] == ccmi.R1_SV and st["bfs_levels"] == 1024
+    assert st["route"] == ccmi.R1_SV and st["bfs_levels"] == 256
     say(f"   bfs_visited={st['bfs_visited']} ms={st['ms_total']:.1f}")
