@@ -133,6 +133,9 @@ struct DegreeResult {
     int64_t max_degree = 0;
     int32_t argmax = -1;
     bool csr_built = false;
+    bool prefetch_tail = false;        // set by the caller: read the tail back with the histograms
+    const int32_t* tail_host = nullptr;   // the first tail_host_n tail entries, in pinned host memory
+    int64_t tail_host_n = 0;
     int64_t* off = nullptr;
     int32_t* adj = nullptr;
 };

@@ -43,6 +43,13 @@ static void set_cursor_bufs(BucketBufs* w, void* po, int64_t m, bool csr) {
                           : nullptr;
 }
 
+// Pinned staging of the degree pass's readback: the histograms and counters
+// at the start, the tail prefetch (up to kTailPrefetch entries) at this offset.
+constexpr size_t kTailPrefetchOff = 64 * 1024;
+constexpr int64_t kTailPrefetch = 16 * 1024;
+static_assert((64 + kExactBins + 3) * sizeof(unsigned long long) <= kTailPrefetchOff, "staging overlap");
+static_assert(kTailPrefetchOff + kTailPrefetch * sizeof(int32_t) <= Workspace::kHostBytes, "staging size");
+
 int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     Workspace& ws = *c.ws;
     BucketPlan p;
@@ -127,6 +134,16 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     if (e == hipSuccess)
         e = hipMemcpyAsync(host + 64 + kExactBins + 2, w.err, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            c.stream);
+    // the route decision needs the tail too: its first entries come back in
+    // the same round trip (the tail count is not known before it)
+    r->tail_host = nullptr;
+    r->tail_host_n = 0;
+    if (e == hipSuccess && r->prefetch_tail) {
+        r->tail_host_n = std::min<int64_t>(tail_cap, kTailPrefetch);
+        r->tail_host = (const int32_t*)((char*)host + kTailPrefetchOff);
+        e = hipMemcpyAsync((void*)r->tail_host, r->tail, (size_t)r->tail_host_n * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c.stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(hist)");
     e = hipStreamSynchronize(c.stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -149,7 +166,11 @@ int decide_heuristic(Call& c, DegreeResult& r, int* route) {
     std::vector<int32_t> pageable;
     const int32_t* tail = nullptr;
     int64_t ntail = 0;
-    if (r.ntail > 0) {
+    if (r.ntail > 0 && std::min(r.ntail, r.tail_cap) <= r.tail_host_n) {
+        // read back with the histograms already
+        ntail = std::min(r.ntail, r.tail_cap);
+        tail = r.tail_host;
+    } else if (r.ntail > 0) {
         ntail = std::min(r.ntail, r.tail_cap);
         int32_t* dst;
         if ((size_t)ntail * sizeof(int32_t) <= Workspace::kHostBytes) {
@@ -468,6 +489,7 @@ int run_label(Call& c) {
         if ((rc = run_degree_pass(c, true, &dr))) return rc;
         route = CC_R0_BFS_SV;
     } else {
+        dr.prefetch_tail = req == CC_ROUTE_HEURISTIC;
         if ((rc = run_degree_pass(c, false, &dr))) return rc;
         if (req == CC_ROUTE_HEURISTIC) rc = decide_heuristic(c, dr, &route);
         else rc = decide_router(c, dr, &route);
