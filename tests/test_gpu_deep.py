@@ -110,3 +110,21 @@ def test_forced_bfs_on_a_long_path(permute):
     assert torch.all(lab == 0)
     assert st["route"] == ccmi.R1_SV and st["bfs_levels"] == 256
     say(f"   bfs_visited={st['bfs_visited']} ms={st['ms_total']:.1f}")
+
+
+def test_router_on_an_ordered_path():
+    """With the shipped router weights, route "router" on a 3M-vertex ordered
+    path: whichever route the MLP picks (a BFS is abandoned after 256 levels),
+    the labels are exact."""
+    import os
+    weights = os.path.join(os.path.dirname(ccmi.__file__), "router_weights.txt")
+    n = 3_000_000
+    u = np.arange(n - 1, dtype=np.int32)
+    ccmi.router_load(weights)
+    try:
+        say("[gpu] router on an ordered path")
+        lab, st = _label(u, u + 1, n, "router")
+    finally:
+        ccmi.router_set(None)
+    assert torch.all(lab == 0)
+    say(f"   route={st['route_name']} bfs_levels={st['bfs_levels']} deep_rounds={st['sv_deep_rounds']}")
