@@ -78,6 +78,10 @@ def main():
                     help="weights loaded for --route router / auto")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (batch4096 vs per-graph launches) and router-vs-heuristic legs")
+    ap.add_argument("--router-graphs", type=int, default=200,
+                    help="held-out graphs of the router-vs-heuristic leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -98,7 +102,8 @@ def main():
         del src, dst
 
     if args.config.startswith("batch"):
-        return bench_batched(args)
+        print(json.dumps(bench_batched(args, args.config, args.steps, args.warmup)), flush=True)
+        return
     if args.route in ("router", "auto"):
         ccmi.router_load(args.router_weights)
 
@@ -178,12 +183,65 @@ def main():
                                       "ms_csr", "ms_bfs", "ms_filter", "ms_sv", "ms_total"]},
         "forced_routes": extra,
     }
+    if not args.no_extras:
+        # the other targets, outside the timed region: batched mode against
+        # per-graph launches on the 4096-graph batch (every graph checked
+        # against the oracle), and the router against the degree heuristic
+        del u, v, labels
+        torch.cuda.empty_cache()
+        b = bench_batched(args, "batch4096", 3, 1)
+        rec["batched_batch4096"] = {k: b[k] for k in ("ms_per_step", "value", "labels_exact_vs_oracle",
+                                                       "per_graph_loop", "passes", "max_link")}
+        rec["batched_batch4096"]["blocks"] = b["config"]["blocks"]
+        rec["router_vs_heuristic"] = router_leg(args)
     print(json.dumps(rec), flush=True)
 
 
-def bench_batched(args):
+def oracle_batch(b, workers):
+    """Oracle labels of every graph of a batch, concatenated, on a thread pool
+    (the oracle's C union-find releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    out = np.empty(int(b.vert_off[-1]), dtype=np.int32)
+
+    def one(g):
+        sub = b.graph(g)
+        a = int(b.vert_off[g])
+        out[a:a + sub.n] = oracle.labels_uf(sub.u, sub.v, sub.n)
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(one, range(b.G)))
+    return out
+
+
+def router_leg(args):
+    """Router against the K-S heuristic, end to end, over the first held-out
+    graphs of the router's evaluation set (new seeds of the training families
+    plus the power-law forest family, never seen in training)."""
+    import paper_1607_06156_amd as ccmi
+    from paper_1607_06156_amd import router_train as rt
+    t = time.time()
+    w = rt.load(args.router_weights)
+    rep, _ = rt.evaluate(w, args.router_graphs, 20_000_000, 10.0, 20.0)
+    ccmi.router_set(None)
+    log(f"[bench] router vs heuristic over {rep['graphs']} held-out graphs: router {rep['router_s'] * 1e3:.1f} ms, "
+        f"heuristic {rep['heuristic_s'] * 1e3:.1f} ms, best forced {rep['best_forced_s'] * 1e3:.1f} ms "
+        f"({time.time() - t:.0f} s)")
+    return {"graphs": rep["graphs"], "router_ms": round(rep["router_s"] * 1e3, 3),
+            "heuristic_ms": round(rep["heuristic_s"] * 1e3, 3), "best_forced_ms": round(rep["best_forced_s"] * 1e3, 3),
+            "router_no_slower": rep["router_no_slower"],
+            "by_family_ms": {f: {"router": round(d["router_s"] * 1e3, 3), "heuristic": round(d["heuristic_s"] * 1e3, 3)}
+                             for f, d in rep["by_family"].items()},
+            "weights": os.path.relpath(args.router_weights, ROOT)}
+
+
+def bench_batched(args, config, steps, warmup):
     """Batched mode: all graphs in one persistent launch, against a loop of
-    per-graph cc_label calls (plain SV) over the same device arrays."""
+    per-graph cc_label calls (plain SV) over the same device arrays; every
+    graph's labels checked against the oracle.  Returns the JSON record."""
     import numpy as np
     import torch
 
@@ -191,25 +249,25 @@ def bench_batched(args):
     import paper_1607_06156_amd as ccmi
 
     t = time.time()
-    b = gen.workload(args.config)
+    b = gen.workload(config)
     m = int(b.edge_off[-1])
     n = int(b.vert_off[-1])
-    log(f"[bench] generated {args.config}: G={b.G} n={n} m={m} in {time.time() - t:.1f}s")
+    log(f"[bench] generated {config}: G={b.G} n={n} m={m} in {time.time() - t:.1f}s")
     u = torch.from_numpy(b.u).cuda()
     v = torch.from_numpy(b.v).cuda()
     eo = torch.from_numpy(b.edge_off).cuda()
     vo = torch.from_numpy(b.vert_off).cuda()
     out = torch.empty(n, dtype=torch.int32, device="cuda")
-    for _ in range(max(args.warmup, 1)):   # the first call also autotunes the grid
+    for _ in range(max(warmup, 1)):   # the first call also autotunes the grid
         ccmi.label_batched(u, v, eo, vo, out=out)
     torch.cuda.synchronize()
     sts = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         _, st = ccmi.label_batched(u, v, eo, vo, out=out, stats=True)
         sts.append(st)
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
+    sec = (time.perf_counter() - t0) / steps
     value = m / sec
     st = sts[-1]
     log(f"[bench] batched: {sec * 1e3:.2f} ms/step {value / 1e9:.2f} G edges/s passes={st['passes']} "
@@ -220,7 +278,7 @@ def bench_batched(args):
     kbytes = 32.0 * m + 16.0 * n
     achieved = kbytes / (kernel_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": "batched_kernel", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("batched", args.config),
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("batched", config),
                 "avg_launch_ms": round(kernel_ms, 4), "bytes_per_launch": kbytes}
     # per-graph launches of the same SV kernels
     loop = None
@@ -246,34 +304,32 @@ def bench_batched(args):
                 "labels_identical": same}
         log(f"[bench] per-graph loop: {lsec * 1e3:.1f} ms  ({m / lsec / 1e9:.2f} G edges/s); batched is "
             f"{lsec / sec:.1f}x; identical={same}")
+        del out2
+    lab_h = out.cpu().numpy()
+    del u, v, eo, vo, out
+    torch.cuda.empty_cache()
+    # every graph against the oracle, on a pool of the host's threads (the
+    # cpu baseline: the oracle over the whole batch)
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    expect = oracle_batch(b, workers)
+    dt = time.perf_counter() - t0
+    exact = bool(np.array_equal(lab_h, expect))
+    log(f"[bench] oracle over all {b.G} graphs on {workers} threads: {dt:.2f} s; labels exact: {exact}")
     cpu = None
-    exact = None
     if not args.no_cpu:
-        import oracle
-        # bounded sample: graphs 0, 16, 32, ... (one in 16) on one thread
-        gs = list(range(0, b.G, 16))
-        lab_h = out.cpu().numpy()
-        t0 = time.perf_counter()
-        me = 0
-        exact = True
-        for g in gs:
-            sub = b.graph(g)
-            lab = oracle.labels_uf(sub.u, sub.v, sub.n)
-            me += sub.m
-            exact &= bool(np.array_equal(lab, lab_h[int(b.vert_off[g]):int(b.vert_off[g + 1])]))
-        dt = time.perf_counter() - t0
-        cpu = {"value": me / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(gs)} of {b.G} graphs (every 16th), {me} edges, one thread, {dt:.2f} s",
-               "host_nproc": os.cpu_count()}
-    rec = {
+        cpu = {"value": m / dt, "unit": "edges/s", "cores": workers, "kind": "oracle",
+               "sample": f"all {b.G} graphs ({m} edges), union-find per graph on a pool of {workers} threads, "
+                         f"{dt:.2f} s", "host_nproc": os.cpu_count()}
+    return {
         "metric": METRIC,
-        "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": value, "unit": "edges/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"{args.config}: {b.G} graphs, log2 n ~ U[8,20], families G(n,m) / R-MAT / thinned "
+        "config": {"workload": f"{config}: {b.G} graphs, log2 n ~ U[8,20], families G(n,m) / R-MAT / thinned "
                                f"lattice / power-law components, seeds 5e6+g", "n": n, "m": m,
                    "blocks": st["blocks"], "tile_edges": st["tile_edges"]},
-        "labels_exact_vs_oracle_sampled": exact,
+        "labels_exact_vs_oracle": exact,
         "kernel_ms": round(kernel_ms, 3),
         "roofline": roofline,
         "passes": st["passes"],
@@ -282,7 +338,6 @@ def bench_batched(args):
         "per_graph_loop": loop,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -26,10 +26,19 @@
  *    work is enqueued on it.  Calls return after their results are complete
  *    (they read small device counters to drive their loops), i.e. they are
  *    host-synchronous with respect to `stream`.
- *  - Scratch memory is taken from a per-device workspace that the library
- *    grows on demand with hipMalloc and keeps until cc_release_workspace() or
- *    process exit.  Calls that overlap on one device from several host threads
- *    are serialised by an internal lock.
+ *  - Scratch memory of cc_label / cc_label_ex (cc_options.scratch,
+ *    cc_options.workspace): by default it is allocated stream-ordered on
+ *    `stream` from a memory pool that the library keeps per device, and
+ *    freed stream-ordered before the call returns; calls on different streams
+ *    or threads then run at once.  A caller may instead pass a device block of
+ *    at least cc_workspace_size() bytes (nothing is allocated on the device
+ *    for scratch), or ask for the library's cached per-device workspace (grown
+ *    with hipMalloc, kept until cc_release_workspace(); calls that use it
+ *    serialise on a per-device lock).  The batched calls and the step entry
+ *    points use the cached workspace.  Small readbacks use pinned host
+ *    buffers that the library keeps (one per call in flight).
+ *    cc_release_workspace() trims the current device's pool and frees its
+ *    cached workspace; cc_shutdown() frees everything the library holds.
  *  - Return value: CC_OK (0) or a negative CC_E* code; cc_last_error() then
  *    returns a message (thread-local).  Nothing is thrown across the ABI.
  */
@@ -42,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CC_VERSION 10000 /* 1.0.0 */
+#define CC_VERSION 10100 /* 1.1.0 */
 
 /* ------------------------------------------------------------ status codes */
 #define CC_OK 0
@@ -72,6 +81,10 @@ extern "C" {
 #define CC_R1_SV 1
 #define CC_R2_SV_THETA 2
 
+/* scratch modes (cc_options.scratch), used when no workspace is given */
+#define CC_SCRATCH_POOL 0   /* stream-ordered allocations on `stream` from the library's per-device pool */
+#define CC_SCRATCH_CACHED 1 /* the library's per-device workspace, kept between calls; calls serialise on it */
+
 typedef struct cc_options {
     int32_t route;       /* CC_ROUTE_* */
     int32_t max_passes;  /* 0: no cap; else CC_EINTERNAL once this many SV passes ran without converging */
@@ -79,7 +92,11 @@ typedef struct cc_options {
     double theta;        /* R2: hook attempts per edge per pass (an edge whose hook finds the root already
                             linked follows the link and retries); < 1 selects 8 */
     int32_t profile;     /* 1: time every kernel launch with HIP events (cc_stats.kernel_*) */
-    int32_t reserved[7]; /* must be zero */
+    int32_t scratch;     /* CC_SCRATCH_*; ignored when workspace is set */
+    void* workspace;     /* device memory owned by the caller, used as the call's only device scratch;
+                            NULL: see scratch.  Must not be used by anything else during the call. */
+    int64_t workspace_bytes; /* its size: at least cc_workspace_size(m, n, route), else CC_EINVAL */
+    int32_t reserved[4]; /* must be zero */
 } cc_options;
 
 /* kernel classes for cc_stats.kernel_* */
@@ -269,8 +286,23 @@ int cc_mlp_forward(const float* params, const float* x, int32_t batch, float* lo
 int cc_mlp_sgd_step(float* params, const float* x, const int32_t* y, int32_t batch, float lr, float* grads,
                     float* loss, void* stream);
 
-/* Free the calling device's workspace. */
+/* Bytes of device scratch a cc_label_ex call on m edges and n vertices may
+ * use with this route (CC_ROUTE_*): the size to give cc_options.workspace.
+ * The forced SV routes need about 20 bytes per edge; the routes that may
+ * take the degree pass and the BFS step about 60 bytes per edge and 40 per
+ * vertex.  Negative (CC_EINVAL) for a negative size or a bad route. */
+int64_t cc_workspace_size(int64_t m, int32_t n, int32_t route);
+
+/* Trim the current device's scratch pool and free its cached workspace
+ * (waits for the device first). */
 int cc_release_workspace(void);
+
+/* Free everything the library holds on every device it used: cached
+ * workspaces, scratch pools, pinned staging buffers and the router weights'
+ * device copies (the loaded weights stay loaded and are copied again on next
+ * use).  Waits for those devices first.  No call may be running; later calls
+ * work as on first use. */
+int cc_shutdown(void);
 
 #ifdef __cplusplus
 }

@@ -8,6 +8,7 @@ fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import math
 import os
@@ -38,9 +39,15 @@ class CCError(RuntimeError):
         self.code = code
 
 
+SCRATCH_POOL, SCRATCH_CACHED = 0, 1
+_SCRATCH_ARG = {None: SCRATCH_POOL, "pool": SCRATCH_POOL, "cached": SCRATCH_CACHED}
+
+
 class Options(ctypes.Structure):
     _fields_ = [("route", ctypes.c_int32), ("max_passes", ctypes.c_int32), ("tau", ctypes.c_double),
-                ("theta", ctypes.c_double), ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("theta", ctypes.c_double), ("profile", ctypes.c_int32), ("scratch", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -117,6 +124,8 @@ def lib():
             "cc_mlp_sgd_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_float, _VP,
                                                ctypes.POINTER(ctypes.c_float), _VP]),
             "cc_release_workspace": (ctypes.c_int, []),
+            "cc_workspace_size": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
+            "cc_shutdown": (ctypes.c_int, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name, None)
@@ -125,7 +134,15 @@ def lib():
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        # release the library's device and pinned memory while the HIP
+        # runtime is still up (Python's exit handlers run before the C ones)
+        atexit.register(_shutdown_at_exit)
     return _lib
+
+
+def _shutdown_at_exit():
+    if _lib is not None:
+        _lib.cc_shutdown()
 
 
 def _check(rc: int):
@@ -155,8 +172,12 @@ def version() -> int:
 
 def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tensor | None = None,
           stats: bool = False, max_passes: int = 0, tau: float = 0.05, theta: float = 8.0,
-          profile: bool = False):
-    """labels[x] = min vertex id of x's component; (u[i], v[i]) are undirected edges."""
+          profile: bool = False, workspace: torch.Tensor | None = None, scratch=None):
+    """labels[x] = min vertex id of x's component; (u[i], v[i]) are undirected edges.
+
+    workspace: a uint8 device tensor of at least workspace_size(m, n, route)
+    bytes used as the call's only device scratch; scratch: "pool" (default,
+    stream-ordered allocations) or "cached" (the library's kept workspace)."""
     m = int(u.numel())
     if int(v.numel()) != m:
         raise ValueError("u and v differ in length")
@@ -169,6 +190,10 @@ def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tenso
     opt.tau = tau
     opt.theta = theta
     opt.profile = 1 if profile else 0
+    opt.scratch = _SCRATCH_ARG[scratch]
+    if workspace is not None:
+        opt.workspace = _dev(workspace, torch.uint8, "workspace")
+        opt.workspace_bytes = int(workspace.numel())
     st = Stats()
     rc = lib().cc_label_ex(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n,
                            _dev(out, torch.int32, "labels"), _stream(), ctypes.byref(opt),
@@ -304,5 +329,18 @@ def router_loaded() -> bool:
     return bool(lib().cc_router_loaded())
 
 
+def workspace_size(m: int, n: int, route=None) -> int:
+    """Bytes of device scratch a label() call on m edges and n vertices may use."""
+    r = lib().cc_workspace_size(int(m), int(n), _ROUTE_ARG[route] if not isinstance(route, int) else route)
+    if r < 0:
+        _check(int(r))
+    return int(r)
+
+
 def release_workspace():
     _check(lib().cc_release_workspace())
+
+
+def shutdown():
+    """Free everything the library holds (no call may be running)."""
+    _check(lib().cc_shutdown())

@@ -40,7 +40,40 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 // --------------------------------------------------------------- workspace
-Workspace::~Workspace() { release(); }
+// Shared pool of pinned staging buffers for the calls that do not use the
+// device's cached workspace: a call leases one and returns it at its end, so
+// calls running at once on different streams never share a buffer.
+static std::mutex g_stage_mu;
+static std::vector<void*> g_stage_free;   // idle buffers
+static std::vector<void*> g_stage_all;    // every buffer made (freed by cc_shutdown)
+
+static int lease_stage(void** out) {
+    {
+        std::lock_guard<std::mutex> g(g_stage_mu);
+        if (!g_stage_free.empty()) {
+            *out = g_stage_free.back();
+            g_stage_free.pop_back();
+            return CC_OK;
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipHostMalloc(&p, Workspace::kHostBytes, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+    std::lock_guard<std::mutex> g(g_stage_mu);
+    g_stage_all.push_back(p);
+    *out = p;
+    return CC_OK;
+}
+
+static void return_stage(void* p) {
+    std::lock_guard<std::mutex> g(g_stage_mu);
+    g_stage_free.push_back(p);
+}
+
+Workspace::~Workspace() {
+    if (mode == kCached) release();
+    else finish();
+}
 
 void Workspace::release() {
     for (auto& b : bufs) {
@@ -48,39 +81,93 @@ void Workspace::release() {
         b.ptr = nullptr;
         b.bytes = 0;
     }
-    if (host) (void)hipHostFree(host);
+    if (host && !host_external && !host_leased) (void)hipHostFree(host);
     host = nullptr;
 }
+
+void Workspace::finish() {
+    if (mode == kPool) {
+        for (auto& b : bufs) {
+            if (b.ptr) (void)hipFreeAsync(b.ptr, stream);
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+    }
+    if (host_leased && host) return_stage(host);
+    if (host_leased) host = nullptr;
+    host_leased = false;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int Workspace::get(int slot, size_t bytes, void** out) {
     if (bytes == 0) bytes = 256;
     Buf& b = bufs[slot];
-    if (b.bytes < bytes) {
+    if (b.bytes >= bytes) {
+        *out = b.ptr;
+        return CC_OK;
+    }
+    if (mode == kArena) {
+        // first use: the slot's whole bound; a request beyond it (none is
+        // expected) gets a fresh region if the block still has room
+        const size_t want = align256(std::max(bytes, b.ptr ? bytes : bound[slot]));
+        const size_t base = align256((size_t)(uintptr_t)arena) - (size_t)(uintptr_t)arena;
+        if (base + arena_used + want > arena_bytes)
+            return fail(CC_ENOMEM, "workspace of %zu bytes is too small for this call (slot %d needs %zu more)",
+                        arena_bytes, slot, want);
+        b.ptr = arena + base + arena_used;
+        b.bytes = want;
+        arena_used += want;
+        *out = b.ptr;
+        return CC_OK;
+    }
+    if (mode == kPool) {
         if (b.ptr) {
-            hipError_t e = hipFree(b.ptr);
-            if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+            hipError_t e = hipFreeAsync(b.ptr, stream);
             b.ptr = nullptr;
             b.bytes = 0;
+            if (e != hipSuccess) return hip_fail(e, "hipFreeAsync(workspace)");
         }
-        size_t want = bytes + bytes / 8;  // headroom against repeated growth
-        hipError_t e = hipMalloc(&b.ptr, want);
+        hipError_t e = hipMallocFromPoolAsync(&b.ptr, bytes, pool, stream);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             b.ptr = nullptr;
-            return hip_fail(e, "hipMalloc(workspace)");
+            return hip_fail(e, "hipMallocFromPoolAsync(workspace)");
         }
-        b.bytes = want;
+        b.bytes = bytes;
+        *out = b.ptr;
+        return CC_OK;
     }
+    if (b.ptr) {
+        hipError_t e = hipFree(b.ptr);
+        if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;  // headroom against repeated growth
+    hipError_t e = hipMalloc(&b.ptr, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.ptr = nullptr;
+        return hip_fail(e, "hipMalloc(workspace)");
+    }
+    b.bytes = want;
     *out = b.ptr;
     return CC_OK;
 }
 
 int Workspace::pinned(void** out) {
     if (!host) {
-        hipError_t e = hipHostMalloc(&host, kHostBytes, hipHostMallocDefault);
-        if (e != hipSuccess) {
-            host = nullptr;
-            return hip_fail(e, "hipHostMalloc");
+        if (mode == kCached) {
+            hipError_t e = hipHostMalloc(&host, kHostBytes, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                host = nullptr;
+                return hip_fail(e, "hipHostMalloc");
+            }
+        } else {
+            int rc = lease_stage(&host);
+            if (rc) return rc;
+            host_leased = true;
         }
     }
     *out = host;
@@ -89,6 +176,7 @@ int Workspace::pinned(void** out) {
 
 static std::mutex g_ws_mu;
 static std::unordered_map<int, Workspace*> g_ws;
+static std::unordered_map<int, hipMemPool_t> g_pools;
 
 int acquire_workspace(Workspace** out) {
     int dev = 0;
@@ -100,6 +188,86 @@ int acquire_workspace(Workspace** out) {
     it->second->device = dev;
     *out = it->second;
     return CC_OK;
+}
+
+// The library's memory pool on the current device: stream-ordered
+// allocations that it keeps after they are freed (release threshold at its
+// maximum), so a call of the same size as an earlier one maps no new memory.
+// cc_release_workspace trims it.
+int pool_workspace(Workspace* ws, hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    auto it = g_pools.find(dev);
+    if (it == g_pools.end()) {
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof props);
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        e = hipMemPoolCreate(&pool, &props);
+        if (e != hipSuccess) return hip_fail(e, "hipMemPoolCreate");
+        uint64_t keep = UINT64_MAX;
+        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        if (e != hipSuccess) {
+            (void)hipMemPoolDestroy(pool);
+            return hip_fail(e, "hipMemPoolSetAttribute");
+        }
+        it = g_pools.emplace(dev, pool).first;
+    }
+    ws->mode = Workspace::kPool;
+    ws->device = dev;
+    ws->stream = s;
+    ws->pool = it->second;
+    return CC_OK;
+}
+
+size_t workspace_bound(int64_t m, int32_t n, bool sv_only, size_t* per_slot) {
+    size_t b[WS_NSLOTS] = {};
+    const size_t M = (size_t)std::max<int64_t>(m, 0), N = (size_t)std::max<int32_t>(n, 0);
+    // SV: at most 8 chunks of 2048 segments, each segment ceil(m / nseg)
+    // slots, so the slots number fewer than m + 16384; the BFS route's rest
+    // (from the CSR rows or the filtered list) holds at most m edges
+    const size_t slots = M + 8 * 2048;
+    b[WS_EDGES0] = slots * 8;
+    b[WS_EDGES1] = slots * 8;
+    b[WS_HOOKED] = slots * 4;
+    b[WS_SEGCOUNT] = (size_t)8 * 2048 * 4 * sizeof(uint32_t);
+    b[WS_TOTALS] = 64 * sizeof(unsigned long long);
+    if (!sv_only) {
+        BucketPlan p;
+        if (bucket_plan(n, m, &p) == 0 && m < ((int64_t)1 << 31)) {
+            const size_t counts = align256((size_t)p.nblk * p.B * sizeof(uint32_t));
+            b[WS_HIST] = counts + (size_t)(2 * p.B + 2) * sizeof(unsigned long long) +
+                         (size_t)p.B * kGroups * sizeof(uint32_t);
+            b[WS_CURSOR] = 16 * M;   // two-level scatter with the other ends, CSR regroup, the rest's arrays
+            b[WS_QUEUE] = align256(2 * M * sizeof(uint16_t)) + 2 * M * sizeof(int32_t);
+            b[WS_DEG] = 4 * N;
+            const size_t tail = std::min(N, 2 * M / kExactBins + 1);
+            b[WS_TAIL] = 4 * tail;
+            b[WS_HISTOUT] = (64 + kExactBins + 4) * sizeof(unsigned long long);
+            b[WS_OFF] = 8 * (N + 1);
+            b[WS_ADJ] = 8 * M;
+            b[WS_BITS] = 12 * ((N + 31) / 32);
+            b[WS_MLP] = 512;
+            // fit: per distinct degree 3 doubles in, and per candidate an
+            // index and 2 doubles out
+            const size_t V = kExactBins + tail;
+            b[WS_KS] = 44 * V + 64;
+            // BFS queues and prefix sums share the SV slots
+            b[WS_HOOKED] = std::max(b[WS_HOOKED], 8 * N);
+            b[WS_SEGCOUNT] = std::max(b[WS_SEGCOUNT], 8 * (N + N / 1024 + 8));
+        }
+    }
+    size_t total = 256;
+    for (int i = 0; i < WS_NSLOTS; ++i) {
+        if (per_slot) per_slot[i] = b[i];
+        if (b[i]) total += align256(b[i]);
+    }
+    return total;
 }
 
 // ------------------------------------------------------------------ timing
@@ -401,13 +569,36 @@ CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
     if (opt.route < CC_ROUTE_AUTO || opt.route > CC_ROUTE_SV_THETA) return fail(CC_EINVAL, "bad route %d", opt.route);
     if (opt.max_passes < 0) return fail(CC_EINVAL, "negative max_passes");
     if (m > (int64_t)2048 * (int64_t)INT32_MAX) return fail(CC_EINVAL, "too many edges");
+    if (opt.workspace && opt.workspace_bytes <= 0) return fail(CC_EINVAL, "workspace given with no size");
+    if (opt.scratch != CC_SCRATCH_POOL && opt.scratch != CC_SCRATCH_CACHED)
+        return fail(CC_EINVAL, "bad scratch mode %d", opt.scratch);
     if (stats) stats_reset(stats);
     if (n == 0) return CC_OK;
 
-    Workspace* ws;
-    int rc = acquire_workspace(&ws);
-    if (rc) return rc;
-    std::lock_guard<std::mutex> guard(ws->mu);
+    // scratch: the caller's block, the library's cached per-device buffers
+    // (serialised by their lock), or stream-ordered allocations from the
+    // library's pool (the default)
+    Workspace local;
+    Workspace* ws = &local;
+    std::unique_lock<std::mutex> lk;
+    int rc;
+    if (opt.workspace) {
+        const bool sv_only = opt.route == CC_ROUTE_SV || opt.route == CC_ROUTE_SV_THETA;
+        const size_t need = workspace_bound(m, n, sv_only, local.bound);
+        if ((size_t)opt.workspace_bytes < need)
+            return fail(CC_EINVAL, "workspace of %lld bytes is smaller than the %zu this call may need",
+                        (long long)opt.workspace_bytes, need);
+        hipError_t e = hipGetDevice(&local.device);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        local.mode = Workspace::kArena;
+        local.arena = (char*)opt.workspace;
+        local.arena_bytes = (size_t)opt.workspace_bytes;
+    } else if (opt.scratch == CC_SCRATCH_CACHED) {
+        if ((rc = acquire_workspace(&ws))) return rc;
+        lk = std::unique_lock<std::mutex>(ws->mu);
+    } else {
+        if ((rc = pool_workspace(&local, (hipStream_t)stream))) return rc;
+    }
 
     Call c;
     c.ws = ws;
@@ -444,6 +635,12 @@ CC_API int cc_label(const int32_t* u, const int32_t* v, int64_t m, int32_t n, in
     return cc_label_ex(u, v, m, n, labels, stream, nullptr, nullptr);
 }
 
+CC_API int64_t cc_workspace_size(int64_t m, int32_t n, int32_t route) {
+    if (m < 0 || n < 0) return fail(CC_EINVAL, "negative size (m=%lld, n=%d)", (long long)m, n);
+    if (route < CC_ROUTE_AUTO || route > CC_ROUTE_SV_THETA) return fail(CC_EINVAL, "bad route %d", route);
+    return (int64_t)workspace_bound(m, n, route == CC_ROUTE_SV || route == CC_ROUTE_SV_THETA, nullptr);
+}
+
 CC_API int cc_release_workspace(void) {
     Workspace* ws;
     int rc = acquire_workspace(&ws);
@@ -452,5 +649,42 @@ CC_API int cc_release_workspace(void) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
     ws->release();
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    auto it = g_pools.find(ws->device);
+    if (it != g_pools.end() && (e = hipMemPoolTrimTo(it->second, 0)) != hipSuccess)
+        return hip_fail(e, "hipMemPoolTrimTo");
     return CC_OK;
+}
+
+// Everything the library holds, on every device it used: cached workspaces,
+// memory pools, pinned staging, router copies.  No call may be running.
+CC_API int cc_shutdown(void) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int rc = CC_OK;
+    {
+        std::lock_guard<std::mutex> g(g_ws_mu);
+        for (auto& kv : g_ws) {
+            if (hipSetDevice(kv.first) != hipSuccess) continue;
+            std::lock_guard<std::mutex> wl(kv.second->mu);
+            if ((e = hipDeviceSynchronize()) != hipSuccess && rc == CC_OK) rc = hip_fail(e, "hipDeviceSynchronize");
+            kv.second->release();
+        }
+        for (auto& kv : g_pools) {
+            if (hipSetDevice(kv.first) != hipSuccess) continue;
+            if ((e = hipDeviceSynchronize()) != hipSuccess && rc == CC_OK) rc = hip_fail(e, "hipDeviceSynchronize");
+            if ((e = hipMemPoolDestroy(kv.second)) != hipSuccess && rc == CC_OK) rc = hip_fail(e, "hipMemPoolDestroy");
+        }
+        g_pools.clear();
+    }
+    {
+        std::lock_guard<std::mutex> g(g_stage_mu);
+        for (void* p : g_stage_all) (void)hipHostFree(p);
+        g_stage_all.clear();
+        g_stage_free.clear();
+    }
+    router_release_all();
+    (void)hipSetDevice(cur);
+    return rc;
 }

@@ -42,6 +42,7 @@ struct BatchArgs {
     unsigned long long* status;  // [0] error bits, [1] passes, [2] range errors, [4] labels left unshifted
     int32_t max_passes;
     int32_t max_link;     // hook attempts per edge per pass (see sv_segment)
+    uint64_t barrier_ticks;     // spin limit of a grid barrier, in 100 MHz wall-clock ticks
     unsigned long long* part;   // per-block partials: survivors, hooks, finds stopped at the hop
                                 // bound (2 x gridDim each)
 };
@@ -65,9 +66,9 @@ __device__ __forceinline__ unsigned long long load_status(unsigned long long* p)
 }
 
 // Sense-reversing grid barrier for a co-resident (cooperative) grid.  The spin
-// is bounded: after ~5 s it flags an error, and a flagged error releases
-// every later barrier at once, so all workgroups always exit.
-__device__ void grid_barrier(unsigned int* bar, unsigned long long* status) {
+// is bounded (by default ~5 s): past the limit it flags an error, and a flagged
+// error releases every later barrier at once, so all workgroups always exit.
+__device__ void grid_barrier(unsigned int* bar, unsigned long long* status, uint64_t limit) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();   // release this block's writes (agent scope)
@@ -80,7 +81,7 @@ __device__ void grid_barrier(unsigned int* bar, unsigned long long* status) {
             const uint64_t t0 = wall_clock64();
             while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 if (load_status(status) & kErrBarrier) break;
-                if (wall_clock64() - t0 > 500000000ull) {   // 5 s at the 100 MHz wall clock
+                if (wall_clock64() - t0 > limit) {
                     __hip_atomic_fetch_or(&status[0], (unsigned long long)kErrBarrier, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
                     break;
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
             __hip_atomic_fetch_or(&A.status[0], (unsigned long long)kErrOffsets, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
     }
-    grid_barrier(A.bar, A.status);
+    grid_barrier(A.bar, A.status, A.barrier_ticks);
     if (load_status(A.status)) return;
     stamp(A.status, 0);
 
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
     uint32_t* cin = A.cnt0;
     uint32_t* cout = A.cnt1;
     for (;;) {
-        grid_barrier(A.bar, A.status);
+        grid_barrier(A.bar, A.status, A.barrier_ticks);
         if (load_status(A.status)) return;
         stamp(A.status, pass);
         // every block sums the same partials and takes the same decisions
@@ -253,12 +254,19 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
         // they far outnumber the surviving edges (typically after the first
         // pass, when nearly every vertex was hooked): then the next pass's
         // finds walk the extra links of the few survivors instead, and the
-        // final compression flattens everything once.  If some find of the
-        // pass stopped at the hop bound, every vertex of this block's tiles is
-        // moved up instead (at most kMaxHops links), so deep chains shrink by
-        // that factor per pass.  Either way only vertices that were no longer
-        // roots at the barrier are written, and a hook of the next pass only
-        // ever lands on a root, so the next pass may start beside these stores.
+        // final compression flattens everything once.  The jumped roots were
+        // hooked before the barrier, so they are no longer roots, and a hook
+        // of the next pass only ever lands on a root: the next pass may start
+        // beside these plain stores.
+        //
+        // If some find of the pass stopped at the hop bound, every vertex of
+        // this block's tiles is moved up instead (at most kMaxHops links), so
+        // deep chains shrink by that factor per pass.  That sweep cannot tell
+        // a vertex linked before the barrier from a root that another
+        // workgroup's next pass has just hooked; a plain store to such a
+        // vertex could erase a second hook's atomicMin and lose a connection.
+        // So the sweep ends at a grid barrier of its own before any hook of
+        // the next pass.
         if (deep > 0) {
             const TileWalk vw(TV, b, nb);
             for (int64_t t = vw.first; t < vw.end; t += vw.step) {
@@ -268,6 +276,8 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
                     if (p != (int32_t)x) A.parent[x] = find_bounded(A.parent, p, &root);
                 }
             }
+            grid_barrier(A.bar, A.status, A.barrier_ticks);
+            if (load_status(A.status)) return;
         } else if (hooks <= kLazyJump * total) {
             for (int64_t t = tw.first; t < tw.end; t += tw.step) {
                 const uint32_t hc = A.hcnt[t];
@@ -348,7 +358,7 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
     }
     if (ballot(left) && lane_id() == 0)
         __hip_atomic_store(&A.status[kDeep], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    grid_barrier(A.bar, A.status);
+    grid_barrier(A.bar, A.status, A.barrier_ticks);
     if (load_status(A.status) || load_status(&A.status[kDeep])) return;
     stamp(A.status, pass + 1);
     for (int64_t t = vw.first; t < vw.end; t += vw.step) {
@@ -458,6 +468,7 @@ hipError_t launch_batched(const BatchArgsHost& h, int blocks, hipStream_t s) {
     A.status = h.status;
     A.max_passes = h.max_passes;
     A.max_link = h.max_link;
+    A.barrier_ticks = h.barrier_ticks;
     A.part = h.part;
     void* args[] = {&A};
     return hipLaunchCooperativeKernel((const void*)batched_kernel, dim3(blocks), dim3(kBlock), args, 0, s);

@@ -26,6 +26,7 @@ struct BatchArgsHost {
     unsigned long long* status;
     int32_t max_passes;
     int32_t max_link;
+    uint64_t barrier_ticks;     // grid-barrier spin limit (100 MHz wall-clock ticks)
 };
 
 constexpr int64_t kBatchTile = 1024;   // edges per tile (256 threads x 4)

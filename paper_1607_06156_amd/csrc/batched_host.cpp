@@ -22,6 +22,20 @@ namespace ccmi {
 constexpr size_t kBatchCtl = 1024;      // barrier words + status block
 constexpr int kStatusWords = 48;        // status[0..3) codes, [4] deep chains left, status[8..48) pass stamps
 constexpr int kStatusDeep = 4;
+// status[0] error bits written by the persistent kernel
+constexpr unsigned long long kErrRangeBit = 1, kErrOffsetsBit = 2, kErrBarrierBit = 4;
+// default spin limit of the kernel's grid barrier: 5 s of the 100 MHz wall clock
+constexpr uint64_t kBarrierTicks = 500000000ull;
+
+// CC_BATCH_BARRIER_TICKS (a positive integer) overrides the spin limit, so the
+// fallback that a barrier timeout takes can be exercised from the host.
+static uint64_t barrier_ticks() {
+    const char* s = getenv("CC_BATCH_BARRIER_TICKS");
+    if (!s || !*s) return kBarrierTicks;
+    char* end = nullptr;
+    unsigned long long t = strtoull(s, &end, 10);
+    return (end && *end == 0 && t > 0) ? (uint64_t)t : kBarrierTicks;
+}
 
 // The persistent kernel's final compression met a chain deeper than one walk
 // (kMaxHops links) and left the labels as global, unflattened parents: flatten
@@ -155,6 +169,16 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
+    // A grid barrier that waited past its limit means that not every
+    // workgroup of the grid was resident at once (the cooperative launch
+    // does not stop kernels of other streams or processes from holding CUs).
+    // Every workgroup has exited, and the disjoint-union fallback
+    // re-initialises the labels, so the call still returns exact labels.
+    // Range and offset errors found before the timeout are reported instead.
+    if ((status_host[0] & kErrBarrierBit) && !(status_host[0] & (kErrRangeBit | kErrOffsetsBit)) && refused) {
+        *refused = true;
+        return CC_OK;
+    }
     if (status_host[0] == 0 && status_host[kStatusDeep]) return finish_deep(h, pb, status_host, s);
     return CC_OK;
 }
@@ -236,7 +260,7 @@ static int run_union(Workspace& ws, const BatchArgsHost& h, hipStream_t s, unsig
 static int status_code(const unsigned long long* st) {
     if (st[0] & 1) return fail(CC_ERANGE, "%llu edges have an endpoint outside their graph's [0, n_g)", st[2]);
     if (st[0] & 2) return fail(CC_EINVAL, "edge_off / vert_off are not non-decreasing");
-    if (st[0] & 4) return fail(CC_EINTERNAL, "grid barrier timed out");
+    if (st[0] & 4) return fail(CC_EINTERNAL, "grid barrier timed out");   // only without a fallback
     if (st[0] & 8) return fail(CC_EINTERNAL, "pass cap reached");
     if (st[0] & 16) return fail(CC_EINTERNAL, "flatten did not finish");
     return CC_OK;
@@ -288,6 +312,7 @@ CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t
     h.n = (int32_t)n;
     h.labels = labels;
     h.max_passes = 100000;
+    h.barrier_ticks = barrier_ticks();
     Tuned cfg;
     maxb &= ~7;   // the tile walk gives each of the 8 XCDs the same number of workgroups
     if (maxb < 8) return fail(CC_EINTERNAL, "persistent grid too small for this device");

@@ -37,23 +37,61 @@ enum WsSlot {
     WS_NSLOTS
 };
 
+// Device scratch of a call, in one of three forms:
+//  kCached : the library's per-device buffers, grown on demand with hipMalloc
+//            and kept between calls (until cc_release_workspace); a caller
+//            holds `mu` while it uses them;
+//  kPool   : stream-ordered allocations from the library's per-device memory
+//            pool on the call's stream, freed (stream-ordered) when the call
+//            ends; the pool keeps the memory for later calls;
+//  kArena  : a caller-provided block, cut into one region per slot, each
+//            sized on its first use to the slot's bound for the call's (m, n)
+//            (workspace_bound), so no request outgrows it.
+// Small readbacks go through `host`: pinned staging of kHostBytes (kCached:
+// the device's own; otherwise taken from a shared pool for the call), or a
+// caller buffer of at least kHostBytes marked host_external.
 struct Workspace {
+    enum Mode { kCached = 0, kPool = 1, kArena = 2 };
     struct Buf {
         void* ptr = nullptr;
         size_t bytes = 0;
     };
     static constexpr size_t kHostBytes = 1 << 20;
+    Mode mode = kCached;
     int device = 0;
-    std::mutex mu;
+    std::mutex mu;              // kCached only
     Buf bufs[WS_NSLOTS];
-    void* host = nullptr;  // pinned staging for small readbacks
+    void* host = nullptr;       // staging for small readbacks
+    bool host_external = false; // host belongs to the caller
+    bool host_leased = false;   // host came from the shared pinned pool
+    // kPool
+    hipStream_t stream = nullptr;
+    hipMemPool_t pool = nullptr;
+    // kArena
+    char* arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
+    size_t bound[WS_NSLOTS] = {};
     ~Workspace();
     void release();
     int get(int slot, size_t bytes, void** out);
     int pinned(void** out);
+    // end of a kPool / kArena call: free the pool allocations on `stream`
+    // and return the pinned staging
+    void finish();
 };
 
+// Upper bound of each slot's size for one cc_label_ex call on (m, n).
+// sv_only: the routes without the degree pass (forced R1 / R2), whose scratch
+// is the SV iteration's alone.  Returns the total, each region rounded up to
+// 256 bytes, plus 256 for the alignment of the block itself.
+size_t workspace_bound(int64_t m, int32_t n, bool sv_only, size_t* per_slot);
+
+// a per-call workspace in kPool mode on the current device (stream-ordered)
+int pool_workspace(Workspace* ws, hipStream_t s);
+
 int acquire_workspace(Workspace** out);
+// frees the router weights' device copies (router.cpp)
+void router_release_all();
 
 struct Timer {
     bool enabled;

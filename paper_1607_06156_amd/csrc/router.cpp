@@ -51,6 +51,19 @@ static int router_device_params(float** out, hipStream_t s) {
     return CC_OK;
 }
 
+// frees the per-device copies of the weights (the host copy stays loaded)
+void router_release_all() {
+    std::lock_guard<std::mutex> g(g_router_mu);
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (auto& kv : g_router_dev) {
+        if (kv.second && hipSetDevice(kv.first) == hipSuccess) (void)hipFree(kv.second);
+        kv.second = nullptr;
+        g_router_dev_gen[kv.first] = ~0ull;
+    }
+    if (have_cur) (void)hipSetDevice(cur);
+}
+
 int decide_router(Call& c, DegreeResult& r, int* route) {
     float* P;
     int rc = router_device_params(&P, c.stream);

@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_1607_06156_amd", "libccmi.so")
 
 def declared():
     src = open(HEADER).read()
-    return re.findall(r"^\s*(?:int|void|const char\*)\s+(cc_\w+)\s*\(", src, re.M)
+    return re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(cc_\w+)\s*\(", src, re.M)
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +29,8 @@ def test_header_declares_the_boundary():
     names = set(declared())
     for must in ["cc_label", "cc_label_ex", "cc_label_batched", "cc_label_batched_ex", "cc_router_load",
                  "cc_last_error", "cc_version", "cc_degree", "cc_degree_histograms", "cc_powerlaw_ks", "cc_csr",
-                 "cc_bfs", "cc_bfs_filter", "cc_mlp_forward", "cc_mlp_sgd_step"]:
+                 "cc_bfs", "cc_bfs_filter", "cc_mlp_forward", "cc_mlp_sgd_step", "cc_workspace_size",
+                 "cc_release_workspace", "cc_shutdown"]:
         assert must in names
 
 
@@ -39,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_defaults(lib):
-    assert lib.cc_version() == 10000
+    assert lib.cc_version() == 10100
     import paper_1607_06156_amd as ccmi
     opt = ccmi.Options()
     lib.cc_default_options(ctypes.byref(opt))
@@ -49,8 +50,8 @@ def test_version_and_defaults(lib):
 def test_struct_layouts_match_header(lib):
     """The Python mirrors of cc_options / cc_stats have the C sizes."""
     import paper_1607_06156_amd as ccmi
-    # cc_options: 2 int32, 2 double, 8 int32
-    assert ctypes.sizeof(ccmi.Options) == 8 + 16 + 32
+    # cc_options: 2 int32, 2 double, 2 int32, a pointer, an int64, 4 int32
+    assert ctypes.sizeof(ccmi.Options) == 8 + 16 + 8 + 8 + 8 + 16
     st = ccmi.Stats()
     assert ctypes.sizeof(st) % 8 == 0
     assert ccmi.Stats.active_edges.offset % 8 == 0
@@ -106,6 +107,33 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert b"below 4096" in lib.cc_last_error()
     lib.cc_router_load.argtypes = [ctypes.c_char_p]
     assert lib.cc_router_load(b"/nonexistent/weights.txt") == -1
+
+
+def test_workspace_size_and_checks(lib):
+    """cc_workspace_size grows with m and n, is smaller for the forced SV
+    routes (no degree pass), rejects bad arguments; a caller workspace below
+    it is refused before any device work."""
+    import paper_1607_06156_amd as ccmi
+    L = ccmi.lib()
+    sv = L.cc_workspace_size(1 << 20, 1 << 18, ccmi.ROUTE_SV)
+    full = L.cc_workspace_size(1 << 20, 1 << 18, ccmi.ROUTE_AUTO)
+    assert 0 < sv < full
+    assert 20 * (1 << 20) <= sv <= 21 * (1 << 20) + (1 << 20)     # ~20 B per edge plus fixed tables
+    assert L.cc_workspace_size(1 << 21, 1 << 18, ccmi.ROUTE_SV) > sv
+    assert L.cc_workspace_size(1 << 20, 1 << 19, ccmi.ROUTE_AUTO) > full
+    assert L.cc_workspace_size(1 << 20, 1 << 18, ccmi.ROUTE_SV_THETA) == sv
+    assert L.cc_workspace_size(-1, 5, 0) == -1 and L.cc_workspace_size(1, 5, 9) == -1
+    opt = ccmi.Options()
+    L.cc_default_options(ctypes.byref(opt))
+    opt.workspace = 4096                                      # never dereferenced: refused on size
+    opt.workspace_bytes = 1024
+    assert L.cc_label_ex(8, 8, 1000, 100, 8, None, ctypes.byref(opt), None) == -1
+    assert b"workspace" in L.cc_last_error()
+    opt.workspace_bytes = 0
+    assert L.cc_label_ex(8, 8, 1000, 100, 8, None, ctypes.byref(opt), None) == -1
+    opt.workspace = None
+    opt.scratch = 7
+    assert L.cc_label_ex(8, 8, 1000, 100, 8, None, ctypes.byref(opt), None) == -1
 
 
 def test_router_weights_file_roundtrip(lib, tmp_path):

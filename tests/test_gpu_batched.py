@@ -121,3 +121,20 @@ def test_dense_and_deep_graphs():
     exp = expected(b)
     for kw in [{}, {"max_link": 1}, {"max_link": 4}, {"tile_edges": 1}]:
         assert np.array_equal(run_batch(b, **kw).cpu().numpy(), exp), kw
+
+
+def test_barrier_timeout_falls_back_to_union(monkeypatch):
+    """A grid barrier that waits past its spin limit (here forced from the
+    host: a limit of one 100 MHz tick, so every early workgroup gives up and
+    all exit) makes the call fall back to the disjoint-union SV loop: the
+    labels are still exact and the stats report no persistent grid."""
+    monkeypatch.setenv("CC_BATCH_BARRIER_TICKS", "1")
+    b = gen.batch(40, 4_242_000, lg_hi=13.0)
+    lab, st = run_batch(b, tile_edges=4096, max_link=1, stats=True)
+    say(f"   passes={st['passes']} blocks={st['blocks']}")
+    assert st["blocks"] == 0
+    assert np.array_equal(lab.cpu().numpy(), expected(b))
+    monkeypatch.delenv("CC_BATCH_BARRIER_TICKS")
+    lab, st = run_batch(b, tile_edges=4096, max_link=1, stats=True)
+    assert st["blocks"] > 0
+    assert np.array_equal(lab.cpu().numpy(), expected(b))

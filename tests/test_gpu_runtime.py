@@ -100,7 +100,8 @@ def test_batched_from_a_second_process():
 def test_concurrent_calls_from_threads():
     """Four host threads, each on its own stream, call the library at once:
     three label single graphs (a different route each call), one labels a
-    batch.  The calls share each device's workspace under its lock; every
+    batch.  The single-graph calls take stream-ordered scratch from the pool
+    (no lock); the batch uses the cached workspace under its lock.  Every
     result is exact and each thread's error slot stays its own."""
     import threading
     graphs = [gen.workload("rmat16"), gen.gnm(200_000, 300_000, seed=3), gen.grid(400, 0.6, seed=4)]
@@ -135,5 +136,68 @@ def test_concurrent_calls_from_threads():
         t.start()
     for t in ts:
         t.join(timeout=120)
+    assert not any(t.is_alive() for t in ts)
+    assert not errors, errors
+
+
+def test_scratch_modes_exact():
+    """The three scratch sources give the same exact labels on every route:
+    stream-ordered pool allocations, the cached per-device workspace, and a
+    caller block of exactly cc_workspace_size bytes (used twice in a row, the
+    second time for a smaller graph)."""
+    graphs = [gen.workload("rmat16"), gen.grid(300, 0.7, seed=8), gen.gnm(50_000, 40_000, seed=9)]
+    for g in graphs:
+        u, v = to_dev(g.u), to_dev(g.v)
+        expect = oracle_labels(g)
+        for route in ("sv", "sv-theta", "heuristic", "bfs+sv"):
+            say(f"[gpu] scratch modes {g.name} {route}")
+            assert_labels_equal(ccmi.label(u, v, g.n, route=route), expect, f"{g.name}/{route}/pool")
+            assert_labels_equal(ccmi.label(u, v, g.n, route=route, scratch="cached"), expect,
+                                f"{g.name}/{route}/cached")
+            size = ccmi.workspace_size(g.m, g.n, route)
+            ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+            assert_labels_equal(ccmi.label(u, v, g.n, route=route, workspace=ws), expect,
+                                f"{g.name}/{route}/workspace")
+            h = gen.gnm(g.n // 3, g.m // 4, seed=10)      # a smaller graph in the same block
+            assert_labels_equal(ccmi.label(to_dev(h.u), to_dev(h.v), h.n, route=route, workspace=ws),
+                                oracle_labels(h), f"{h.name}/{route}/workspace reused")
+            with pytest.raises(ccmi.CCError):
+                ccmi.label(u, v, g.n, route=route, workspace=ws[: size - 1])
+
+
+def test_threads_with_their_own_workspaces():
+    """Two host threads, each with its own stream and its own caller
+    workspace, label different graphs at the same time, five times each,
+    through every route; every result is exact."""
+    import threading
+    graphs = [gen.workload("rmat16"), gen.grid(500, 0.65, seed=21)]
+    expects = [oracle_labels(g) for g in graphs]
+    errors = []
+    start = threading.Barrier(2)
+
+    def work(k):
+        try:
+            g = graphs[k]
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                u, v = to_dev(g.u), to_dev(g.v)
+                ws = torch.empty(ccmi.workspace_size(g.m, g.n, "auto"), dtype=torch.uint8, device="cuda")
+                s.synchronize()
+                start.wait(timeout=60)
+                for rep in range(5):
+                    for route in ("sv", "heuristic", "bfs+sv", "sv-theta"):
+                        lab = ccmi.label(u, v, g.n, route=route, workspace=ws)
+                        s.synchronize()
+                        if not np.array_equal(lab.cpu().numpy(), expects[k]):
+                            errors.append(f"thread {k} rep {rep} {route}: labels differ")
+        except Exception as e:   # noqa: BLE001 -- reported below
+            errors.append(f"thread {k}: {e!r}")
+
+    say("[gpu] 2 threads, own workspaces")
+    ts = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=180)
     assert not any(t.is_alive() for t in ts)
     assert not errors, errors
