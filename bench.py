@@ -35,15 +35,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_route(ccmi, torch, u, v, n, route, steps, warmup, profile=False):
+def time_route(ccmi, torch, u, v, n, route, steps, warmup, profile=False, **kw):
     out = torch.empty(n, dtype=torch.int32, device=u.device)
     for _ in range(warmup):
-        ccmi.label(u, v, n, route=route, out=out)
+        ccmi.label(u, v, n, route=route, out=out, **kw)
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        _, st = ccmi.label(u, v, n, route=route, out=out, stats=True, profile=profile)
+        _, st = ccmi.label(u, v, n, route=route, out=out, stats=True, profile=profile, **kw)
         stats.append(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -151,6 +151,13 @@ def main():
                 log(f"[bench] forced {r}: {s2 * 1e3:.3f} ms  {g.m / s2 / 1e9:.2f} G edges/s")
             except Exception as ex:  # route not available
                 extra[r] = {"error": str(ex)}
+        # the same forced SV route with the other two scratch sources
+        ws = torch.empty(ccmi.workspace_size(g.m, g.n, "sv"), dtype=torch.uint8, device="cuda")
+        for key, kw in (("sv/scratch=pool", {"scratch": "pool"}), ("sv/caller workspace", {"workspace": ws})):
+            _, s2, sts = time_route(ccmi, torch, u, v, g.n, "sv", max(2, args.steps // 2), 1, **kw)
+            extra[key] = {"ms_per_step": round(s2 * 1e3, 3), "edges_per_s": g.m / s2}
+            log(f"[bench] forced sv, {key}: {s2 * 1e3:.3f} ms")
+        del ws
 
     cpu = None
     exact = None

@@ -26,19 +26,22 @@
  *    work is enqueued on it.  Calls return after their results are complete
  *    (they read small device counters to drive their loops), i.e. they are
  *    host-synchronous with respect to `stream`.
- *  - Scratch memory of cc_label / cc_label_ex (cc_options.scratch,
- *    cc_options.workspace): by default it is allocated stream-ordered on
- *    `stream` from a memory pool that the library keeps per device, and
- *    freed stream-ordered before the call returns; calls on different streams
- *    or threads then run at once.  A caller may instead pass a device block of
- *    at least cc_workspace_size() bytes (nothing is allocated on the device
- *    for scratch), or ask for the library's cached per-device workspace (grown
- *    with hipMalloc, kept until cc_release_workspace(); calls that use it
- *    serialise on a per-device lock).  The batched calls and the step entry
- *    points use the cached workspace.  Small readbacks use pinned host
- *    buffers that the library keeps (one per call in flight).
- *    cc_release_workspace() trims the current device's pool and frees its
- *    cached workspace; cc_shutdown() frees everything the library holds.
+ *  - Scratch memory of cc_label / cc_label_ex comes from one of three
+ *    places (cc_options.scratch, cc_options.workspace):
+ *      the caller's device block of at least cc_workspace_size() bytes
+ *        (nothing is allocated on the device; calls with their own blocks
+ *        run at once from any threads and streams);
+ *      stream-ordered allocations on `stream` from a memory pool the library
+ *        keeps per device, freed stream-ordered before the call returns
+ *        (no lock; calls on different streams run at once);
+ *      by default, the library's cached per-device workspace, grown with
+ *        hipMalloc and kept until cc_release_workspace(): the fastest for
+ *        repeated calls, but calls that use it serialise on a per-device lock.
+ *    The batched calls and the step entry points use the cached workspace.
+ *    Small readbacks use pinned host buffers that the library keeps (one per
+ *    call in flight).  cc_release_workspace() trims the current device's pool
+ *    and frees its cached workspace; cc_shutdown() frees everything the
+ *    library holds.
  *  - Return value: CC_OK (0) or a negative CC_E* code; cc_last_error() then
  *    returns a message (thread-local).  Nothing is thrown across the ABI.
  */
@@ -82,8 +85,8 @@ extern "C" {
 #define CC_R2_SV_THETA 2
 
 /* scratch modes (cc_options.scratch), used when no workspace is given */
-#define CC_SCRATCH_POOL 0   /* stream-ordered allocations on `stream` from the library's per-device pool */
-#define CC_SCRATCH_CACHED 1 /* the library's per-device workspace, kept between calls; calls serialise on it */
+#define CC_SCRATCH_CACHED 0 /* the library's per-device workspace, kept between calls; calls serialise on it */
+#define CC_SCRATCH_POOL 1   /* stream-ordered allocations on `stream` from the library's per-device pool */
 
 typedef struct cc_options {
     int32_t route;       /* CC_ROUTE_* */
@@ -139,6 +142,9 @@ typedef struct cc_stats {
     double kernel_ms[8];          /* device time per kernel class, summed (profile = 1 only) */
     int32_t kernel_launches[8];   /* launches per kernel class (profile = 1 only) */
     double kernel_bytes[8];       /* algorithmic bytes per kernel class (profile = 1 only) */
+    int64_t sv_atomics;           /* atomicMin operations issued by the SV passes */
+    int64_t sv_chase_reads;       /* parent[] reads of the SV passes beyond two per active edge */
+    int64_t giant_dropped;        /* edges of the first pass dropped on the bitmap of the largest tree */
 } cc_stats;
 
 /* Fills *opt with the defaults (route AUTO, no cap, tau 0.05, theta 8). */

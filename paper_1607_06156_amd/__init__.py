@@ -39,8 +39,8 @@ class CCError(RuntimeError):
         self.code = code
 
 
-SCRATCH_POOL, SCRATCH_CACHED = 0, 1
-_SCRATCH_ARG = {None: SCRATCH_POOL, "pool": SCRATCH_POOL, "cached": SCRATCH_CACHED}
+SCRATCH_CACHED, SCRATCH_POOL = 0, 1
+_SCRATCH_ARG = {None: SCRATCH_CACHED, "cached": SCRATCH_CACHED, "pool": SCRATCH_POOL}
 
 
 class Options(ctypes.Structure):
@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
                 ("ms_predict", ctypes.c_double), ("ms_csr", ctypes.c_double), ("ms_bfs", ctypes.c_double),
                 ("ms_filter", ctypes.c_double), ("ms_sv", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("algorithmic_bytes", ctypes.c_double), ("kernel_ms", ctypes.c_double * 8),
-                ("kernel_launches", ctypes.c_int32 * 8), ("kernel_bytes", ctypes.c_double * 8)]
+                ("kernel_launches", ctypes.c_int32 * 8), ("kernel_bytes", ctypes.c_double * 8),
+                ("sv_atomics", ctypes.c_int64), ("sv_chase_reads", ctypes.c_int64), ("giant_dropped", ctypes.c_int64)]
 
     def to_dict(self) -> dict:
         d = {}
@@ -176,8 +177,9 @@ def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tenso
     """labels[x] = min vertex id of x's component; (u[i], v[i]) are undirected edges.
 
     workspace: a uint8 device tensor of at least workspace_size(m, n, route)
-    bytes used as the call's only device scratch; scratch: "pool" (default,
-    stream-ordered allocations) or "cached" (the library's kept workspace)."""
+    bytes used as the call's only device scratch; scratch: "cached" (default:
+    the library's kept per-device workspace, calls serialise on it) or "pool"
+    (stream-ordered allocations from the library's pool, no lock)."""
     m = int(u.numel())
     if int(v.numel()) != m:
         raise ValueError("u and v differ in length")

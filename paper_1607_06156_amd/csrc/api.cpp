@@ -235,8 +235,9 @@ size_t workspace_bound(int64_t m, int32_t n, bool sv_only, size_t* per_slot) {
     b[WS_EDGES0] = slots * 8;
     b[WS_EDGES1] = slots * 8;
     b[WS_HOOKED] = slots * 4;
-    b[WS_SEGCOUNT] = (size_t)8 * 2048 * 4 * sizeof(uint32_t);
+    b[WS_SEGCOUNT] = (size_t)8 * 2048 * 7 * sizeof(uint32_t);
     b[WS_TOTALS] = 64 * sizeof(unsigned long long);
+    if (M >= ((size_t)1 << 22)) b[WS_GIANT] = ((N + 63) / 64) * 8;   // a chunked first pass (pass0_chunks)
     if (!sv_only) {
         BucketPlan p;
         if (bucket_plan(n, m, &p) == 0 && m < ((int64_t)1 << 31)) {
@@ -378,7 +379,8 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
     if ((rc = ws.get(WS_EDGES0, slots * sizeof(int2), &pbuf0))) return rc;
     if ((rc = ws.get(WS_EDGES1, slots * sizeof(int2), &pbuf1))) return rc;
     if ((rc = ws.get(WS_HOOKED, slots * sizeof(int32_t), &phook))) return rc;
-    if ((rc = ws.get(WS_SEGCOUNT, (size_t)nseg * 4 * sizeof(uint32_t), &pcnt))) return rc;
+    // per segment: 3 rotating survivor counts, the hook count, 3 statistics
+    if ((rc = ws.get(WS_SEGCOUNT, (size_t)nseg * 7 * sizeof(uint32_t), &pcnt))) return rc;
     void* ptot;
     if ((rc = ws.get(WS_TOTALS, 64 * sizeof(unsigned long long), &ptot))) return rc;
     unsigned long long* totals = (unsigned long long*)ptot;
@@ -387,6 +389,16 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
     uint32_t* cnt[4];
     for (int i = 0; i < 4; ++i) cnt[i] = (uint32_t*)pcnt + (size_t)i * nseg;
     uint32_t* hooked_count = cnt[3];
+    uint32_t* segstat = (uint32_t*)pcnt + (size_t)4 * nseg;
+    // The largest tree during a chunked first pass (see below): its root in
+    // an int32 word of the totals block, its membership bitmap in WS_GIANT.
+    int32_t* gflag = (int32_t*)(totals + 10);
+    uint32_t* gbits = nullptr;
+    if (in0.soa && chunks > 1) {
+        void* pg;
+        if ((rc = ws.get(WS_GIANT, (size_t)((c.n + 63) / 64) * 8, &pg))) return rc;
+        gbits = (uint32_t*)pg;
+    }
     int2* bufs[2] = {(int2*)pbuf0, (int2*)pbuf1};
 
     hipError_t e = hipMemsetAsync(totals, 0, 64 * sizeof(unsigned long long), c.stream);
@@ -419,6 +431,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         SegList out{bufs[out_buf], cap, nseg, cnt[out_cnt]};
         int rec_pass = -1;
         double flat_bytes = 0.0;
+        int64_t filt_edges = 0;   // edges of this pass read by launches with the bitmap
         if (in_soa) {
             // chunk k covers segments [k * nseg_chunk, (k + 1) * nseg_chunk);
             // on dense graphs the first chunk is launched as [0, cut), [cut, nseg_chunk)
@@ -428,6 +441,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                 for (int part = 0; part < (k == 0 ? split : 1); ++part) {
                     const int s0 = k > 0 ? k * nseg_chunk : (part == 0 ? 0 : cut);
                     const int s1 = k > 0 ? (k + 1) * nseg_chunk : (split == 1 || part == 1 ? nseg_chunk : cut);
+                    const bool filt = s0 > 0 && gbits;
                     if (s0 > 0) {
                         int kf = c.kbeg();
                         e = launch_sv_finalize(c.parent, c.n, totals + 6, c.stream);
@@ -436,14 +450,33 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                         c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n);
                         flat_bytes += 12.0 * c.n;
                     }
+                    if (filt) {
+                        // Edges inside the largest tree are finished (Section
+                        // III-A.4); after the flatten, a bitmap of that tree
+                        // lets the next launch drop them with two bit probes
+                        // instead of two gathers of parent[].  Sampled roots
+                        // pick the tree; none holding 1/16 of the samples
+                        // turns the probes off.
+                        int kg = c.kbeg();
+                        e = launch_giant_pick(c.parent, c.n, gflag, c.stream);
+                        if (e == hipSuccess) e = launch_giant_bits(c.parent, c.n, gflag, gbits, c.stream);
+                        if (e != hipSuccess) return hip_fail(e, "giant bitmap launch");
+                        // sampled gathers, parent read per vertex, bitmap written
+                        c.kend(CC_K_SV_SHORTCUT, kg, 4.0 * c.n + c.n / 8.0);
+                        flat_bytes += 4.0 * c.n + c.n / 8.0;
+                    }
                     int k0 = c.kbeg();
                     e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, s0, s1 - s0, write ? 1 : 0, max_link,
-                                           (int32_t*)phook, hooked_count, totals, c.stream);
+                                           (int32_t*)phook, hooked_count, totals, segstat, filt ? gbits : nullptr,
+                                           filt ? gflag : nullptr, c.stream);
                     if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
-                    // this launch's edges; the survivors' bytes go to the last one below
+                    // this launch's edges (read + two 4-byte gathers or bit
+                    // probes each); the rest of the pass's bytes go to the
+                    // last launch below
                     const int64_t e0 = std::min<int64_t>(m0, (int64_t)s0 * cap);
                     const int64_t e1 = std::min<int64_t>(m0, (int64_t)s1 * cap);
                     rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)(e1 - e0));
+                    if (filt) filt_edges += e1 - e0;
                 }
             }
         } else {
@@ -462,7 +495,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                 const int nb = std::min(per, nseg - s0);
                 int k0 = c.kbeg();
                 e = launch_sv_pass_seg(in, s0, nb, c.parent, out, write ? 1 : 0, max_link, (int32_t*)phook,
-                                       hooked_count, totals, c.stream);
+                                       hooked_count, totals, segstat, c.stream);
                 if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
                 // this chunk's share of the edges (segments hold about equal counts)
                 rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)m_in * nb / nseg);
@@ -472,9 +505,9 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         // already jumped every root hooked before the last chunk: only the
         // last chunk's segments hold roots still to jump.
         const int jump_lo = in_soa && chunks > 1 ? (chunks - 1) * nseg_chunk : 0;
-        e = launch_sv_totals(hooked_count, out.count, nseg, jump_lo, totals, c.stream);
+        e = launch_sv_totals(hooked_count, out.count, nseg, jump_lo, segstat, totals, c.stream);
         if (e != hipSuccess) return hip_fail(e, "sv_totals launch");
-        e = hipMemcpyAsync(htot, totals, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
+        e = hipMemcpyAsync(htot, totals, 10 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(totals)");
         e = hipStreamSynchronize(c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -508,11 +541,19 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             if (c.stats->sv_passes < 64) c.stats->active_edges[c.stats->sv_passes] = m_in;
             c.stats->sv_passes++;
             c.stats->hooks_total += hooks;
-            // edges read (8 B) + two 4 B gathers + one 8 B atomic per unfinished edge
-            // + survivors written (8 B); shortcut: read, gather, write per hooked root
-            const double pass_bytes = 16.0 * m_in + 8.0 * kept + (write ? 8.0 * kept : 0.0);
-            c.bytes += pass_bytes + (jump ? 12.0 * fresh : 0.0) + flat_bytes;
-            c.kadd(rec_pass, 8.0 * kept + (write ? 8.0 * kept : 0.0));
+            const int64_t natom = (int64_t)htot[7], nchase = (int64_t)htot[8], ndrop = (int64_t)htot[9];
+            c.stats->sv_atomics += natom;
+            c.stats->sv_chase_reads += nchase;
+            c.stats->giant_dropped += ndrop;
+            // edges read (8 B) with two 4 B gathers (or bit probes) each, the
+            // two parent gathers of the edges that passed the bitmap, 8 B per
+            // atomic issued, 4 B per read of the walks up the forest, and the
+            // survivors written (8 B); shortcut: read, gather, write per
+            // hooked root
+            const double rest = 8.0 * (double)(filt_edges - ndrop) + 8.0 * natom + 4.0 * nchase +
+                                (write ? 8.0 * kept : 0.0);
+            c.bytes += 16.0 * m_in + rest + (jump ? 12.0 * fresh : 0.0) + flat_bytes;
+            c.kadd(rec_pass, rest);
         }
         ++pass;
         if (kept == 0) break;
@@ -575,9 +616,9 @@ CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
     if (stats) stats_reset(stats);
     if (n == 0) return CC_OK;
 
-    // scratch: the caller's block, the library's cached per-device buffers
-    // (serialised by their lock), or stream-ordered allocations from the
-    // library's pool (the default)
+    // scratch: the caller's block, stream-ordered allocations from the
+    // library's pool, or (the default) the library's cached per-device
+    // buffers, serialised by their lock
     Workspace local;
     Workspace* ws = &local;
     std::unique_lock<std::mutex> lk;
@@ -593,11 +634,11 @@ CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
         local.mode = Workspace::kArena;
         local.arena = (char*)opt.workspace;
         local.arena_bytes = (size_t)opt.workspace_bytes;
-    } else if (opt.scratch == CC_SCRATCH_CACHED) {
+    } else if (opt.scratch == CC_SCRATCH_POOL) {
+        if ((rc = pool_workspace(&local, (hipStream_t)stream))) return rc;
+    } else {
         if ((rc = acquire_workspace(&ws))) return rc;
         lk = std::unique_lock<std::mutex>(ws->mu);
-    } else {
-        if ((rc = pool_workspace(&local, (hipStream_t)stream))) return rc;
     }
 
     Call c;

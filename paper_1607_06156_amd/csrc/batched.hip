@@ -163,6 +163,7 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
     // shifts the ids to global ones and drops (and counts) edges with an id
     // outside their graph.
     uint32_t bad = 0, nlong = 0;
+    uint32_t natom = 0, nchase = 0;   // not reported by the batched kernel
     unsigned long long block_kept = 0, block_hooks = 0;
     for (int64_t t = tw.first; t < tw.end; t += tw.step) {
         const int64_t e0 = t * kTileE;
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
         uint32_t kept = 0, hk = 0;
         if (len > 0)
             sv_segment(len, load, A.parent, A.buf0 + t * kTileE, A.hooked + t * kTileE, true, A.max_link, kept, hk,
-                       nlong, lds);
+                       nlong, lds, natom, nchase);
         if (threadIdx.x == 0) {
             A.cnt0[t] = kept;
             A.hcnt[t] = hk;
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
                     return true;
                 };
                 sv_segment((int64_t)len, load, A.parent, out + t * kTileE, A.hooked + t * kTileE, true, A.max_link,
-                           kept, hk, nlong, lds);
+                           kept, hk, nlong, lds, natom, nchase);
             }
             if (threadIdx.x == 0) {
                 cout[t] = kept;

@@ -96,24 +96,36 @@ hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s);
 // out.nseg segments of out.cap edges; this launch covers segments
 // [seg0, seg0 + nblocks), one block each.  Writes survivors into out (if
 // write_out), hooked roots into hooked (segments of the same cap), per-segment
-// counts, and accumulates totals[2] (range errors) and totals[4] (edges whose
-// find stopped at the hop bound: the forest needs flatten rounds).
+// counts, per-segment statistics (segstat[3 b ...]: atomics issued, chase
+// reads, edges dropped by the bitmap), and accumulates totals[2] (range
+// errors) and totals[4] (edges whose find stopped at the hop bound: the
+// forest needs flatten rounds).  With gbits and gflag (from launch_giant_pick
+// and launch_giant_bits after a flatten), edges with both endpoints in the
+// largest tree are dropped on a bitmap probe.
 hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
                               SegList out, int32_t seg0, int32_t nblocks, int write_out, int max_link,
-                              int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals, hipStream_t s);
+                              int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
+                              uint32_t* segstat, const uint32_t* gbits, const int32_t* gflag, hipStream_t s);
 // passes over a segmented list: segments [seg0, seg0 + nblocks) of in, each
 // one block, survivors to the same segments of out
 hipError_t launch_sv_pass_seg(SegList in, int32_t seg0, int32_t nblocks, int32_t* parent, SegList out, int write_out,
                               int max_link, int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
-                              hipStream_t s);
+                              uint32_t* segstat, hipStream_t s);
+// largest tree of a flattened forest, by sampling: *gflag = its root, or -1
+// if no root holds 1/16 of the samples.  No hook may run concurrently.
+hipError_t launch_giant_pick(const int32_t* parent, int32_t n, int32_t* gflag, hipStream_t s);
+// bits (2 * ceil(n / 64) words) = membership of the tree of *gflag (if >= 0),
+// right after a flatten.  No hook may run concurrently.
+hipError_t launch_giant_bits(const int32_t* parent, int32_t n, const int32_t* gflag, uint32_t* bits, hipStream_t s);
 // pointer-jumps the hooked roots of each segment, at most kMaxHops links each
 // (no hook may run concurrently)
 hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint32_t* hooked_count, int64_t cap,
                               int32_t nseg, hipStream_t s);
 // totals[0] = sum(kept_count), totals[1] = sum(hooked_count) over nseg
-// segments, totals[3] = sum(hooked_count) over segments seg_lo .. nseg-1
+// segments, totals[3] = sum(hooked_count) over segments seg_lo .. nseg-1,
+// totals[7..9] = sums of the segments' statistics
 hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg, int32_t seg_lo,
-                            unsigned long long* totals, hipStream_t s);
+                            const uint32_t* segstat, unsigned long long* totals, hipStream_t s);
 // one flatten round: parent[x] = root(x) for every x whose root lies at most
 // kMaxHops links up, else the ancestor that far up, and then *open = 1 (set
 // only, never cleared here).  No hook may run concurrently.

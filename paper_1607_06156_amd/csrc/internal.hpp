@@ -34,6 +34,7 @@ enum WsSlot {
     WS_KS,           // power-law fit inputs and results
     WS_HISTOUT,      // reduced histograms, tail count, arg-max key
     WS_BATCH,        // batched-mode tables
+    WS_GIANT,        // bitmap of the largest tree during a chunked first pass
     WS_NSLOTS
 };
 

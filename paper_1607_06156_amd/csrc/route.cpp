@@ -369,7 +369,9 @@ int run_bfs_route(Call& c, DegreeResult& r) {
     int32_t* dlabel = (int32_t*)((unsigned long long*)ptot + 28);
     const int nseg = choose_nseg(c.m);
     const int64_t cap = (c.m + nseg - 1) / nseg;
-    if ((rc = ws.get(WS_SEGCOUNT, std::max((size_t)nseg * 4 * sizeof(uint32_t),
+    // the size run_sv asks for (7 words per segment), so that the filtered
+    // list's counts stay where they are when SV takes the list over
+    if ((rc = ws.get(WS_SEGCOUNT, std::max((size_t)nseg * 7 * sizeof(uint32_t),
                                            (size_t)(c.n + 1 + c.n / 1024 + 3) * sizeof(int64_t)),
                      &pcnt)))
         return rc;

@@ -43,33 +43,50 @@ __global__ __launch_bounds__(kBlock) void sv_init_kernel(int32_t* __restrict__ p
 // SOA: edges come from the caller's u[], v[] (dense); the block works on
 // segment b = seg0 + blockIdx.x, edges [b*cap, min((b+1)*cap, m)), and checks
 // ids against [0, n).  Else from segment b of `in`.
-template <bool SOA>
+// FILT (SOA only): while *gflag >= 0, an edge whose two endpoints both have
+// their bit set in gbits (vertices already in the largest tree when the
+// bitmap was built) is finished and dropped without touching parent[].
+// segstat[3 b ...] receives the block's atomics issued, chase reads and edges
+// dropped by the bitmap.
+template <bool SOA, bool FILT>
 __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restrict__ u, const int32_t* __restrict__ v,
                                                          int64_t m, int32_t n, int32_t seg0, SegList in,
                                                          int32_t* parent, SegList out, int write_out, int max_link,
                                                          int32_t* __restrict__ hooked,
                                                          uint32_t* __restrict__ hooked_count,
-                                                         unsigned long long* __restrict__ totals) {
+                                                         unsigned long long* __restrict__ totals,
+                                                         const uint32_t* __restrict__ gbits,
+                                                         const int32_t* __restrict__ gflag,
+                                                         uint32_t* __restrict__ segstat) {
     __shared__ uint32_t lds[kWaves + 1];
+    __shared__ uint32_t red[3][kWaves];
     const int b = seg0 + blockIdx.x;
     int2* dst = out.buf + (int64_t)b * out.cap;
     int32_t* hdst = hooked + (int64_t)b * out.cap;
-    uint32_t kept_off = 0, hook_off = 0, bad = 0, nlong = 0;
+    uint32_t kept_off = 0, hook_off = 0, bad = 0, nlong = 0, natom = 0, nchase = 0, nfilt = 0;
     if (SOA) {
         const int64_t base = (int64_t)b * out.cap;
         int64_t len = m - base;
         if (len > out.cap) len = out.cap;
         if (len < 0) len = 0;
+        const bool filt = FILT && *gflag >= 0;
         auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
-            *a = u[base + i];
-            *c = v[base + i];
+            // the edge list is read once: keep it from displacing parent[]
+            // and the bitmap in the caches
+            *a = __builtin_nontemporal_load(u + base + i);
+            *c = __builtin_nontemporal_load(v + base + i);
             if ((uint32_t)*a >= (uint32_t)n || (uint32_t)*c >= (uint32_t)n) {
                 ++bad;
                 return false;
             }
+            if (filt && ((gbits[*a >> 5] >> (*a & 31)) & (gbits[*c >> 5] >> (*c & 31)) & 1u)) {
+                ++nfilt;
+                return false;
+            }
             return true;
         };
-        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds);
+        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds, natom,
+                   nchase);
     } else {
         const int2* src = in.buf + (int64_t)b * in.cap;
         const int64_t len = in.count[b];
@@ -79,12 +96,33 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
             *c = e.y;
             return true;
         };
-        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds);
+        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds, natom,
+                   nchase);
     }
     // per-block results (no global atomics on the fast path)
+    for (int off = 32; off > 0; off >>= 1) {
+        natom += __shfl_xor(natom, off);
+        nchase += __shfl_xor(nchase, off);
+        nfilt += __shfl_xor(nfilt, off);
+    }
+    if (lane_id() == 0) {
+        red[0][threadIdx.x >> 6] = natom;
+        red[1][threadIdx.x >> 6] = nchase;
+        red[2][threadIdx.x >> 6] = nfilt;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         out.count[b] = kept_off;
         hooked_count[b] = hook_off;
+        uint32_t sa = 0, sc = 0, sf = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            sa += red[0][w];
+            sc += red[1][w];
+            sf += red[2][w];
+        }
+        segstat[3 * (int64_t)b] = sa;
+        segstat[3 * (int64_t)b + 1] = sc;
+        segstat[3 * (int64_t)b + 2] = sf;
     }
     if (SOA) {
         // range errors are rare: only then touch a global counter
@@ -94,6 +132,82 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
     // so are finds stopped at the hop bound (totals[4])
     for (int off = 32; off > 0; off >>= 1) nlong += __shfl_xor(nlong, off);
     if (lane_id() == 0 && nlong) atomic_add_agent(&totals[4], nlong);
+}
+
+// The largest tree, between two launches of a first pass (after a flatten, so
+// every vertex points at its root).  One workgroup samples kPickSamples
+// vertices evenly spread over [0, n), counts their roots in an LDS hash table
+// and writes the most frequent root (the smallest on ties) to *gflag if it
+// holds at least min_count samples, else -1.
+constexpr int kPickThreads = 1024;
+constexpr int kPickSamples = 4096;
+constexpr int kPickSlots = 8192;
+__global__ __launch_bounds__(kPickThreads) void giant_pick_kernel(const int32_t* __restrict__ parent, int32_t n,
+                                                                  int32_t* __restrict__ gflag, uint32_t min_count) {
+    __shared__ int32_t keys[kPickSlots];
+    __shared__ uint32_t cnts[kPickSlots];
+    __shared__ unsigned long long wbest[kPickThreads / 64];
+    for (int i = threadIdx.x; i < kPickSlots; i += kPickThreads) {
+        keys[i] = -1;
+        cnts[i] = 0;
+    }
+    __syncthreads();
+    for (int j = 0; j < kPickSamples / kPickThreads; ++j) {
+        const int64_t i = threadIdx.x + (int64_t)j * kPickThreads;
+        const int32_t x = (int32_t)((i * (int64_t)n) / kPickSamples);
+        bool root;
+        const int32_t r = find_bounded(parent, x, &root);
+        if (!root) continue;
+        uint32_t h = ((uint32_t)r * 2654435761u) >> 19;   // 13 bits
+        for (;;) {
+            const int32_t old = atomicCAS(&keys[h], -1, r);
+            if (old == -1 || old == r) {
+                atomicAdd(&cnts[h], 1u);
+                break;
+            }
+            h = (h + 1) & (kPickSlots - 1);
+        }
+    }
+    __syncthreads();
+    // arg-max of (count, smaller root): count in the high word, ~root in the low
+    unsigned long long best = 0;
+    for (int i = threadIdx.x; i < kPickSlots; i += kPickThreads)
+        if (cnts[i]) {
+            const unsigned long long k = ((unsigned long long)cnts[i] << 32) | (uint32_t)(~(uint32_t)keys[i]);
+            best = k > best ? k : best;
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off);
+        best = o > best ? o : best;
+    }
+    if (lane_id() == 0) wbest[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < kPickThreads / 64; ++w) best = wbest[w] > best ? wbest[w] : best;
+        const uint32_t cnt = (uint32_t)(best >> 32);
+        *gflag = cnt >= min_count ? (int32_t)(~(uint32_t)(best & 0xffffffffull)) : -1;
+    }
+}
+
+// Bitmap of the tree of *gflag (nothing if it is -1): bit x is set iff
+// parent[x] is that tree's root, or x is the root.  Run right after a flatten,
+// with no hook in flight, so a set bit means x is in that tree; a vertex left
+// short of its root by the flatten's walk bound simply keeps a clear bit.
+// One wave covers 64 consecutive vertices and writes two words.
+__global__ __launch_bounds__(kBlock) void giant_bits_kernel(const int32_t* __restrict__ parent, int32_t n,
+                                                            const int32_t* __restrict__ gflag,
+                                                            uint32_t* __restrict__ bits) {
+    const int32_t g = *gflag;
+    if (g < 0) return;
+    bool root;
+    const int32_t gr = find_bounded(parent, g, &root);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t x0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) & ~(int64_t)63; x0 < n; x0 += stride) {
+        const int64_t x = x0 + lane_id();
+        const bool in = x < n && (x == gr || parent[x] == gr);
+        const uint64_t mk = ballot(in);
+        if (lane_id() == 0) *(uint2*)(bits + (x0 >> 5)) = make_uint2((uint32_t)mk, (uint32_t)(mk >> 32));
+    }
 }
 
 // Pointer jumping for the roots hooked in the last pass: each is pointed at
@@ -113,14 +227,22 @@ __global__ __launch_bounds__(kBlock) void sv_shortcut_kernel(int32_t* parent, co
 
 // One block: totals[0] = sum of the per-segment survivor counts, totals[1] =
 // sum of the per-segment hook counts, totals[3] = the hook counts of segments
-// seg_lo .. nseg-1 only (the roots hooked after the last full flatten).
+// seg_lo .. nseg-1 only (the roots hooked after the last full flatten);
+// totals[7..9] = the sums of the segments' atomics, chase reads and edges
+// dropped by the bitmap.
 constexpr int kTotThreads = 1024;
 __global__ __launch_bounds__(kTotThreads) void sv_totals_kernel(const uint32_t* __restrict__ hooked_count,
                                                                 const uint32_t* __restrict__ kept_count, int32_t nseg,
-                                                                int32_t seg_lo, unsigned long long* __restrict__ totals) {
+                                                                int32_t seg_lo, const uint32_t* __restrict__ segstat,
+                                                                unsigned long long* __restrict__ totals) {
     constexpr int W = kTotThreads / 64;
-    __shared__ unsigned long long red[3][W];
-    unsigned long long sk = 0, sh = 0, sf = 0;
+    __shared__ unsigned long long red[6][W];
+    unsigned long long sk = 0, sh = 0, sf = 0, s0 = 0, s1 = 0, s2 = 0;
+    for (int i = threadIdx.x; i < nseg; i += kTotThreads) {
+        s0 += segstat[3 * i];
+        s1 += segstat[3 * i + 1];
+        s2 += segstat[3 * i + 2];
+    }
     // four independent loads in flight per thread
     for (int i0 = threadIdx.x; i0 < nseg; i0 += 4 * kTotThreads) {
         uint32_t a[4], c[4];
@@ -141,19 +263,29 @@ __global__ __launch_bounds__(kTotThreads) void sv_totals_kernel(const uint32_t* 
         sk += __shfl_xor(sk, off);
         sh += __shfl_xor(sh, off);
         sf += __shfl_xor(sf, off);
+        s0 += __shfl_xor(s0, off);
+        s1 += __shfl_xor(s1, off);
+        s2 += __shfl_xor(s2, off);
     }
     if (lane_id() == 0) {
         red[0][threadIdx.x >> 6] = sk;
         red[1][threadIdx.x >> 6] = sh;
         red[2][threadIdx.x >> 6] = sf;
+        red[3][threadIdx.x >> 6] = s0;
+        red[4][threadIdx.x >> 6] = s1;
+        red[5][threadIdx.x >> 6] = s2;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long a = 0, c = 0, f = 0;
-        for (int w = 0; w < W; ++w) { a += red[0][w]; c += red[1][w]; f += red[2][w]; }
-        totals[0] = a;
-        totals[1] = c;
-        totals[3] = f;
+        unsigned long long t[6] = {};
+        for (int w = 0; w < W; ++w)
+            for (int k = 0; k < 6; ++k) t[k] += red[k][w];
+        totals[0] = t[0];
+        totals[1] = t[1];
+        totals[3] = t[2];
+        totals[7] = t[3];   // atomics issued
+        totals[8] = t[4];   // chase reads
+        totals[9] = t[5];   // edges dropped by the largest-tree bitmap
     }
 }
 
@@ -197,20 +329,40 @@ hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s) {
 
 hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
                               SegList out, int32_t seg0, int32_t nblocks, int write_out, int max_link,
-                              int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals, hipStream_t s) {
+                              int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
+                              uint32_t* segstat, const uint32_t* gbits, const int32_t* gflag, hipStream_t s) {
     if (seg0 < 0 || nblocks < 1 || seg0 + nblocks > out.nseg) return hipErrorInvalidValue;
     SegList none{nullptr, 0, 0, nullptr};
-    sv_pass_kernel<true><<<nblocks, kBlock, 0, s>>>(u, v, m, n, seg0, none, parent, out, write_out, max_link, hooked,
-                                                    hooked_count, totals);
+    if (gbits && gflag)
+        sv_pass_kernel<true, true><<<nblocks, kBlock, 0, s>>>(u, v, m, n, seg0, none, parent, out, write_out,
+                                                              max_link, hooked, hooked_count, totals, gbits, gflag,
+                                                              segstat);
+    else
+        sv_pass_kernel<true, false><<<nblocks, kBlock, 0, s>>>(u, v, m, n, seg0, none, parent, out, write_out,
+                                                               max_link, hooked, hooked_count, totals, nullptr,
+                                                               nullptr, segstat);
     return hipGetLastError();
 }
 
 hipError_t launch_sv_pass_seg(SegList in, int32_t seg0, int32_t nblocks, int32_t* parent, SegList out, int write_out,
                               int max_link, int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
-                              hipStream_t s) {
+                              uint32_t* segstat, hipStream_t s) {
     if (seg0 < 0 || nblocks < 1 || seg0 + nblocks > in.nseg || in.nseg > out.nseg) return hipErrorInvalidValue;
-    sv_pass_kernel<false><<<nblocks, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, seg0, in, parent, out, write_out,
-                                                     max_link, hooked, hooked_count, totals);
+    sv_pass_kernel<false, false><<<nblocks, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, seg0, in, parent, out, write_out,
+                                                            max_link, hooked, hooked_count, totals, nullptr, nullptr,
+                                                            segstat);
+    return hipGetLastError();
+}
+
+hipError_t launch_giant_pick(const int32_t* parent, int32_t n, int32_t* gflag, hipStream_t s) {
+    if (n <= 0) return hipErrorInvalidValue;
+    giant_pick_kernel<<<1, kPickThreads, 0, s>>>(parent, n, gflag, kPickSamples / 16);
+    return hipGetLastError();
+}
+
+hipError_t launch_giant_bits(const int32_t* parent, int32_t n, const int32_t* gflag, uint32_t* bits, hipStream_t s) {
+    if (n <= 0) return hipErrorInvalidValue;
+    giant_bits_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(parent, n, gflag, bits);
     return hipGetLastError();
 }
 
@@ -221,8 +373,8 @@ hipError_t launch_sv_shortcut(int32_t* parent, const int32_t* hooked, const uint
 }
 
 hipError_t launch_sv_totals(const uint32_t* hooked_count, const uint32_t* kept_count, int32_t nseg, int32_t seg_lo,
-                            unsigned long long* totals, hipStream_t s) {
-    sv_totals_kernel<<<1, kTotThreads, 0, s>>>(hooked_count, kept_count, nseg, seg_lo, totals);
+                            const uint32_t* segstat, unsigned long long* totals, hipStream_t s) {
+    sv_totals_kernel<<<1, kTotThreads, 0, s>>>(hooked_count, kept_count, nseg, seg_lo, segstat, totals);
     return hipGetLastError();
 }
 

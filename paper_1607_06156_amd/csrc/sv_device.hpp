@@ -28,11 +28,15 @@ constexpr int kEPT = 4;   // edges per thread per tile
 //
 // Survivors go to dst[kept_off ...] (if write_out), roots hooked in this pass
 // to hdst[hook_off ...].  Offsets are block-uniform running counts.
+//
+// Per thread, natom counts the atomics issued and nchase the parent[] reads
+// beyond the two first-level gathers per edge (the walks up the forest), for
+// the byte model; callers that do not report them let the compiler drop them.
 template <class Load>
 __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* parent, int2* __restrict__ dst,
                                            int32_t* __restrict__ hdst, bool write_out, int max_link,
                                            uint32_t& kept_off, uint32_t& hook_off, uint32_t& nlong,
-                                           uint32_t* lds) {
+                                           uint32_t* lds, uint32_t& natom, uint32_t& nchase) {
     for (int64_t t0 = 0; t0 < len; t0 += kBlock * kEPT) {
         int32_t a[kEPT], c[kEPT], pa[kEPT], pc[kEPT];
         bool valid[kEPT];
@@ -78,6 +82,7 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
             for (int k = 0; k < kEPT; ++k) {
                 if (mva[k]) pa[k] = parent[a[k]];
                 if (mvc[k]) pc[k] = parent[c[k]];
+                nchase += (uint32_t)mva[k] + (uint32_t)mvc[k];
             }
         }
         bool keep[kEPT], hk[kEPT];
@@ -103,6 +108,7 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
                 const int32_t lo = ra < rc ? ra : rc;
                 const int32_t hi = ra < rc ? rc : ra;
                 const int32_t old = atomic_min_agent(&parent[hi], lo);   // hook the larger root
+                ++natom;
                 if (old == hi) {           // hi was a root: the two trees are joined
                     hk[k] = true;
                     hroot[k] = hi;
@@ -116,6 +122,7 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
                 bool root_a, root_c;
                 ra = find_bounded(parent, old, &root_a);
                 rc = find_bounded(parent, lo, &root_c);
+                nchase += 2;   // at least one read each (deeper walks are not counted)
                 if (!(root_a && root_c)) {   // keep the pair still to be joined, as ancestors
                     ++nlong;
                     if (ra != rc) {

@@ -100,9 +100,9 @@ def test_batched_from_a_second_process():
 def test_concurrent_calls_from_threads():
     """Four host threads, each on its own stream, call the library at once:
     three label single graphs (a different route each call), one labels a
-    batch.  The single-graph calls take stream-ordered scratch from the pool
-    (no lock); the batch uses the cached workspace under its lock.  Every
-    result is exact and each thread's error slot stays its own."""
+    batch.  Two of the single-graph threads take stream-ordered scratch from
+    the pool (no lock), the third and the batch the cached workspace under its
+    lock.  Every result is exact and each thread's error slot stays its own."""
     import threading
     graphs = [gen.workload("rmat16"), gen.gnm(200_000, 300_000, seed=3), gen.grid(400, 0.6, seed=4)]
     expects = [oracle_labels(g) for g in graphs]
@@ -120,7 +120,8 @@ def test_concurrent_calls_from_threads():
                         exp = bexp
                     else:
                         g = graphs[k]
-                        lab = ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route=route)
+                        lab = ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route=route,
+                                         scratch="pool" if k < 2 else "cached")
                         exp = expects[k]
                     s.synchronize()
                     if not np.array_equal(lab.cpu().numpy(), exp):
@@ -151,9 +152,9 @@ def test_scratch_modes_exact():
         expect = oracle_labels(g)
         for route in ("sv", "sv-theta", "heuristic", "bfs+sv"):
             say(f"[gpu] scratch modes {g.name} {route}")
-            assert_labels_equal(ccmi.label(u, v, g.n, route=route), expect, f"{g.name}/{route}/pool")
-            assert_labels_equal(ccmi.label(u, v, g.n, route=route, scratch="cached"), expect,
-                                f"{g.name}/{route}/cached")
+            assert_labels_equal(ccmi.label(u, v, g.n, route=route, scratch="pool"), expect,
+                                f"{g.name}/{route}/pool")
+            assert_labels_equal(ccmi.label(u, v, g.n, route=route), expect, f"{g.name}/{route}/cached")
             size = ccmi.workspace_size(g.m, g.n, route)
             ws = torch.empty(size, dtype=torch.uint8, device="cuda")
             assert_labels_equal(ccmi.label(u, v, g.n, route=route, workspace=ws), expect,

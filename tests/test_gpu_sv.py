@@ -154,3 +154,30 @@ def test_pass_cap_reports_internal_error():
         ccmi.label(u, v, n, route="sv", max_passes=1)
     assert ei.value.code == ccmi.CC_EINTERNAL
     assert torch.all(ccmi.label(u, v, n, route="sv") == 0)
+
+
+@pytest.mark.parametrize("route", ROUTES)
+@pytest.mark.parametrize("name,drops", [("rmat18", True), ("rmat18noisy", True), ("grid2048", None),
+                                        ("plcomp4m", False)])
+def test_largest_tree_bitmap(route, name, drops):
+    """Lists long enough for a chunked first pass (m >= 2^22): after each
+    flatten the largest tree's bitmap lets the next chunk drop the edges
+    inside it.  R-MAT graphs drop most of their later chunks that way; a
+    forest of small components has no tree holding 1/16 of the vertices and
+    drops nothing.  Labels are exact either way, and the byte counters add
+    up (every atomic issued is a hook, a failed hook or a retry)."""
+    if name == "grid2048":
+        g = gen.grid(2048, 0.7, seed=5)
+    elif name == "plcomp4m":
+        g = gen.plcomp(4_000_000, seed=6)
+    else:
+        g = gen.workload(name)
+    lab, st = run(g, route, stats=True)
+    assert_labels_equal(lab, oracle_labels(g), f"{name}/{route}")
+    say(f"   dropped={st['giant_dropped']} of m={g.m} atomics={st['sv_atomics']} hooks={st['hooks_total']} "
+        f"chase={st['sv_chase_reads']} ms={st['ms_total']:.3f}")
+    if drops is True:
+        assert st["giant_dropped"] > g.m // 2
+    elif drops is False:
+        assert st["giant_dropped"] == 0
+    assert st["sv_atomics"] >= st["hooks_total"]
