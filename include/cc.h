@@ -170,6 +170,21 @@ int cc_label(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* 
 int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream,
                 const cc_options* opt, cc_stats* stats);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): cc_label on the plain SV
+ * route (R1) that allocates nothing, neither device nor host memory.  Its
+ * device scratch is a fixed array of CC_NOALLOC_SCRATCH_BYTES inside the
+ * library's code object, one copy per GPU, held from load until the process
+ * ends; readbacks use the calling thread's stack.  Arguments, outputs,
+ * errors and synchrony are those of cc_label.  Limit: m edges need
+ * cc_workspace_size(m, n, CC_ROUTE_SV) <= CC_NOALLOC_SCRATCH_BYTES, which
+ * holds for every m up to 3 300 000 (any n); a larger m returns CC_EINVAL
+ * before any device work.  Every call on one GPU uses that GPU's one array:
+ * calls that overlap on one GPU (from several threads or streams) race and
+ * must not be made. */
+#define CC_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+int cc_label_noalloc(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream);
+
 /* Label G independent graphs in one call (one persistent launch for the
  * SV iteration over all of them).
  *  u, v       device, int32: graph g owns edges [edge_off[g], edge_off[g+1]);

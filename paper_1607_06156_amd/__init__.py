@@ -127,6 +127,7 @@ def lib():
             "cc_release_workspace": (ctypes.c_int, []),
             "cc_workspace_size": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
             "cc_shutdown": (ctypes.c_int, []),
+            "cc_label_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name, None)
@@ -202,6 +203,20 @@ def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tenso
                            ctypes.byref(st) if stats else None)
     _check(rc)
     return (out, st.to_dict()) if stats else out
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def label_noalloc(u: torch.Tensor, v: torch.Tensor, n: int, out: torch.Tensor):
+    """cc_label_noalloc: plain SV labels with no allocation (scratch is the
+    library's fixed per-GPU array; out must be given)."""
+    m = int(u.numel())
+    if int(v.numel()) != m:
+        raise ValueError("u and v differ in length")
+    _check(lib().cc_label_noalloc(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n,
+                                  _dev(out, torch.int32, "labels"), _stream()))
+    return out
 
 
 def label_batched(u, v, edge_off, vert_off, out=None, tile_edges: int = 0, max_link: int = 0,

@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     for must in ["cc_label", "cc_label_ex", "cc_label_batched", "cc_label_batched_ex", "cc_router_load",
                  "cc_last_error", "cc_version", "cc_degree", "cc_degree_histograms", "cc_powerlaw_ks", "cc_csr",
                  "cc_bfs", "cc_bfs_filter", "cc_mlp_forward", "cc_mlp_sgd_step", "cc_workspace_size",
-                 "cc_release_workspace", "cc_shutdown"]:
+                 "cc_release_workspace", "cc_shutdown",
+                 "cc_label_noalloc"]:
         assert must in names
 
 
