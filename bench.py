@@ -82,6 +82,9 @@ def main():
                     help="skip the batched (batch4096 vs per-graph launches) and router-vs-heuristic legs")
     ap.add_argument("--router-graphs", type=int, default=200,
                     help="held-out graphs of the router-vs-heuristic leg")
+    ap.add_argument("--tuples", default="",
+                    help="comma-separated workloads: time Algorithm 1 with radix sorts (cc_label_tuples) against "
+                         "the atomic-hooking SV route, one JSON line each, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,6 +104,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.tuples:
+        for name in args.tuples.split(","):
+            print(json.dumps(bench_tuples(name)), flush=True)
+        return
     if args.config.startswith("batch"):
         print(json.dumps(bench_batched(args, args.config, args.steps, args.warmup)), flush=True)
         return
@@ -202,6 +209,41 @@ def main():
         rec["batched_batch4096"]["blocks"] = b["config"]["blocks"]
         rec["router_vs_heuristic"] = router_leg(args)
     print(json.dumps(rec), flush=True)
+
+
+def bench_tuples(name):
+    """Algorithm 1 as the paper runs it (tuple array, four radix sorts per
+    iteration) against the atomic-hooking SV route on one workload: time,
+    iterations and the share of the time spent sorting (Section V,
+    Performance Anatomy).  Labels of the two are compared element by element."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1607_06156_amd as ccmi
+    g = gen.workload(name)
+    u = torch.from_numpy(g.u).cuda()
+    v = torch.from_numpy(g.v).cuda()
+    lab_t, st = ccmi.label_tuples(u, v, g.n)              # first call also sizes the workspace
+    torch.cuda.synchronize()
+    lab_t, st = ccmi.label_tuples(u, v, g.n, out=lab_t)
+    _, sv_sec, sts = time_route(ccmi, torch, u, v, g.n, "sv", 3, 1, profile=True)
+    lab_s = ccmi.label(u, v, g.n, route="sv")
+    exact = bool(torch.equal(lab_t, lab_s))
+    sv_sort_free = sts[-1]
+    rec = {"workload": f"{name}: {WORKLOAD_DESC.get(name, name)}", "n": g.n, "m": g.m,
+           "tuples": st["tuples"], "iterations": st["iterations"], "sorts": st["sorts"],
+           "passes_per_sort": st["passes_per_sort"], "tuples_ms": round(st["ms_total"], 3),
+           "tuples_sort_ms": round(st["ms_sort"], 3), "sort_share": round(st["ms_sort"] / st["ms_total"], 4),
+           "sv_ms": round(sv_sec * 1e3, 3), "sv_passes": sv_sort_free["sv_passes"],
+           "sv_kernel_ms": {ccmi.KERNEL_CLASSES[i]: round(float(x), 3)
+                            for i, x in enumerate(sv_sort_free["kernel_ms"]) if x},
+           "labels_identical": exact}
+    log(f"[bench] tuples {name}: {st['ms_total']:.1f} ms ({st['iterations']} iterations, sorts "
+        f"{100 * st['ms_sort'] / st['ms_total']:.1f} %) against SV {sv_sec * 1e3:.2f} ms; identical={exact}")
+    del u, v, lab_t, lab_s
+    torch.cuda.empty_cache()
+    return rec
 
 
 def oracle_batch(b, workers):

@@ -170,6 +170,50 @@ int cc_label(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* 
 int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream,
                 const cc_options* opt, cc_stats* stats);
 
+/* Arbitrary 64-bit vertex ids (Section III-B relabels the ids of a graph to
+ * [0, |V|) before its BFS; Section V treats every id as a 64-bit integer).
+ *  u, v       device, int64[m]: edge i joins u[i] and v[i]; any 64-bit value
+ *             is an id (INT64_MIN included), repeats and self-loops allowed.
+ *  n_max      an upper bound on the number of distinct ids (<= 0: 2m, the
+ *             most m edges can have); at most 2^30.  Sizes the device hash
+ *             table (2 n_max slots rounded up to a power of two, 8 bytes each)
+ *             and bounds the outputs.
+ *  ids        device, int64[n_max], written: each distinct id once, in an
+ *             unspecified order (it may differ between calls).
+ *  labels     device, int64[n_max], written: labels[i] = the smallest id of
+ *             the component of ids[i].
+ *  n_out      host: the number of distinct ids (entries written).
+ * The ids are compacted to [0, n) on the device (hash table + scan), the
+ * compact graph is labelled like cc_label (route from opt, as cc_label_ex),
+ * and the labels are mapped back to original ids.  Scratch is the cached
+ * per-device workspace (calls serialise on it; opt->workspace must be NULL).
+ * Errors: CC_EINVAL (m < 0, NULL pointers, n_max above 2^30, more distinct
+ * ids than n_max: outputs undefined), CC_ENOMEM, CC_EHIP. */
+int cc_label64(const int64_t* u, const int64_t* v, int64_t m, int64_t n_max, int64_t* ids, int64_t* labels,
+               int64_t* n_out, void* stream);
+int cc_label64_ex(const int64_t* u, const int64_t* v, int64_t m, int64_t n_max, int64_t* ids, int64_t* labels,
+                  int64_t* n_out, void* stream, const cc_options* opt, cc_stats* stats);
+
+/* Algorithm 1 as the paper runs it (Section III-A.2, with the sorts of
+ * Section III-A.3): the tuple array <p, q, r>, grouped by radix sorts four
+ * times per iteration, with the pointer-doubling temporary tuples; no
+ * completed partitions are set aside.  An ablation beside the atomic-hooking
+ * SV of cc_label, to measure the share of time the sorts take (Section V,
+ * Performance Anatomy).  Same arguments, result and errors as cc_label
+ * (n + 2m + n must stay below 2^32); scratch is the cached per-device
+ * workspace, about 32 bytes per tuple.  st (host, may be NULL) receives: */
+typedef struct cc_tuple_stats {
+    int32_t iterations;       /* iterations of Algorithm 1 until no partition changed */
+    int32_t sorts;            /* radix sorts (4 per iteration) */
+    int32_t passes_per_sort;  /* 8-bit digit passes of each sort (the key is two ids) */
+    int32_t reserved;
+    int64_t tuples;           /* n + 2m */
+    double ms_sort;           /* device time of the sorts */
+    double ms_total;          /* whole call, host clock */
+} cc_tuple_stats;
+int cc_label_tuples(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream,
+                    cc_tuple_stats* st);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): cc_label on the plain SV
  * route (R1) that allocates nothing, neither device nor host memory.  Its

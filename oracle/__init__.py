@@ -13,6 +13,11 @@ What it computes (each function cites the passage it follows):
 * ``labels_bfs_brute``-- the same labels by one BFS per component in ascending
                          id order (Section I: "a single traversal is necessary for
                          each connected component"); pure Python, tiny graphs.
+* ``labels64``        -- arbitrary 64-bit ids: relabel to [0, |V|) in sorted
+                         order (Section III-B relabelling; Section V: 64-bit
+                         ids), union-find, labels mapped back to original ids.
+* ``labels64_brute``  -- the same by BFS over a dict adjacency, seeds in
+                         ascending id order; pure Python, tiny graphs.
 * ``alg1``            -- the tuple-array algorithm of Section III-A (Algorithm 1)
                          step by step in the paper's notation, small graphs.
 * ``degree``          -- degree distribution (Section III-B, Algorithm 2 line
@@ -112,3 +117,42 @@ def labels_bfs_brute(u, v, n: int) -> np.ndarray:
 def component_count(labels: np.ndarray) -> int:
     labels = np.asarray(labels)
     return int(np.count_nonzero(labels == np.arange(labels.shape[0], dtype=labels.dtype)))
+
+
+def labels64(u, v):
+    """Arbitrary 64-bit ids (Section III-B relabels the vertices to [0, |V|);
+    Section V: ids are 64-bit integers).  The distinct endpoint ids, sorted,
+    become 0 .. n-1, so the relabelling keeps the order and the smallest
+    compact id of a component is its smallest original id.  Returns (ids,
+    labels): each distinct id once in ascending order, with the smallest id of
+    its component."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    ids = np.unique(np.concatenate([u, v]))
+    cu = np.searchsorted(ids, u).astype(np.int32)
+    cv = np.searchsorted(ids, v).astype(np.int32)
+    lab = labels_uf(cu, cv, int(ids.shape[0]))
+    return ids, ids[lab]
+
+
+def labels64_brute(u, v):
+    """labels64 by one BFS per component over a dict adjacency, seeds taken
+    in ascending id order (Section I)."""
+    adj = {}
+    for a, b in zip(np.asarray(u).tolist(), np.asarray(v).tolist()):
+        adj.setdefault(a, []).append(b)
+        adj.setdefault(b, []).append(a)
+    lab = {}
+    for s in sorted(adj):
+        if s in lab:
+            continue
+        lab[s] = s
+        q = deque([s])
+        while q:
+            x = q.popleft()
+            for y in adj[x]:
+                if y not in lab:
+                    lab[y] = s
+                    q.append(y)
+    ids = np.asarray(sorted(adj), dtype=np.int64)
+    return ids, np.asarray([lab[x] for x in ids.tolist()], dtype=np.int64)

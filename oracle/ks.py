@@ -110,13 +110,18 @@ def mle_alpha(dmin, mean_log, iters: int = 200):
     return np.where(at_hi, ALPHA_HI, 0.5 * (lo + hi))
 
 
-def ks_distance(vals: np.ndarray, cnts: np.ndarray, dmin: int, alpha: float) -> float:
-    """D(dmin) for a given alpha; vals sorted ascending, all >= dmin."""
+def ks_distance(vals: np.ndarray, cnts: np.ndarray, dmin: int, alpha: float, observed_only: bool = False) -> float:
+    """D(dmin) for a given alpha; vals sorted ascending, all >= dmin.
+
+    observed_only: the other reading of step 2, with the gap taken only at
+    the observed degrees d_j (not on the integers in between)."""
     N = float(cnts.sum())
     S = np.cumsum(cnts) / N                       # S(d_j)
     z0 = hurwitz_zeta(alpha, float(dmin))
     F_at = 1.0 - hurwitz_zeta(alpha, vals + 1.0) / z0          # model CDF at d_j
     dev = np.abs(S - F_at)
+    if observed_only:
+        return float(np.max(dev))
     if vals.shape[0] > 1:
         # just before the next observed value: S still S(d_j), model at d_{j+1} - 1
         F_before = 1.0 - hurwitz_zeta(alpha, vals[1:].astype(np.float64)) / z0
@@ -125,12 +130,14 @@ def ks_distance(vals: np.ndarray, cnts: np.ndarray, dmin: int, alpha: float) -> 
     return float(np.max(dev))
 
 
-def fit(vals, cnts):
+def fit(vals, cnts, observed_only: bool = False):
     """Clauset fit over all candidate cutoffs.
 
     vals: distinct positive degrees (any order); cnts: vertices per degree.
     Returns dict(ks, alpha, dmin, ntail, candidates).  ks = inf when no
     candidate cutoff exists (the graph is then never classed scale-free).
+    observed_only selects the reading of step 2 that takes the gap at the
+    observed degrees only (see ks_distance).
     """
     vals = np.asarray(vals, np.int64)
     cnts = np.asarray(cnts, np.int64)
@@ -151,7 +158,7 @@ def fit(vals, cnts):
     alphas = mle_alpha(vals[cand], tail_s[cand] / tail_n[cand])
     best = None
     for i, a in zip(cand.tolist(), alphas.tolist()):
-        D = ks_distance(vals[i:], cnts[i:], int(vals[i]), a)
+        D = ks_distance(vals[i:], cnts[i:], int(vals[i]), a, observed_only)
         if best is None or D < best[0]:
             best = (D, a, int(vals[i]), int(tail_n[i]))
     return dict(ks=best[0], alpha=best[1], dmin=best[2], ntail=best[3], candidates=int(cand.shape[0]))

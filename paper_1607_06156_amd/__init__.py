@@ -81,6 +81,12 @@ class Stats(ctypes.Structure):
         return d
 
 
+class TupleStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("sorts", ctypes.c_int32), ("passes_per_sort", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tuples", ctypes.c_int64), ("ms_sort", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
 class BatchStats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("tile_edges", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("max_link", ctypes.c_int32), ("total_edges", ctypes.c_int64),
@@ -128,6 +134,13 @@ def lib():
             "cc_workspace_size": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
             "cc_shutdown": (ctypes.c_int, []),
             "cc_label_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP]),
+            "cc_label_tuples": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP,
+                                               ctypes.POINTER(TupleStats)]),
+            "cc_label64": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP,
+                                          ctypes.POINTER(ctypes.c_int64), _VP]),
+            "cc_label64_ex": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP,
+                                             ctypes.POINTER(ctypes.c_int64), _VP, ctypes.POINTER(Options),
+                                             ctypes.POINTER(Stats)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name, None)
@@ -203,6 +216,41 @@ def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tenso
                            ctypes.byref(st) if stats else None)
     _check(rc)
     return (out, st.to_dict()) if stats else out
+
+
+def label_tuples(u: torch.Tensor, v: torch.Tensor, n: int, out: torch.Tensor | None = None):
+    """Algorithm 1 with radix sorts (cc_label_tuples): (labels, stats dict)."""
+    m = int(u.numel())
+    if int(v.numel()) != m:
+        raise ValueError("u and v differ in length")
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=u.device)
+    st = TupleStats()
+    _check(lib().cc_label_tuples(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n,
+                                 _dev(out, torch.int32, "labels"), _stream(), ctypes.byref(st)))
+    return out, {k: getattr(st, k) for k, _ in TupleStats._fields_ if k != "reserved"}
+
+
+def label64(u: torch.Tensor, v: torch.Tensor, n_max: int = 0, route=None, stats: bool = False):
+    """Arbitrary 64-bit ids: (ids, labels) as int64 device tensors, each
+    distinct endpoint id once (unspecified order) with the smallest id of its
+    component (cc_label64)."""
+    m = int(u.numel())
+    if int(v.numel()) != m:
+        raise ValueError("u and v differ in length")
+    cap = int(n_max) if n_max > 0 else 2 * m
+    ids = torch.empty(max(cap, 1), dtype=torch.int64, device=u.device)
+    labels = torch.empty(max(cap, 1), dtype=torch.int64, device=u.device)
+    n = ctypes.c_int64(0)
+    opt = Options()
+    lib().cc_default_options(ctypes.byref(opt))
+    opt.route = _ROUTE_ARG[route] if not isinstance(route, int) else route
+    st = Stats()
+    _check(lib().cc_label64_ex(_dev(u, torch.int64, "u"), _dev(v, torch.int64, "v"), m, int(n_max),
+                               _dev(ids, torch.int64, "ids"), _dev(labels, torch.int64, "labels"),
+                               ctypes.byref(n), _stream(), ctypes.byref(opt), ctypes.byref(st) if stats else None))
+    k = int(n.value)
+    return (ids[:k], labels[:k], st.to_dict()) if stats else (ids[:k], labels[:k])
 
 
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024

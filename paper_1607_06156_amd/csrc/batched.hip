@@ -173,23 +173,43 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
         if (threadIdx.x == 0) sh_g = graph_of(A.edge_off, A.G, e0);
         __syncthreads();
         int32_t g = sh_g;
-        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
-            const int64_t e = e0 + i;
-            const int32_t x = A.u[e], y = A.v[e];
-            while (A.edge_off[g + 1] <= e) ++g;
-            const int64_t v0 = A.vert_off[g];
-            const int64_t nl = A.vert_off[g + 1] - v0;
-            if (x < 0 || y < 0 || (int64_t)x >= nl || (int64_t)y >= nl) {
-                ++bad;
-                return false;
+        // All of the thread's edge reads go out first (non-temporal: the
+        // list is read once); its edges arrive in increasing order, so g only
+        // walks forward.  Indices past the tile's end read its first edge.
+        auto loader = [&](int64_t t0, int32_t* a, int32_t* c, bool* valid) {
+            int64_t e[kEPT];
+            bool in[kEPT];
+            int32_t x[kEPT], y[kEPT];
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                const int64_t i = t0 + threadIdx.x + (int64_t)k * kBlock;
+                in[k] = i < len;
+                e[k] = e0 + (in[k] ? i : 0);
             }
-            *a = (int32_t)(v0 + x);
-            *c = (int32_t)(v0 + y);
-            return true;
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                x[k] = __builtin_nontemporal_load(A.u + e[k]);
+                y[k] = __builtin_nontemporal_load(A.v + e[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                valid[k] = false;
+                if (!in[k]) continue;
+                while (A.edge_off[g + 1] <= e[k]) ++g;
+                const int64_t v0 = A.vert_off[g];
+                const int64_t nl = A.vert_off[g + 1] - v0;
+                if (x[k] < 0 || y[k] < 0 || (int64_t)x[k] >= nl || (int64_t)y[k] >= nl) {
+                    ++bad;
+                    continue;
+                }
+                a[k] = (int32_t)(v0 + x[k]);
+                c[k] = (int32_t)(v0 + y[k]);
+                valid[k] = true;
+            }
         };
         uint32_t kept = 0, hk = 0;
         if (len > 0)
-            sv_segment(len, load, A.parent, A.buf0 + t * kTileE, A.hooked + t * kTileE, true, A.max_link, kept, hk,
+            sv_segment(len, loader, A.parent, A.buf0 + t * kTileE, A.hooked + t * kTileE, true, A.max_link, kept, hk,
                        nlong, lds, natom, nchase);
         if (threadIdx.x == 0) {
             A.cnt0[t] = kept;
@@ -309,13 +329,17 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
             uint32_t kept = 0, hk = 0;
             if (len) {
                 const int2* src = in + t * kTileE;
-                auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
-                    const int2 e = src[i];
-                    *a = e.x;
-                    *c = e.y;
-                    return true;
+                auto loader = [&](int64_t t0, int32_t* a, int32_t* c, bool* valid) {
+#pragma unroll
+                    for (int k = 0; k < kEPT; ++k) {
+                        const int64_t i = t0 + threadIdx.x + (int64_t)k * kBlock;
+                        valid[k] = i < (int64_t)len;
+                        const int2 e = src[valid[k] ? i : 0];
+                        a[k] = e.x;
+                        c[k] = e.y;
+                    }
                 };
-                sv_segment((int64_t)len, load, A.parent, out + t * kTileE, A.hooked + t * kTileE, true, A.max_link,
+                sv_segment((int64_t)len, loader, A.parent, out + t * kTileE, A.hooked + t * kTileE, true, A.max_link,
                            kept, hk, nlong, lds, natom, nchase);
             }
             if (threadIdx.x == 0) {

@@ -13,6 +13,7 @@
 namespace ccmi {
 
 int fail(int code, const char* fmt, ...);
+void clear_error();   // empties this thread's message
 int hip_fail(hipError_t e, const char* what);
 
 // workspace slots (grow-only device buffers, one set per device)
@@ -35,6 +36,11 @@ enum WsSlot {
     WS_HISTOUT,      // reduced histograms, tail count, arg-max key
     WS_BATCH,        // batched-mode tables
     WS_GIANT,        // bitmap of the largest tree during a chunked first pass
+    WS_R64_KEYS,     // 64-bit relabel: hash table keys, then the compact labels
+    WS_R64_CID,      // 64-bit relabel: compact id of each slot
+    WS_R64_EDGES,    // 64-bit relabel: edges as slots, then as compact ids
+    WS_R64_FLAGS,    // 64-bit relabel: flags and the distinct-id count
+    WS_R64_SCAN,     // 64-bit relabel: scan tile sums
     WS_NSLOTS
 };
 

@@ -70,33 +70,61 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
         if (len > out.cap) len = out.cap;
         if (len < 0) len = 0;
         const bool filt = FILT && *gflag >= 0;
-        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
-            // the edge list is read once: keep it from displacing parent[]
-            // and the bitmap in the caches
-            *a = __builtin_nontemporal_load(u + base + i);
-            *c = __builtin_nontemporal_load(v + base + i);
-            if ((uint32_t)*a >= (uint32_t)n || (uint32_t)*c >= (uint32_t)n) {
-                ++bad;
-                return false;
+        // Every read of a tile goes out before any is used: the edges (read
+        // once, with non-temporal loads that keep them from displacing
+        // parent[] and the bitmap in the caches), then the bit probes.
+        // Indices past the end read edge 0 of the segment and are dropped.
+        auto loader = [&](int64_t t0, int32_t* a, int32_t* c, bool* valid) {
+            int64_t idx[kEPT];
+            bool in[kEPT];
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                const int64_t i = t0 + threadIdx.x + (int64_t)k * kBlock;
+                in[k] = i < len;
+                idx[k] = base + (in[k] ? i : 0);
             }
-            if (filt && ((gbits[*a >> 5] >> (*a & 31)) & (gbits[*c >> 5] >> (*c & 31)) & 1u)) {
-                ++nfilt;
-                return false;
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                a[k] = __builtin_nontemporal_load(u + idx[k]);
+                c[k] = __builtin_nontemporal_load(v + idx[k]);
             }
-            return true;
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                const bool ok = (uint32_t)a[k] < (uint32_t)n && (uint32_t)c[k] < (uint32_t)n;
+                bad += (in[k] && !ok) ? 1u : 0u;
+                valid[k] = in[k] && ok;
+            }
+            if (filt) {
+                uint32_t wa[kEPT], wc[kEPT];
+#pragma unroll
+                for (int k = 0; k < kEPT; ++k) {
+                    wa[k] = gbits[(uint32_t)(valid[k] ? a[k] : 0) >> 5];
+                    wc[k] = gbits[(uint32_t)(valid[k] ? c[k] : 0) >> 5];
+                }
+#pragma unroll
+                for (int k = 0; k < kEPT; ++k) {
+                    const bool both = valid[k] && ((wa[k] >> (a[k] & 31)) & (wc[k] >> (c[k] & 31)) & 1u);
+                    nfilt += both ? 1u : 0u;
+                    valid[k] = valid[k] && !both;
+                }
+            }
         };
-        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds, natom,
+        sv_segment(len, loader, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds, natom,
                    nchase);
     } else {
         const int2* src = in.buf + (int64_t)b * in.cap;
         const int64_t len = in.count[b];
-        auto load = [&](int64_t i, int32_t* a, int32_t* c) -> bool {
-            const int2 e = src[i];
-            *a = e.x;
-            *c = e.y;
-            return true;
+        auto loader = [&](int64_t t0, int32_t* a, int32_t* c, bool* valid) {
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                const int64_t i = t0 + threadIdx.x + (int64_t)k * kBlock;
+                valid[k] = i < len;
+                const int2 e = src[valid[k] ? i : 0];
+                a[k] = e.x;
+                c[k] = e.y;
+            }
         };
-        sv_segment(len, load, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds, natom,
+        sv_segment(len, loader, parent, dst, hdst, write_out != 0, max_link, kept_off, hook_off, nlong, lds, natom,
                    nchase);
     }
     // per-block results (no global atomics on the fast path)

@@ -9,8 +9,12 @@ namespace ccmi {
 
 constexpr int kEPT = 4;   // edges per thread per tile
 
-// Process `len` edges of this block.  load(i, &a, &c) fetches edge i of the
-// segment as two vertex ids and returns false to skip it.
+// Process `len` edges of this block.  loader(t0, a, c, valid) fills this
+// thread's kEPT edges of the tile that starts at edge t0 of the segment
+// (edge t0 + threadIdx.x + k * kBlock in slot k; valid[k] false for an edge
+// past the end or one to skip).  A loader that issues all of its reads
+// before it uses any lets them overlap: each edge's reads then cost one
+// memory round trip per tile instead of one per edge.
 //
 // Per edge: find both roots; if they differ, hook the larger root below the
 // smaller with atomicMin.  The edge is finished (dropped) when its roots
@@ -32,19 +36,15 @@ constexpr int kEPT = 4;   // edges per thread per tile
 // Per thread, natom counts the atomics issued and nchase the parent[] reads
 // beyond the two first-level gathers per edge (the walks up the forest), for
 // the byte model; callers that do not report them let the compiler drop them.
-template <class Load>
-__device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* parent, int2* __restrict__ dst,
+template <class Loader>
+__device__ __forceinline__ void sv_segment(int64_t len, Loader loader, int32_t* parent, int2* __restrict__ dst,
                                            int32_t* __restrict__ hdst, bool write_out, int max_link,
                                            uint32_t& kept_off, uint32_t& hook_off, uint32_t& nlong,
                                            uint32_t* lds, uint32_t& natom, uint32_t& nchase) {
     for (int64_t t0 = 0; t0 < len; t0 += kBlock * kEPT) {
         int32_t a[kEPT], c[kEPT], pa[kEPT], pc[kEPT];
         bool valid[kEPT];
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            const int64_t i = t0 + threadIdx.x + (int64_t)k * kBlock;
-            valid[k] = i < len && load(i, &a[k], &c[k]);
-        }
+        loader(t0, a, c, valid);
         // all first-level gathers before any dependent chase
 #pragma unroll
         for (int k = 0; k < kEPT; ++k) {
@@ -85,17 +85,19 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
                 nchase += (uint32_t)mva[k] + (uint32_t)mvc[k];
             }
         }
-        bool keep[kEPT], hk[kEPT];
+        bool keep[kEPT], hk[kEPT], go[kEPT];
         int2 e[kEPT];
-        int32_t hroot[kEPT];
+        int32_t hroot[kEPT], lo[kEPT], hi[kEPT], old[kEPT];
 #pragma unroll
         for (int k = 0; k < kEPT; ++k) {
             keep[k] = false;
             hk[k] = false;
+            go[k] = false;
             hroot[k] = 0;
+            lo[k] = hi[k] = 0;
             if (!valid[k]) continue;
-            int32_t ra = a[k];
-            int32_t rc = c[k];
+            const int32_t ra = a[k];
+            const int32_t rc = c[k];
             if (cut && (pa[k] != ra || pc[k] != rc)) {   // a find stopped short of a root
                 ++nlong;
                 if (ra != rc) {
@@ -104,24 +106,35 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
                 }
                 continue;
             }
-            for (int tries = 0; ra != rc;) {
-                const int32_t lo = ra < rc ? ra : rc;
-                const int32_t hi = ra < rc ? rc : ra;
-                const int32_t old = atomic_min_agent(&parent[hi], lo);   // hook the larger root
+            go[k] = ra != rc;
+            lo[k] = ra < rc ? ra : rc;
+            hi[k] = ra < rc ? rc : ra;
+        }
+        // first hook attempt of every edge of the thread, all in flight together
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k)
+            if (go[k]) {
+                old[k] = atomic_min_agent(&parent[hi[k]], lo[k]);   // hook the larger root
                 ++natom;
-                if (old == hi) {           // hi was a root: the two trees are joined
+            }
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            if (!go[k]) continue;
+            int32_t o = old[k], l = lo[k], h = hi[k];
+            for (int tries = 1;;) {
+                if (o == h) {              // h was a root: the two trees are joined
                     hk[k] = true;
-                    hroot[k] = hi;
+                    hroot[k] = h;
                     break;
                 }
-                if (++tries >= max_link) {
+                if (tries >= max_link) {
                     keep[k] = true;
-                    e[k] = old > lo ? make_int2(old, hi) : make_int2(lo, hi);
+                    e[k] = o > l ? make_int2(o, h) : make_int2(l, h);
                     break;
                 }
                 bool root_a, root_c;
-                ra = find_bounded(parent, old, &root_a);
-                rc = find_bounded(parent, lo, &root_c);
+                const int32_t ra = find_bounded(parent, o, &root_a);
+                const int32_t rc = find_bounded(parent, l, &root_c);
                 nchase += 2;   // at least one read each (deeper walks are not counted)
                 if (!(root_a && root_c)) {   // keep the pair still to be joined, as ancestors
                     ++nlong;
@@ -131,6 +144,12 @@ __device__ __forceinline__ void sv_segment(int64_t len, Load load, int32_t* pare
                     }
                     break;
                 }
+                if (ra == rc) break;       // joined meanwhile: finished
+                l = ra < rc ? ra : rc;
+                h = ra < rc ? rc : ra;
+                o = atomic_min_agent(&parent[h], l);
+                ++natom;
+                ++tries;
             }
         }
         // wave ballots -> slot prefixes; one block scan of packed (kept | hooks << 16)

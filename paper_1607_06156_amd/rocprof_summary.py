@@ -3,12 +3,15 @@
     python -m paper_1607_06156_amd.rocprof_summary stats DIR [--title T] [--command C]
     python -m paper_1607_06156_amd.rocprof_summary pmc --fetch DIR --write DIR --kernel NAME
         --cls CLASS --copy-mib N [--last K] [--title T] [--command C]
+    python -m paper_1607_06156_amd.rocprof_summary counters DIR [DIR ...] [--title T] [--command C]
 
 `stats` condenses a `--kernel-trace --stats` run (its *_kernel_stats.csv) into
 a table.  `pmc` takes two counter runs (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`,
 each a *_counter_collection.csv) of a program that also ran one plain
 device-to-device copy of N MiB, and converts the kernel's per-dispatch KiB
 into bytes with the factor that makes the copy read and write exactly N MiB.
+`counters` tabulates every counter of one or more `--pmc` runs per kernel:
+dispatches, the sum over them and the average per dispatch.
 
 The pmc summary carries `key: value` lines that bench.py reads back, among
 them the SHA-256 of the kernel's source files: bench.py reports the traffic
@@ -108,6 +111,22 @@ def pmc_per_dispatch(dirname: str, counter: str) -> dict:
     return {k: [v[d] for d in sorted(v)] for k, v in per.items()}
 
 
+def counters_table(dirs) -> str:
+    """kernel x counter: dispatches, total and per-dispatch average."""
+    rows = defaultdict(lambda: defaultdict(lambda: defaultdict(float)))
+    for d in dirs:
+        path = _find(d, "counter_collection.csv")
+        for r in csv.DictReader(open(path)):
+            did = int(r.get("Dispatch_Id") or r.get("Correlation_Id"))
+            rows[(_short(r["Kernel_Name"], True), r["Counter_Name"])][d][did] += float(r["Counter_Value"])
+    lines = ["| kernel | counter | dispatches | total | per dispatch |", "|---|---|---|---|---|"]
+    for (k, c) in sorted(rows):
+        vals = [v for per in rows[(k, c)].values() for v in per.values()]
+        tot = sum(vals)
+        lines.append(f"| {k} | {c} | {len(vals)} | {tot:.6g} | {tot / max(len(vals), 1):.6g} |")
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -125,7 +144,20 @@ def main(argv=None):
     p.add_argument("--last", type=int, default=0, help="average only the kernel's last N dispatches")
     p.add_argument("--title", default="HBM traffic")
     p.add_argument("--command", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--title", default="rocprofv3 counters")
+    c.add_argument("--command", default="")
     a = ap.parse_args(argv)
+    if a.mode == "counters":
+        print(f"# {a.title}\n")
+        if a.command:
+            print("Commands (from the repository root):\n")
+            for cmd in a.command.split(" ;; "):
+                print(f"    {cmd}")
+            print()
+        print(counters_table(a.dirs))
+        return
     if a.mode == "stats":
         print(f"# {a.title}\n")
         if a.command:

@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     for must in ["cc_label", "cc_label_ex", "cc_label_batched", "cc_label_batched_ex", "cc_router_load",
                  "cc_last_error", "cc_version", "cc_degree", "cc_degree_histograms", "cc_powerlaw_ks", "cc_csr",
                  "cc_bfs", "cc_bfs_filter", "cc_mlp_forward", "cc_mlp_sgd_step", "cc_workspace_size",
-                 "cc_release_workspace", "cc_shutdown",
+                 "cc_release_workspace", "cc_shutdown", "cc_label64", "cc_label64_ex", "cc_label_tuples",
                  "cc_label_noalloc"]:
         assert must in names
 
@@ -68,7 +68,8 @@ def test_struct_layouts_match_compiled_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    mirrors = {"cc_options": ccmi.Options, "cc_stats": ccmi.Stats, "cc_batch_stats": ccmi.BatchStats}
+    mirrors = {"cc_options": ccmi.Options, "cc_stats": ccmi.Stats, "cc_batch_stats": ccmi.BatchStats,
+               "cc_tuple_stats": ccmi.TupleStats}
     lines = []
     for cname, py in mirrors.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -135,6 +136,22 @@ def test_workspace_size_and_checks(lib):
     opt.workspace = None
     opt.scratch = 7
     assert L.cc_label_ex(8, 8, 1000, 100, 8, None, ctypes.byref(opt), None) == -1
+
+
+def test_label64_and_tuples_reject_bad_arguments_on_host(lib):
+    import paper_1607_06156_amd as ccmi
+    L = ccmi.lib()
+    n = ctypes.c_int64(-5)
+    assert L.cc_label64(None, None, -1, 0, None, None, ctypes.byref(n), None) == -1
+    assert L.cc_label64(None, None, 0, 0, None, None, ctypes.byref(n), None) == 0 and n.value == 0
+    assert L.cc_label64(8, 8, 10, 1 << 31, 8, 8, ctypes.byref(n), None) == -1     # n_max above 2^30
+    assert b"2^30" in L.cc_last_error()
+    assert L.cc_label64(None, None, 10, 0, 8, 8, ctypes.byref(n), None) == -1     # NULL edges
+    st = ccmi.TupleStats()
+    assert L.cc_label_tuples(None, None, -1, 5, None, None, ctypes.byref(st)) == -1
+    assert L.cc_label_tuples(None, None, 0, 0, None, None, ctypes.byref(st)) == 0
+    assert L.cc_label_tuples(8, 8, 1 << 31, 1 << 30, 8, None, ctypes.byref(st)) == -1   # n + 2m + n >= 2^32
+    assert L.cc_label_noalloc(None, None, -1, 5, None, None) == -1
 
 
 def test_router_weights_file_roundtrip(lib, tmp_path):

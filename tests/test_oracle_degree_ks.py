@@ -194,3 +194,34 @@ def test_planted_sign_error_in_derivative_is_caught():
     h = 1e-5 * s
     fd = (ss.zeta(s + h, q) - ss.zeta(s - h, q)) / (2 * h)
     assert abs(-float(ks.hurwitz_zeta_ds(s, q)) / fd - 1) > 1.0
+
+
+def test_observed_only_reading():
+    """The two readings of the K-S gap: over every integer of [d_min, d_max]
+    (the statistic used) or at the observed degrees only.  The second takes
+    the maximum over a subset, so it never exceeds the first; on a support
+    without gaps the two coincide; across a gap the integer reading also sees
+    the model CDF rise before the next observed degree (worked here by hand:
+    alpha = 2, degrees 1 and 10 with 61 and 39 vertices)."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        vals = np.unique(rng.integers(1, 400, int(rng.integers(3, 40))))
+        cnts = rng.integers(1, 500, vals.shape[0])
+        a = ks.fit(vals, cnts)
+        b = ks.fit(vals, cnts, observed_only=True)
+        if math.isfinite(a["ks"]):
+            assert b["ks"] <= a["ks"] + 1e-15
+    vals = np.arange(1, 60)
+    cnts = np.maximum(1, (1e5 * vals ** -2.2).astype(np.int64))
+    assert ks.fit(vals, cnts)["ks"] == ks.fit(vals, cnts, observed_only=True)["ks"]
+    vals = np.asarray([1, 10])
+    cnts = np.asarray([61, 39])
+    z = ss.zeta(2.0, 1.0)
+    s1, f1 = 0.61, 1.0 / z                                # S(1), P(D <= 1)
+    f9 = 1.0 - ss.zeta(2.0, 10.0) / z                     # P(D <= 9): the model just before 10
+    f10 = 1.0 - ss.zeta(2.0, 11.0) / z
+    d_int = max(abs(s1 - f1), abs(s1 - f9), abs(1.0 - f10))
+    d_obs = max(abs(s1 - f1), abs(1.0 - f10))
+    assert abs(ks.ks_distance(vals, cnts, 1, 2.0) - d_int) < 1e-12
+    assert abs(ks.ks_distance(vals, cnts, 1, 2.0, observed_only=True) - d_obs) < 1e-12
+    assert d_obs < 0.1 < d_int

@@ -244,3 +244,71 @@ def test_pins_accept_correct_variant():
                                 dict(drop_every_kth=7)])
 def test_pins_reject_planted_mistakes(kw):
     assert not _pins_pass(lambda u, v, n: _uf_variant(u, v, n, **kw))
+
+
+# ------------------------------------------------------------ 64-bit ids
+I64_MIN, I64_MAX = np.iinfo(np.int64).min, np.iinfo(np.int64).max
+
+
+def _random_ids64(rng, k):
+    """k distinct 64-bit ids spread over the whole range, extremes included."""
+    pool = set([I64_MIN, I64_MAX, -1, 0, 1])
+    while len(pool) < k + 5:
+        pool.add(int(rng.integers(I64_MIN, I64_MAX, dtype=np.int64)))
+    return np.asarray(rng.permutation(sorted(pool))[:k], dtype=np.int64)
+
+
+def test_labels64_against_brute_force():
+    rng = np.random.default_rng(64)
+    for trial in range(200):
+        k = int(rng.integers(1, 14))
+        ids = _random_ids64(rng, k)
+        m = int(rng.integers(0, 20))
+        a = ids[rng.integers(0, k, m)]
+        b = ids[rng.integers(0, k, m)]
+        got = oracle.labels64(a, b)
+        exp = oracle.labels64_brute(a, b)
+        assert np.array_equal(got[0], exp[0]) and np.array_equal(got[1], exp[1]), trial
+
+
+def test_labels64_reduces_to_dense_labels():
+    """Ids 0 .. n-1 that all occur: the 64-bit labels are the dense ones."""
+    g = gen.gnm(3000, 2500, seed=5)
+    u = np.concatenate([g.u, np.arange(g.n, dtype=np.int32)])    # self-loops make every id occur
+    v = np.concatenate([g.v, np.arange(g.n, dtype=np.int32)])
+    ids, lab = oracle.labels64(u.astype(np.int64), v.astype(np.int64))
+    assert np.array_equal(ids, np.arange(g.n))
+    assert np.array_equal(lab, oracle.labels_uf(u, v, g.n).astype(np.int64))
+
+
+def test_labels64_order_preserving_map_commutes():
+    """An increasing map of the ids maps the labels the same way; a
+    decreasing one turns each component's label into the image of its
+    largest member."""
+    g = gen.rmat(12, 4, seed=6)
+    u, v = g.u.astype(np.int64), g.v.astype(np.int64)
+    ids, lab = oracle.labels64(u, v)
+    f = lambda x: x * 1_000_003 - (1 << 40)                      # increasing, no overflow here
+    ids2, lab2 = oracle.labels64(f(u), f(v))
+    assert np.array_equal(ids2, f(ids)) and np.array_equal(lab2, f(lab))
+    ids3, lab3 = oracle.labels64(-u, -v)                         # decreasing
+    big = {}
+    for x, l in zip(ids.tolist(), lab.tolist()):
+        big[l] = max(big.get(l, x), x)
+    exp = {-x: -big[l] for x, l in zip(ids.tolist(), lab.tolist())}
+    assert all(exp[x] == l for x, l in zip(ids3.tolist(), lab3.tolist()))
+
+
+def test_labels64_planted_mistake_fails():
+    """Numbering the ids in order of first appearance instead of sorted order
+    (a relabel that does not keep the order) labels by the wrong member."""
+    u = np.asarray([50, 7], dtype=np.int64)
+    v = np.asarray([7, 50], dtype=np.int64)
+    order = {50: 0, 7: 1}                                         # first appearance
+    cu = np.asarray([order[x] for x in u.tolist()], np.int32)
+    cv = np.asarray([order[x] for x in v.tolist()], np.int32)
+    lab = oracle.labels_uf(cu, cv, 2)
+    wrong = np.asarray([50, 7], np.int64)[lab]
+    ids, exp = oracle.labels64_brute(u, v)
+    assert not np.array_equal(np.sort(wrong), exp)
+    assert np.array_equal(oracle.labels64(u, v)[1], exp)

@@ -104,3 +104,15 @@ def test_router_weights_save_load_roundtrip(tmp_path):
     (tmp_path / "short.txt").write_text("# two\n1 2\n")
     with pytest.raises(ValueError):
         rt.load(str(tmp_path / "short.txt"))
+
+
+def test_counters_table(tmp_path, capsys):
+    _counters(tmp_path / "a", "TCC_ATOMIC_sum", [(1, "void ccmi::sv_pass_kernel<true, true>(int)", 10.0),
+                                                 (2, "void ccmi::sv_pass_kernel<true, true>(int)", 30.0),
+                                                 (3, "ccmi::giant_pick_kernel(int)", 0.0)])
+    _counters(tmp_path / "b", "SQ_INSTS_VALU_MFMA_MOPS_F32", [(1, "void ccmi::sv_pass_kernel<true, true>(int)", 0.0)])
+    rs.main(["counters", str(tmp_path / "a"), str(tmp_path / "b"), "--title", "t"])
+    out = capsys.readouterr().out
+    assert "| sv_pass_kernel<true, true> | TCC_ATOMIC_sum | 2 | 40 | 20 |" in out
+    assert "| sv_pass_kernel<true, true> | SQ_INSTS_VALU_MFMA_MOPS_F32 | 1 | 0 | 0 |" in out
+    assert "| giant_pick_kernel | TCC_ATOMIC_sum | 1 | 0 | 0 |" in out
