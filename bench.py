@@ -322,9 +322,13 @@ def bench_batched(args, config, steps, warmup):
     log(f"[bench] batched: {sec * 1e3:.2f} ms/step {value / 1e9:.2f} G edges/s passes={st['passes']} "
         f"blocks={st['blocks']} max_link={st['max_link']} pass_ms={st['pass_ms']}")
     kernel_ms = float(np.mean([s["ms_total"] for s in sts]))
-    # the persistent kernel is the only kernel: algorithmic bytes of one launch
-    # (a lower bound: later passes, ~1 % of the edges, are not counted)
-    kbytes = 32.0 * m + 16.0 * n
+    # the persistent kernel is the only kernel: algorithmic bytes of one
+    # launch from its own counts (the single-graph model): identity init
+    # (4 B per vertex), per active edge read 8 B plus two 4 B gathers, 8 B per
+    # atomic, 4 B per walk read, 8 B per survivor written, final labels
+    # (8 B per vertex)
+    kbytes = (12.0 * n + 16.0 * st["edges_read"] + 8.0 * st["atomics"] + 4.0 * st["chase_reads"]
+              + 8.0 * st["survivors_written"])
     achieved = kbytes / (kernel_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "kernel": "batched_kernel", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("batched", config),

@@ -260,6 +260,10 @@ typedef struct cc_batch_stats {
     int64_t total_vertices;
     double ms_total;     /* device time of the launch */
     float pass_ms[32];   /* device time of pass i (the entry after the last pass: final labels) */
+    int64_t atomics;           /* atomicMin operations issued, over all passes */
+    int64_t chase_reads;       /* parent[] reads of the walks beyond two per active edge */
+    int64_t edges_read;        /* active edges read, summed over the passes */
+    int64_t survivors_written; /* edges kept for a later pass, summed over the passes */
 } cc_batch_stats;
 
 /* cc_label_batched with an explicit launch shape and statistics (may be NULL).

@@ -90,7 +90,9 @@ class TupleStats(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("tile_edges", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("max_link", ctypes.c_int32), ("total_edges", ctypes.c_int64),
-                ("total_vertices", ctypes.c_int64), ("ms_total", ctypes.c_double), ("pass_ms", ctypes.c_float * 32)]
+                ("total_vertices", ctypes.c_int64), ("ms_total", ctypes.c_double), ("pass_ms", ctypes.c_float * 32),
+                ("atomics", ctypes.c_int64), ("chase_reads", ctypes.c_int64), ("edges_read", ctypes.c_int64),
+                ("survivors_written", ctypes.c_int64)]
 
 
 _lib = None

@@ -318,6 +318,13 @@ constexpr int64_t kLazyJump = 8;
 // launch 2.5x slower.
 constexpr int kFirstLaunch = 8;
 constexpr int64_t kSplitDegree = 8;
+// On lists with more than kMergeAfter + 2 first-pass chunks, chunks
+// kMergeAfter and later run as one launch.  Measured on MI355X (forced SV,
+// each chunk its own launch / from the third chunk on as one / from the
+// fourth): R-MAT scale 24 3.98 / 3.65 / 3.70 ms, noisy R-MAT 3.92 / 3.49 /
+// 3.55 ms; the 8192^2 lattice (4 chunks) 10.08 / 11.04 ms when merged from
+// the third, the 200 M-vertex forest (4 chunks) 22.2 / 20.7 ms.
+constexpr int kMergeAfter = 2;
 
 // Chunks of the first pass.  Within one pass the trees only grow (no
 // shortcut runs while hooks are in flight), so the finds of late edges walk
@@ -434,15 +441,25 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         int rec_pass = -1;
         double flat_bytes = 0.0;
         int64_t filt_edges = 0;   // edges of this pass read by launches with the bitmap
+        int last_lo = 0;          // first segment of the first pass's last launch
         if (in_soa) {
             // chunk k covers segments [k * nseg_chunk, (k + 1) * nseg_chunk);
             // on dense graphs the first chunk is launched as [0, cut), [cut, nseg_chunk)
             const int split = chunks > 1 && m0 >= kSplitDegree * (int64_t)c.n && nseg_chunk >= 2 ? 2 : 1;
             const int cut = std::max(1, nseg_chunk / kFirstLaunch);
+            // On dense lists (more than kMergeAfter + 2 chunks) the chunks from
+            // kMergeAfter on run as one launch: by then the largest tree's
+            // bitmap drops nearly all of their edges, and the flattens, picks
+            // and bitmaps between them cost more than the shallower trees
+            // save.  Sparse lists keep every chunk (a lattice's largest tree
+            // appears only in its last chunks).
+            const int merge_at = chunks > kMergeAfter + 2 ? kMergeAfter : chunks;
+            last_lo = std::min(merge_at, chunks - 1) * nseg_chunk;
             for (int k = 0; k < chunks; ++k) {
                 for (int part = 0; part < (k == 0 ? split : 1); ++part) {
                     const int s0 = k > 0 ? k * nseg_chunk : (part == 0 ? 0 : cut);
-                    const int s1 = k > 0 ? (k + 1) * nseg_chunk : (split == 1 || part == 1 ? nseg_chunk : cut);
+                    const int s1 = k >= merge_at ? chunks * nseg_chunk
+                                 : k > 0 ? (k + 1) * nseg_chunk : (split == 1 || part == 1 ? nseg_chunk : cut);
                     const bool filt = s0 > 0 && gbits;
                     if (s0 > 0) {
                         int kf = c.kbeg();
@@ -480,6 +497,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                     rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)(e1 - e0));
                     if (filt) filt_edges += e1 - e0;
                 }
+                if (k >= merge_at) break;
             }
         } else {
             // a long list handed over by an earlier step (the edges a BFS left)
@@ -503,10 +521,10 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                 rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)m_in * nb / nseg);
             }
         }
-        // After a chunked first pass, the full flatten after each chunk has
-        // already jumped every root hooked before the last chunk: only the
-        // last chunk's segments hold roots still to jump.
-        const int jump_lo = in_soa && chunks > 1 ? (chunks - 1) * nseg_chunk : 0;
+        // After a chunked first pass, the full flatten before each launch has
+        // already jumped every root hooked before the last launch: only its
+        // segments hold roots still to jump.
+        const int jump_lo = in_soa && chunks > 1 ? last_lo : 0;
         e = launch_sv_totals(hooked_count, out.count, nseg, jump_lo, segstat, totals, c.stream);
         if (e != hipSuccess) return hip_fail(e, "sv_totals launch");
         e = hipMemcpyAsync(htot, totals, 10 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);

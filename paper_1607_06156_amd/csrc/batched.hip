@@ -45,6 +45,8 @@ struct BatchArgs {
     uint64_t barrier_ticks;     // spin limit of a grid barrier, in 100 MHz wall-clock ticks
     unsigned long long* part;   // per-block partials: survivors, hooks, finds stopped at the hop
                                 // bound (2 x gridDim each)
+    unsigned long long* bstat;  // per block, over all passes (gridDim each): atomics issued, walk
+                                // reads, active edges read, survivors written
 };
 
 constexpr int64_t kTileE = (int64_t)kBlock * kEPT;   // edges (or vertices) per tile
@@ -163,8 +165,9 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
     // shifts the ids to global ones and drops (and counts) edges with an id
     // outside their graph.
     uint32_t bad = 0, nlong = 0;
-    uint32_t natom = 0, nchase = 0;   // not reported by the batched kernel
+    uint32_t natom = 0, nchase = 0;   // per thread, over all passes
     unsigned long long block_kept = 0, block_hooks = 0;
+    unsigned long long tot_read = 0, tot_kept = 0;   // this block, over all passes (thread 0's count)
     for (int64_t t = tw.first; t < tw.end; t += tw.step) {
         const int64_t e0 = t * kTileE;
         int64_t len = A.m - e0;
@@ -217,7 +220,9 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
         }
         block_kept += kept;
         block_hooks += hk;
+        tot_read += len > 0 ? (unsigned long long)len : 0ull;
     }
+    tot_kept += block_kept;
     for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o);
     if (lane_id() == 0 && bad) {
         __hip_atomic_fetch_add(&A.status[2], (unsigned long long)bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -348,7 +353,9 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
             }
             block_kept += kept;
             block_hooks += hk;
+            tot_read += len;
         }
+        tot_kept += block_kept;
         for (int o = 32; o > 0; o >>= 1) nlong += __shfl_xor(nlong, o);
         if (threadIdx.x == 0) sh_blong = 0;
         __syncthreads();
@@ -365,6 +372,32 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
         uint32_t* tc = cin; cin = cout; cout = tc;
     }
     if (b == 0 && threadIdx.x == 0) A.status[1] = (unsigned long long)pass;
+    // this block's counts for the byte model (sh_total / sh_hooks are free:
+    // every thread has read them before the loop ended)
+    __syncthreads();
+    {
+        unsigned long long sa = natom, sc = nchase;
+        for (int o = 32; o > 0; o >>= 1) {
+            sa += __shfl_xor(sa, o);
+            sc += __shfl_xor(sc, o);
+        }
+        if (threadIdx.x == 0) {
+            sh_total = 0;
+            sh_hooks = 0;
+        }
+        __syncthreads();
+        if (lane_id() == 0) {
+            atomicAdd(&sh_total, sa);
+            atomicAdd(&sh_hooks, sc);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            A.bstat[b] = sh_total;
+            A.bstat[nb + b] = sh_hooks;
+            A.bstat[2 * nb + b] = tot_read;
+            A.bstat[3 * nb + b] = tot_kept;
+        }
+    }
 
     // ---- final labels: compress to roots, then shift to graph-local ids.
     // A root beyond the walk bound (a chain deeper than kMaxHops links) leaves
@@ -495,6 +528,7 @@ hipError_t launch_batched(const BatchArgsHost& h, int blocks, hipStream_t s) {
     A.max_link = h.max_link;
     A.barrier_ticks = h.barrier_ticks;
     A.part = h.part;
+    A.bstat = h.bstat;
     void* args[] = {&A};
     return hipLaunchCooperativeKernel((const void*)batched_kernel, dim3(blocks), dim3(kBlock), args, 0, s);
 }

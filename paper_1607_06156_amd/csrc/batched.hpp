@@ -18,6 +18,7 @@ struct BatchArgsHost {
     int2* buf0;
     int2* buf1;
     unsigned long long* part;   // 6 x blocks partials (survivors, hooks, bounded finds; 2 arrays each)
+    unsigned long long* bstat;  // 4 x blocks: atomics, walk reads, edges read, survivors written
     uint32_t* cnt0;
     uint32_t* cnt1;
     uint32_t* hcnt;

@@ -2,6 +2,7 @@
 // the C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -22,6 +23,10 @@ namespace ccmi {
 constexpr size_t kBatchCtl = 1024;      // barrier words + status block
 constexpr int kStatusWords = 48;        // status[0..3) codes, [4] deep chains left, status[8..48) pass stamps
 constexpr int kStatusDeep = 4;
+// host staging: the status words at 0, the per-block counts (4 x blocks,
+// blocks <= 16384) from this word on
+constexpr size_t kBstatHost = 1024;
+static_assert((kBstatHost + 4 * 16384) * sizeof(unsigned long long) <= Workspace::kHostBytes, "staging size");
 // status[0] error bits written by the persistent kernel
 constexpr unsigned long long kErrRangeBit = 1, kErrOffsetsBit = 2, kErrBarrierBit = 4;
 // default spin limit of the kernel's grid barrier: 5 s of the 100 MHz wall clock
@@ -127,7 +132,7 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     const size_t cnt_bytes = ((size_t)tiles * 3 * sizeof(uint32_t) + 255) & ~(size_t)255;
     // per-tile counts, then per-block partials (survivors, hooks and finds
     // stopped at the hop bound, two arrays each)
-    if ((rc = ws.get(WS_SEGCOUNT, cnt_bytes + (size_t)blocks * 6 * sizeof(unsigned long long), &pc))) return rc;
+    if ((rc = ws.get(WS_SEGCOUNT, cnt_bytes + (size_t)blocks * 10 * sizeof(unsigned long long), &pc))) return rc;
     if ((rc = ws.get(WS_BATCH, kBatchCtl, &pb))) return rc;
     h.buf0 = (int2*)p0;
     h.buf1 = (int2*)p1;
@@ -136,6 +141,7 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     h.cnt1 = h.cnt0 + tiles;
     h.hcnt = h.cnt1 + tiles;
     h.part = (unsigned long long*)((char*)pc + cnt_bytes);
+    h.bstat = h.part + (size_t)blocks * 6;
     h.bar = (unsigned int*)pb;
     h.status = (unsigned long long*)((char*)pb + 64);
     h.max_link = link;
@@ -160,6 +166,10 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     if (e == hipSuccess)
         e = hipMemcpyAsync(status_host, h.status, kStatusWords * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            s);
+    // the per-block counts of the byte model, behind the status words
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(status_host + kBstatHost, h.bstat, (size_t)blocks * 4 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && ms) {
         float t = 0;
@@ -250,6 +260,12 @@ static int run_union(Workspace& ws, const BatchArgsHost& h, hipStream_t s, unsig
         stats->total_edges = m;
         stats->total_vertices = n;
         stats->ms_total = t;
+        stats->atomics = st.sv_atomics;
+        stats->chase_reads = st.sv_chase_reads;
+        for (int i = 0; i < std::min(st.sv_passes, 64); ++i) {
+            stats->edges_read += st.active_edges[i];
+            if (i > 0) stats->survivors_written += st.active_edges[i];
+        }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -376,6 +392,14 @@ CC_API int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t
         stats->total_edges = m;
         stats->total_vertices = n;
         stats->ms_total = ms;
+        const unsigned long long* bs = host + kBstatHost;
+        const int nbk = cfg.blocks;
+        for (int i = 0; i < nbk; ++i) {
+            stats->atomics += (int64_t)bs[i];
+            stats->chase_reads += (int64_t)bs[nbk + i];
+            stats->edges_read += (int64_t)bs[2 * nbk + i];
+            stats->survivors_written += (int64_t)bs[3 * nbk + i];
+        }
         // barrier stamps (100 MHz wall clock): pass i runs between stamps i and i+1
         for (int i = 0; i < 32 && i + 1 < 40 && i < passes + 1; ++i) {
             const unsigned long long a = host[8 + i], b = host[8 + i + 1];

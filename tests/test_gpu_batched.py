@@ -30,8 +30,14 @@ def expected(b):
 def test_batch_small_families():
     b = gen.batch(64, 5_000_000, lg_hi=14.0)
     lab, st = run_batch(b, stats=True)
-    say(f"   passes={st['passes']} blocks={st['blocks']} tile={st['tile_edges']} ms={st['ms_total']:.3f}")
+    say(f"   passes={st['passes']} blocks={st['blocks']} tile={st['tile_edges']} ms={st['ms_total']:.3f} "
+        f"read={st['edges_read']} atomics={st['atomics']} chase={st['chase_reads']} kept={st['survivors_written']}")
     assert np.array_equal(lab.cpu().numpy(), expected(b))
+    # the byte model's counts: the first pass reads every edge and later
+    # passes read what earlier ones kept
+    m = int(b.edge_off[-1])
+    assert st["edges_read"] == m + st["survivors_written"]
+    assert st["atomics"] > 0 and st["chase_reads"] >= 0
 
 
 def test_batch_uneven_sizes():
