@@ -227,6 +227,9 @@ def bench_tuples(name):
     lab_t, st = ccmi.label_tuples(u, v, g.n)              # first call also sizes the workspace
     torch.cuda.synchronize()
     lab_t, st = ccmi.label_tuples(u, v, g.n, out=lab_t)
+    lab_x, stx = ccmi.label_tuples(u, v, g.n, exclude=True)   # completed partitions set aside
+    exact_x = bool(torch.equal(lab_t, lab_x))
+    del lab_x
     _, sv_sec, sts = time_route(ccmi, torch, u, v, g.n, "sv", 3, 1, profile=True)
     lab_s = ccmi.label(u, v, g.n, route="sv")
     exact = bool(torch.equal(lab_t, lab_s))
@@ -235,6 +238,9 @@ def bench_tuples(name):
            "tuples": st["tuples"], "iterations": st["iterations"], "sorts": st["sorts"],
            "passes_per_sort": st["passes_per_sort"], "tuples_ms": round(st["ms_total"], 3),
            "tuples_sort_ms": round(st["ms_sort"], 3), "sort_share": round(st["ms_sort"] / st["ms_total"], 4),
+           "exclusion": {"iterations": stx["iterations"], "tuples_ms": round(stx["ms_total"], 3),
+                         "tuples_sort_ms": round(stx["ms_sort"], 3),
+                         "sort_share": round(stx["ms_sort"] / stx["ms_total"], 4), "labels_identical": exact_x},
            "sv_ms": round(sv_sec * 1e3, 3), "sv_passes": sv_sort_free["sv_passes"],
            "sv_kernel_ms": {ccmi.KERNEL_CLASSES[i]: round(float(x), 3)
                             for i, x in enumerate(sv_sort_free["kernel_ms"]) if x},

@@ -196,12 +196,16 @@ int cc_label64_ex(const int64_t* u, const int64_t* v, int64_t m, int64_t n_max, 
 
 /* Algorithm 1 as the paper runs it (Section III-A.2, with the sorts of
  * Section III-A.3): the tuple array <p, q, r>, grouped by radix sorts four
- * times per iteration, with the pointer-doubling temporary tuples; no
- * completed partitions are set aside.  An ablation beside the atomic-hooking
- * SV of cc_label, to measure the share of time the sorts take (Section V,
- * Performance Anatomy).  Same arguments, result and errors as cc_label
- * (n + 2m + n must stay below 2^32); scratch is the cached per-device
- * workspace, about 32 bytes per tuple.  st (host, may be NULL) receives: */
+ * times per iteration, with the pointer-doubling temporary tuples.  An
+ * ablation beside the atomic-hooking SV of cc_label, to measure the share of
+ * time the sorts take (Section V, Performance Anatomy).  exclude != 0 sets
+ * completed partitions aside as
+ * Section III-A.4 describes: after the first join of an iteration, a
+ * partition whose vertices are in no other partition, and which did not
+ * move, gets its labels and leaves the array.  Same arguments, result and
+ * errors as cc_label otherwise (n + 2m + n must stay below 2^32); scratch is
+ * the cached per-device workspace, about 32 bytes per tuple.  st (host, may
+ * be NULL) receives: */
 typedef struct cc_tuple_stats {
     int32_t iterations;       /* iterations of Algorithm 1 until no partition changed */
     int32_t sorts;            /* radix sorts (4 per iteration) */
@@ -212,7 +216,7 @@ typedef struct cc_tuple_stats {
     double ms_total;          /* whole call, host clock */
 } cc_tuple_stats;
 int cc_label_tuples(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream,
-                    cc_tuple_stats* st);
+                    int32_t exclude, cc_tuple_stats* st);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): cc_label on the plain SV

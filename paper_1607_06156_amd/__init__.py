@@ -136,7 +136,7 @@ def lib():
             "cc_workspace_size": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
             "cc_shutdown": (ctypes.c_int, []),
             "cc_label_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP]),
-            "cc_label_tuples": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP,
+            "cc_label_tuples": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
                                                ctypes.POINTER(TupleStats)]),
             "cc_label64": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP,
                                           ctypes.POINTER(ctypes.c_int64), _VP]),
@@ -220,8 +220,9 @@ def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tenso
     return (out, st.to_dict()) if stats else out
 
 
-def label_tuples(u: torch.Tensor, v: torch.Tensor, n: int, out: torch.Tensor | None = None):
-    """Algorithm 1 with radix sorts (cc_label_tuples): (labels, stats dict)."""
+def label_tuples(u: torch.Tensor, v: torch.Tensor, n: int, out: torch.Tensor | None = None, exclude: bool = False):
+    """Algorithm 1 with radix sorts (cc_label_tuples): (labels, stats dict);
+    exclude sets completed partitions aside (Section III-A.4)."""
     m = int(u.numel())
     if int(v.numel()) != m:
         raise ValueError("u and v differ in length")
@@ -229,7 +230,7 @@ def label_tuples(u: torch.Tensor, v: torch.Tensor, n: int, out: torch.Tensor | N
         out = torch.empty(max(n, 0), dtype=torch.int32, device=u.device)
     st = TupleStats()
     _check(lib().cc_label_tuples(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n,
-                                 _dev(out, torch.int32, "labels"), _stream(), ctypes.byref(st)))
+                                 _dev(out, torch.int32, "labels"), _stream(), 1 if exclude else 0, ctypes.byref(st)))
     return out, {k: getattr(st, k) for k, _ in TupleStats._fields_ if k != "reserved"}
 
 

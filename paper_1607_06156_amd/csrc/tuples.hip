@@ -15,8 +15,13 @@
 //   4. steps 1 and 2 again with the temporary tuples (pointer doubling, Fig.
 //      "doubling"), then the temporary tuples are erased.
 // The loop ends when no partition changed in either step 2.  The label of u
-// is p of any tuple <p, q, u>.  Completed partitions are not set aside
-// (Section III-A.4): every iteration sorts the whole array.
+// is p of any tuple <p, q, u>.
+// With exclusion (Section III-A.4), after step 2 a tuple is potentially
+// completed when its vertex bucket holds a single partition (the bucket's
+// largest p equals its smallest); a partition all of whose tuples are
+// potentially completed, and which did not move, is complete: its tuples get
+// their labels and leave the array before step 3.  Without it every
+// iteration sorts the whole array.
 //
 // The sorts are least-significant-digit radix sorts on the two 32-bit fields
 // of the key (8-bit digits over the bits that ids below n use): per digit a
@@ -44,6 +49,10 @@ constexpr int kRsWaves = kRsThreads / 64;
 constexpr int kRsRounds = 16;                                  // 64-tuple rounds per wave
 constexpr int64_t kRsTile = (int64_t)kRsThreads * kRsRounds;   // tuples per tile
 constexpr int32_t kNone = INT32_MAX;                           // the "_" of a tuple
+// tuple.w flags
+constexpr int32_t kTmp = 1;    // a temporary tuple
+constexpr int32_t kPot = 2;    // potentially completed (its vertex bucket holds one partition)
+constexpr int32_t kDone = 4;   // its partition is complete: leaves the array
 
 // composite key of a tuple: by (r, p) when by_p is false, by (p, q) when true
 __device__ __forceinline__ uint64_t tuple_key(const int4& t, bool by_p, int bits) {
@@ -144,6 +153,32 @@ __global__ __launch_bounds__(kBlock) void bucket_head_kernel(const int4* __restr
     }
 }
 
+// last tuple of each bucket sorted by (r, p): slot[r] = the bucket's largest p
+__global__ __launch_bounds__(kBlock) void bucket_tail_kernel(const int4* __restrict__ a, int64_t T,
+                                                             int32_t* __restrict__ slot) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < T; i += stride) {
+        const int4 t = a[i];
+        const bool tail = i == T - 1 || a[i + 1].z != t.z;
+        if (tail) slot[t.z] = t.x;
+    }
+}
+
+// potentially completed: the bucket's largest p (slot2[r]) equals its
+// smallest (q, just nominated); a tuple that is not clears its partition's
+// flag in allpot (set to 1 for every vertex beforehand)
+__global__ __launch_bounds__(kBlock) void potential_kernel(int4* __restrict__ a, int64_t T,
+                                                           const int32_t* __restrict__ slot2,
+                                                           uint32_t* __restrict__ allpot) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < T; i += stride) {
+        const int4 t = a[i];
+        const bool pot = slot2[t.z] == t.y;
+        if (pot) a[i].w = t.w | kPot;
+        else allpot[t.x] = 0u;
+    }
+}
+
 // nominate: q <- slot[r] (u_min of the vertex bucket)
 __global__ __launch_bounds__(kBlock) void nominate_kernel(int4* __restrict__ a, int64_t T,
                                                           const int32_t* __restrict__ slot) {
@@ -153,17 +188,29 @@ __global__ __launch_bounds__(kBlock) void nominate_kernel(int4* __restrict__ a, 
 
 // join: p <- slot[p] (p_min of the partition bucket); *changed = 1 if any
 // tuple moved.  mark (optional): mark[p_min] = 1 for the temporary tuples.
+// allpot (optional, exclusion): a tuple whose partition did not move and whose
+// partition's tuples are all potentially completed is done: labels[r] = p, it
+// is flagged to leave the array, and it gets no temporary tuple.
 __global__ __launch_bounds__(kBlock) void join_kernel(int4* __restrict__ a, int64_t T,
                                                       const int32_t* __restrict__ slot, uint32_t* __restrict__ mark,
+                                                      const uint32_t* __restrict__ allpot,
+                                                      int32_t* __restrict__ labels,
                                                       unsigned long long* __restrict__ changed) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     bool moved = false;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < T; i += stride) {
-        const int32_t p = a[i].x;
+        const int4 t = a[i];
+        const int32_t p = t.x;
         const int32_t pm = slot[p];
         moved |= pm != p;
+        const bool done = allpot && pm == p && allpot[p] != 0u;
         a[i].x = pm;
-        if (mark) mark[pm] = 1u;
+        if (done) {
+            a[i].w = t.w | kDone;
+            labels[t.z] = p;
+        } else if (mark) {
+            mark[pm] = 1u;
+        }
     }
     if (ballot(moved) && lane_id() == 0) atomic_add_agent(changed, 1ull);
 }
@@ -229,18 +276,22 @@ struct TmpEmit {   // a temporary tuple <x, _, x> per marked x, after the T tupl
     int4* a;
     int64_t T;
     __device__ void operator()(int64_t x, uint32_t pre, uint32_t c) const {
-        if (c) a[T + pre] = make_int4((int32_t)x, kNone, (int32_t)x, 1);
+        if (c) a[T + pre] = make_int4((int32_t)x, kNone, (int32_t)x, kTmp);
     }
 };
-struct KeepCount {   // tuples that are not temporary
+struct KeepCount {   // tuples that are neither temporary nor done
     const int4* a;
-    __device__ uint32_t operator()(int64_t i) const { return a[i].w == 0 ? 1u : 0u; }
+    __device__ uint32_t operator()(int64_t i) const { return (a[i].w & (kTmp | kDone)) == 0 ? 1u : 0u; }
 };
-struct KeepEmit {
+struct KeepEmit {   // kept tuples, their potential-completion flag cleared
     const int4* a;
     int4* out;
     __device__ void operator()(int64_t i, uint32_t pre, uint32_t c) const {
-        if (c) out[pre] = a[i];
+        if (c) {
+            int4 t = a[i];
+            t.w &= ~kPot;
+            out[pre] = t;
+        }
     }
 };
 
@@ -281,7 +332,7 @@ static hipError_t sort_tuples(TupleRun& r, int64_t T, bool by_p) {
 using namespace ccmi;
 
 CC_API int cc_label_tuples(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream,
-                           cc_tuple_stats* st) {
+                           int32_t exclude, cc_tuple_stats* st) {
     clear_error();
     if (st) memset(st, 0, sizeof *st);
     if (m < 0 || n < 0) return fail(CC_EINVAL, "negative size (m=%lld, n=%d)", (long long)m, n);
@@ -308,6 +359,11 @@ CC_API int cc_label_tuples(const int32_t* u, const int32_t* v, int64_t m, int32_
         return rc;
     if ((rc = ws->get(WS_DEG, (size_t)n * sizeof(int32_t), &ps))) return rc;
     if ((rc = ws->get(WS_TAIL, (size_t)n * sizeof(uint32_t), &pm))) return rc;
+    void *ps2, *pap;
+    if ((rc = ws->get(WS_QUEUE, (size_t)n * sizeof(int32_t), &ps2))) return rc;
+    if ((rc = ws->get(WS_BITS, (size_t)n * sizeof(uint32_t), &pap))) return rc;
+    int32_t* slot2 = (int32_t*)ps2;      // largest p of each vertex bucket (exclusion)
+    uint32_t* allpot = (uint32_t*)pap;   // per partition: all of its tuples potentially completed
     if ((rc = ws->get(WS_TOTALS, 64 * sizeof(unsigned long long), &pk))) return rc;
     unsigned long long* host;
     if ((rc = ws->pinned((void**)&host))) return rc;
@@ -370,10 +426,26 @@ CC_API int cc_label_tuples(const int32_t* u, const int32_t* v, int64_t m, int32_
         if ((e = timed_sort(T, false)) != hipSuccess) break;
         bucket_head_kernel<<<grid_t(T), kBlock, 0, s>>>(r.a, T, false, r.slot);
         nominate_kernel<<<grid_t(T), kBlock, 0, s>>>(r.a, T, r.slot);
+        if (exclude) {
+            bucket_tail_kernel<<<grid_t(T), kBlock, 0, s>>>(r.a, T, slot2);
+            fill_u32_kernel<<<grid_t(n), kBlock, 0, s>>>(allpot, n, 1u);
+            potential_kernel<<<grid_t(T), kBlock, 0, s>>>(r.a, T, slot2, allpot);
+        }
         if ((e = timed_sort(T, true)) != hipSuccess) break;
         bucket_head_kernel<<<grid_t(T), kBlock, 0, s>>>(r.a, T, true, r.slot);
         fill_u32_kernel<<<grid_t(n), kBlock, 0, s>>>(r.mark, n, 0u);
-        join_kernel<<<grid_t(T), kBlock, 0, s>>>(r.a, T, r.slot, r.mark, r.ctl);
+        join_kernel<<<grid_t(T), kBlock, 0, s>>>(r.a, T, r.slot, r.mark, exclude ? allpot : nullptr, labels, r.ctl);
+        if (exclude) {
+            // completed partitions leave the array
+            if ((e = device_scan(KeepCount{r.a}, KeepEmit{r.a, r.b}, T, r.bsum, r.ctl + 2, s)) != hipSuccess) break;
+            std::swap(r.a, r.b);
+            if ((e = hipMemcpyAsync(host, r.ctl + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess)
+                break;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+            T = (int64_t)host[0];
+            if (T == 0) break;   // every partition completed: nothing moved, nothing left
+        }
         // temporary tuples <p_min, _, p_min>, one per partition of the result
         if ((e = device_scan(MarkCount{r.mark}, TmpEmit{r.a, T}, n, r.bsum, r.ctl + 2, s)) != hipSuccess) break;
         if ((e = hipMemcpyAsync(host, r.ctl + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -386,7 +458,7 @@ CC_API int cc_label_tuples(const int32_t* u, const int32_t* v, int64_t m, int32_
         nominate_kernel<<<grid_t(T2), kBlock, 0, s>>>(r.a, T2, r.slot);
         if ((e = timed_sort(T2, true)) != hipSuccess) break;
         bucket_head_kernel<<<grid_t(T2), kBlock, 0, s>>>(r.a, T2, true, r.slot);
-        join_kernel<<<grid_t(T2), kBlock, 0, s>>>(r.a, T2, r.slot, nullptr, r.ctl + 1);
+        join_kernel<<<grid_t(T2), kBlock, 0, s>>>(r.a, T2, r.slot, nullptr, nullptr, nullptr, r.ctl + 1);
         // erase the temporary tuples
         if ((e = device_scan(KeepCount{r.a}, KeepEmit{r.a, r.b}, T2, r.bsum, r.ctl + 2, s)) != hipSuccess) break;
         std::swap(r.a, r.b);

@@ -148,9 +148,9 @@ def test_label64_and_tuples_reject_bad_arguments_on_host(lib):
     assert b"2^30" in L.cc_last_error()
     assert L.cc_label64(None, None, 10, 0, 8, 8, ctypes.byref(n), None) == -1     # NULL edges
     st = ccmi.TupleStats()
-    assert L.cc_label_tuples(None, None, -1, 5, None, None, ctypes.byref(st)) == -1
-    assert L.cc_label_tuples(None, None, 0, 0, None, None, ctypes.byref(st)) == 0
-    assert L.cc_label_tuples(8, 8, 1 << 31, 1 << 30, 8, None, ctypes.byref(st)) == -1   # n + 2m + n >= 2^32
+    assert L.cc_label_tuples(None, None, -1, 5, None, None, 0, ctypes.byref(st)) == -1
+    assert L.cc_label_tuples(None, None, 0, 0, None, None, 1, ctypes.byref(st)) == 0
+    assert L.cc_label_tuples(8, 8, 1 << 31, 1 << 30, 8, None, 0, ctypes.byref(st)) == -1   # n + 2m + n >= 2^32
     assert L.cc_label_noalloc(None, None, -1, 5, None, None) == -1
 
 

@@ -15,9 +15,9 @@ pytestmark = pytest.mark.gpu
 ccmi = pytest.importorskip("paper_1607_06156_amd")
 
 
-def run(g):
-    say(f"[gpu] tuples {g.name} n={g.n} m={g.m}")
-    lab, st = ccmi.label_tuples(to_dev(g.u), to_dev(g.v), g.n)
+def run(g, exclude=False):
+    say(f"[gpu] tuples {g.name} n={g.n} m={g.m} exclude={exclude}")
+    lab, st = ccmi.label_tuples(to_dev(g.u), to_dev(g.v), g.n, exclude=exclude)
     say(f"   iterations={st['iterations']} sorts={st['sorts']} passes={st['passes_per_sort']} "
         f"sort {st['ms_sort']:.2f} of {st['ms_total']:.2f} ms")
     return lab, st
@@ -39,6 +39,22 @@ def test_tuples_match_algorithm1_oracle(name, g):
     assert st["sorts"] == 4 * it and st["tuples"] == g.n + 2 * g.m
 
 
+@pytest.mark.parametrize("name,g", [
+    ("gnm", gen.gnm(3000, 2500, seed=1)),
+    ("rmat", gen.rmat(11, 4, seed=2)),
+    ("grid", gen.grid(40, 0.6, seed=3)),
+    ("plcomp", gen.plcomp(20_000, seed=4)),
+])
+def test_tuples_with_exclusion_match_oracle(name, g):
+    """Completed partitions set aside (Section III-A.4): same labels, and the
+    iteration count of the oracle transcription run with the same option."""
+    lab, st = run(g, exclude=True)
+    exp, it = alg1.run(g.u, g.v, g.n, exclude_completed=True)
+    assert_labels_equal(lab, exp, name)
+    assert_labels_equal(lab, oracle_labels(g), name)
+    assert st["iterations"] == it
+
+
 def test_tuples_closed_forms_and_ragged_sizes():
     rng = np.random.default_rng(3)
     n = 5000
@@ -54,8 +70,11 @@ def test_tuples_closed_forms_and_ragged_sizes():
     assert_labels_equal(lab, np.arange(9, dtype=np.int32), "self-loops")
     for m in [1, 5, 1023, 4095, 4097, 70001]:                         # around the 4096-tuple tile
         g = gen.gnm(max(8, m), m, seed=m)
-        lab, _ = run(g)
-        assert_labels_equal(lab, oracle_labels(g), f"gnm m={m}")
+        for ex in (False, True):
+            lab, _ = run(g, exclude=ex)
+            assert_labels_equal(lab, oracle_labels(g), f"gnm m={m} exclude={ex}")
+    lab, _ = run(loops, exclude=True)                                  # every partition completes at once
+    assert_labels_equal(lab, np.arange(9, dtype=np.int32), "self-loops, exclusion")
 
 
 def test_tuples_medium_graphs():
