@@ -143,6 +143,141 @@ __global__ __launch_bounds__(kBlock) void topdown_kernel(const int32_t* __restri
     if (lane_id() == 0 && mdeg) atomic_add_agent(&ctr[1], mdeg);
 }
 
+// ----------------------------------------------- small levels in one workgroup
+// A level whose frontier has few adjacency entries is microseconds of work,
+// while a launch and a host round trip per level cost about 50 us (C1's 27
+// levels took 1.4 ms that way).  One workgroup therefore runs consecutive
+// top-down levels with workgroup barriers between them, from the frontier in
+// q (qn vertices, their bits already set in vis), and stops before a level
+// whose frontier has more than max_entries entries (the multi-launch levels
+// take it), after max_levels levels, or when the frontier is empty.  Per
+// level: a block scan of the frontier's degrees into pre[], then each thread
+// expands a contiguous share of the entries (one binary search for its first
+// vertex, then a forward walk, four entries' reads in flight at a time),
+// appending new vertices to the other queue through an LDS counter.  The
+// frontier it stops at is left in q.
+// out: [0] levels expanded, [1] vertices visited, [2] entries examined,
+// [3] degree sum of the vertices visited, [4] vertices of the frontier left,
+// [5] their degree sum.
+constexpr int kFewThreads = 1024;
+__global__ __launch_bounds__(kFewThreads) void bfs_few_kernel(const int64_t* __restrict__ off,
+                                                              const int32_t* __restrict__ adj, int32_t* qa,
+                                                              int32_t* qb, int64_t qn0, int64_t max_entries,
+                                                              int32_t max_levels, uint32_t* vis, int64_t* pre,
+                                                              unsigned long long* __restrict__ out) {
+    __shared__ uint32_t s_found;
+    __shared__ int64_t s_wsum[kFewThreads / 64];
+    __shared__ int64_t s_carry;
+    __shared__ unsigned long long s_fdeg;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    int32_t* q = qa;
+    int32_t* nq = qb;
+    int64_t qn = qn0, visited = 0, examined = 0;
+    unsigned long long fdeg_all = 0;
+    int32_t levels = 0;
+    int64_t total = 0;
+    for (;;) {
+        // exclusive scan of the frontier's degrees into pre[0..qn]
+        if (tid == 0) s_carry = 0;
+        __syncthreads();
+        for (int64_t r0 = 0; r0 < qn; r0 += kFewThreads) {
+            const int64_t i = r0 + tid;
+            int64_t d = 0;
+            if (i < qn) {
+                const int32_t x = q[i];
+                d = off[x + 1] - off[x];
+            }
+            int64_t x = d;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int64_t y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) s_wsum[w] = x;
+            __syncthreads();
+            int64_t before = s_carry;
+            for (int k = 0; k < w; ++k) before += s_wsum[k];
+            if (i < qn) pre[i] = before + x - d;
+            __syncthreads();
+            if (tid == 0) {
+                int64_t t = 0;
+                for (int k = 0; k < kFewThreads / 64; ++k) t += s_wsum[k];
+                s_carry += t;
+            }
+            __syncthreads();
+        }
+        total = s_carry;
+        if (qn == 0 || total > max_entries || levels >= max_levels) break;   // uniform: every thread read it
+        if (tid == 0) {
+            pre[qn] = total;
+            s_found = 0;
+            s_fdeg = 0;
+        }
+        __syncthreads();
+        const int64_t e0 = total * tid / kFewThreads, e1 = total * (tid + 1) / kFewThreads;
+        unsigned long long fdeg = 0;
+        if (e0 < e1) {
+            int64_t lo = 0, hi = qn - 1;   // last i with pre[i] <= e0
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= e0) lo = mid; else hi = mid - 1;
+            }
+            int64_t i = lo, next = pre[i + 1], base = off[q[i]] - pre[i];
+            for (int64_t e = e0; e < e1; e += 4) {
+                int32_t y[4];
+                bool ok[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    ok[k] = e + k < e1;
+                    y[k] = 0;
+                    if (ok[k]) {
+                        while (e + k >= next) {
+                            ++i;
+                            next = pre[i + 1];
+                            base = off[q[i]] - pre[i];
+                        }
+                        y[k] = adj[base + e + k];
+                    }
+                }
+                uint32_t wv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) wv[k] = ok[k] ? vis[y[k] >> 5] : ~0u;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t bit = 1u << (y[k] & 31);
+                    if (!ok[k] || (wv[k] & bit)) continue;
+                    const uint32_t old = atomic_or_agent(&vis[y[k] >> 5], bit);
+                    if (old & bit) continue;
+                    nq[atomicAdd(&s_found, 1u)] = y[k];
+                    fdeg += (unsigned long long)(off[y[k] + 1] - off[y[k]]);
+                }
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) fdeg += __shfl_xor(fdeg, o);
+        if (lane == 0 && fdeg) atomicAdd(&s_fdeg, fdeg);
+        __syncthreads();
+        qn = s_found;
+        visited += qn;
+        examined += total;
+        fdeg_all += s_fdeg;
+        ++levels;
+        int32_t* t = q;
+        q = nq;
+        nq = t;
+        __syncthreads();   // every thread has read s_found and s_fdeg before the next level resets them
+    }
+    // the frontier left behind goes back to qa
+    if (q != qa)
+        for (int64_t i = tid; i < qn; i += kFewThreads) qa[i] = q[i];
+    if (tid == 0) {
+        out[0] = (unsigned long long)levels;
+        out[1] = (unsigned long long)visited;
+        out[2] = (unsigned long long)examined;
+        out[3] = fdeg_all;
+        out[4] = (unsigned long long)qn;
+        out[5] = (unsigned long long)total;
+    }
+}
+
 // --------------------------------------------------------- bottom-up level
 // Grid-stride over runs of 8 bitmap words (256 vertices, one per thread).
 __global__ __launch_bounds__(kBlock) void bottomup_kernel(int32_t n, const int64_t* __restrict__ off,
@@ -504,6 +639,14 @@ hipError_t launch_topdown(const int32_t* q, int64_t qn, const int64_t* pre, int6
     }
     if (g < 1) g = 1;
     topdown_kernel<<<(unsigned)g, kBlock, 0, s>>>(q, qn, pre, off, adj, vis, nq, ctr, per);
+    return hipGetLastError();
+}
+
+hipError_t launch_bfs_few(const int64_t* off, const int32_t* adj, int32_t* qa, int32_t* qb, int64_t qn,
+                          int64_t max_entries, int32_t max_levels, uint32_t* vis, int64_t* pre,
+                          unsigned long long* out, hipStream_t s) {
+    if (qn < 0 || max_levels < 1) return hipErrorInvalidValue;
+    bfs_few_kernel<<<1, kFewThreads, 0, s>>>(off, adj, qa, qb, qn, max_entries, max_levels, vis, pre, out);
     return hipGetLastError();
 }
 

@@ -21,6 +21,16 @@ hipError_t launch_topdown(const int32_t* q, int64_t qn, const int64_t* pre, int6
 // ctr[0] += new vertices (bits in next), ctr[1] += their degrees, ctr[2] += entries examined
 hipError_t launch_bottomup(int32_t n, const int64_t* off, const int32_t* adj, uint32_t* vis, const uint32_t* front,
                            uint32_t* next, unsigned long long* ctr, hipStream_t s);
+// Consecutive top-down levels in one workgroup, from the frontier in qa (qn
+// vertices, already marked in vis), while a level's frontier has at most
+// max_entries adjacency entries and for at most max_levels levels; the
+// frontier it stops at is left in qa.  qa / qb hold n entries, pre n + 1.
+// out[0..6): levels, vertices visited, entries examined, degree sum of the
+// vertices visited, frontier size left, its degree sum.
+constexpr int64_t kFewLevelEntries = 65536;   // largest frontier (in entries) it expands
+hipError_t launch_bfs_few(const int64_t* off, const int32_t* adj, int32_t* qa, int32_t* qb, int64_t qn,
+                          int64_t max_entries, int32_t max_levels, uint32_t* vis, int64_t* pre,
+                          unsigned long long* out, hipStream_t s);
 hipError_t launch_queue_to_bits(const int32_t* q, int64_t qn, uint32_t* bits, hipStream_t s);
 hipError_t launch_bits_to_queue(const uint32_t* bits, int64_t words, int32_t* q, unsigned long long* qn,
                                 hipStream_t s);

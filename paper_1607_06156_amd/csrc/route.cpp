@@ -236,6 +236,43 @@ int run_bfs(Call& c, const int64_t* off, const int32_t* adj, int64_t nadj, int32
     bool topdown = true;
     int levels = 0, bu_levels = 0;
     while (nf > 0) {
+        if (topdown && mf <= kFewLevelEntries) {
+            // small frontiers: as many levels as stay small in one workgroup,
+            // one launch and one readback for all of them
+            const int budget = max_levels > 0 ? max_levels - levels : INT32_MAX;
+            int k0 = c.kbeg();
+            if ((e = launch_bfs_few(off, adj, q, nq, qn, kFewLevelEntries, budget, vis, pre, ctr, c.stream)) !=
+                hipSuccess)
+                return hip_fail(e, "bfs_few launch");
+            int rec = c.kend(CC_K_BFS, k0, 0.0);
+            if ((rc = sync_read(c, host, ctr, 6 * sizeof(unsigned long long)))) return rc;
+            const int lr = (int)host[0];
+            if (lr < 1) {
+                // the frontier's entries exceed what the host counted: expand
+                // it with the launch-per-level code below
+                mf = (int64_t)host[5];
+                if (mf <= kFewLevelEntries) return fail(CC_EINTERNAL, "BFS made no progress on a small frontier");
+                goto multi;
+            }
+            // per level: queue and offsets of the frontier (scan and walk),
+            // entries, bitmap probes, new vertices' offsets and queue slots
+            const double lbytes = 28.0 * (double)host[1] + 8.0 * (double)host[2];
+            c.kbytes(rec, lbytes);
+            if (c.stats) c.bytes += lbytes;
+            levels += lr;
+            visited += (int64_t)host[1];
+            examined += (int64_t)host[2];
+            mu -= (int64_t)host[3];
+            prev_nf = nf;
+            nf = qn = (int64_t)host[4];
+            mf = (int64_t)host[5];
+            if (max_levels > 0 && levels >= max_levels && nf > 0) {
+                br->abandoned = true;
+                break;
+            }
+            continue;
+        }
+    multi:
         if (topdown && (double)mf > (double)mu / kBeamerAlpha) {
             // switch to bottom-up: frontier queue -> bitmap
             if ((e = hipMemsetAsync(front, 0, words * sizeof(uint32_t), c.stream)) != hipSuccess)

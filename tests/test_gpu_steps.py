@@ -356,3 +356,50 @@ def test_router_route_matches_fp64_argmax():
     with pytest.raises(ccmi.CCError) as ei:
         ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route="router")
     assert ei.value.code == ccmi.CC_ENOROUTER
+
+
+def test_small_frontiers_run_in_one_workgroup():
+    """Top-down levels whose frontier holds at most 65 536 adjacency entries
+    run in one workgroup, many levels per launch; a larger frontier hands
+    off to the launch-per-level BFS and a frontier that shrinks again comes
+    back.  Cases: a 50 000-vertex path from one end (50 000 levels), a
+    300-square lattice from a corner, a star of 400 000 leaves from a leaf
+    (the hub's row hands off), and a broom (a 1 000-vertex path, a hub with
+    200 000 leaves, a second 1 000-vertex path hanging off one leaf) from the
+    first path's far end, which leaves the workgroup and comes back.  Visited
+    set and level count against the oracle; the level budget of the BFS route
+    still applies."""
+    rng = np.random.default_rng(5)
+    n = 50_000
+    perm = rng.permutation(n).astype(np.int32)
+    path = gen.Graph(perm[:-1], perm[1:], n, "path")
+    leaves = 400_000
+    star = gen.Graph(np.zeros(leaves, np.int32), np.arange(1, leaves + 1, dtype=np.int32), leaves + 1, "star")
+    lat = gen.grid(300, 1.0, seed=6)
+    # broom ids: path a 0..999 (999 joins the hub), hub 1000, leaves
+    # 1001..201000, path b 201001..202000 hanging off leaf 1001
+    hub, nl, pl = 1000, 200_000, 1000
+    bu_ = [np.arange(0, pl - 1), [pl - 1], np.full(nl, hub), [hub + 1], np.arange(hub + nl + 1, hub + nl + pl)]
+    bv_ = [np.arange(1, pl), [hub], np.arange(hub + 1, hub + nl + 1), [hub + nl + 1],
+           np.arange(hub + nl + 2, hub + nl + pl + 1)]
+    nb = hub + nl + pl + 1
+    bperm = rng.permutation(nb).astype(np.int32)
+    broom = gen.Graph(bperm[np.concatenate(bu_).astype(np.int64)], bperm[np.concatenate(bv_).astype(np.int64)],
+                      nb, "broom")
+    for g, s, handoff in ((path, int(perm[0]), False), (lat, 0, False), (star, 7, True),
+                          (broom, int(bperm[0]), True)):
+        say(f"[gpu] small-frontier bfs {g.name} n={g.n} seed={s}")
+        off, adj, _ = ccmi.csr(to_dev(g.u), to_dev(g.v), g.n)
+        vis, levels, bu = ccmi.bfs(off, adj, g.n, s)
+        bits = np.unpackbits(vis.cpu().numpy().view(np.uint8), bitorder="little")[: g.n].astype(bool)
+        assert np.array_equal(bits, hybrid.bfs_visited(g.u, g.v, g.n, s)), g.name
+        assert levels == hybrid.bfs_levels(g.u, g.v, g.n, s), g.name
+        assert (bu > 0) == handoff, (g.name, bu)
+    # through the BFS route: the path's BFS is abandoned at the level budget
+    # and SV labels it; the star's, from the hub, finishes in 2 levels
+    lab, st = ccmi.label(to_dev(path.u), to_dev(path.v), n, route="bfs+sv", stats=True)
+    assert_labels_equal(lab, np.zeros(n, np.int32), "path via bfs+sv")
+    assert st["route"] == ccmi.R1_SV and st["bfs_levels"] == 256
+    lab, st = ccmi.label(to_dev(star.u), to_dev(star.v), star.n, route="bfs+sv", stats=True)
+    assert_labels_equal(lab, np.zeros(star.n, np.int32), "star via bfs+sv")
+    assert st["route"] == ccmi.R0_BFS_SV and st["bfs_levels"] == 2 and st["bfs_visited"] == star.n
