@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define CC_VERSION 10100 /* 1.1.0 */
+#define CC_VERSION 10200 /* 1.2.0 */
 
 /* ------------------------------------------------------------ status codes */
 #define CC_OK 0
@@ -99,7 +99,14 @@ typedef struct cc_options {
     void* workspace;     /* device memory owned by the caller, used as the call's only device scratch;
                             NULL: see scratch.  Must not be used by anything else during the call. */
     int64_t workspace_bytes; /* its size: at least cc_workspace_size(m, n, route), else CC_EINVAL */
-    int32_t reserved[4]; /* must be zero */
+    int32_t check;       /* 1: debug checks on the device (the environment variable CCMI_CHECK=1 turns
+                            them on for every call): after every SV pass, each parent link must point
+                            into [0, x]; on return, the ends of every edge must carry one label and
+                            labels[x] <= x, labels[labels[x]] == labels[x]; a violation fails the call
+                            with CC_EINTERNAL.  More SV passes than 8 ceil(log2(n + 1)) + 64 (Section
+                            III-A bounds the iterations by O(log n)) set bit 1 of cc_stats.check_flags.
+                            Costs one extra read of parent[] per pass and one of the result. */
+    int32_t reserved[3]; /* must be zero */
 } cc_options;
 
 /* kernel classes for cc_stats.kernel_* */
@@ -145,6 +152,9 @@ typedef struct cc_stats {
     int64_t sv_atomics;           /* atomicMin operations issued by the SV passes */
     int64_t sv_chase_reads;       /* parent[] reads of the SV passes beyond two per active edge */
     int64_t giant_dropped;        /* edges of the first pass dropped on the bitmap of the largest tree */
+    int32_t check_flags;          /* bit 0: the debug checks ran and passed; bit 1: more SV passes than
+                                     check_pass_limit */
+    int32_t check_pass_limit;     /* 8 ceil(log2(n + 1)) + 64 when the checks ran, else 0 */
 } cc_stats;
 
 /* Fills *opt with the defaults (route AUTO, no cap, tau 0.05, theta 8). */
@@ -286,8 +296,10 @@ int cc_label_batched_ex(const int32_t* u, const int32_t* v, const int64_t* edge_
 #define CC_ROUTER_NFEATURES 66
 
 /* Load router weights from a text file: CC_ROUTER_NPARAMS decimal floats
- * separated by white space (lines starting with '#' are comments).  Returns
- * CC_EINVAL if the file cannot be read or has the wrong count. */
+ * separated by blanks or line breaks, lines of any length (lines starting
+ * with '#' are comments).  Returns CC_EINVAL, keeping the weights loaded
+ * before, if the file cannot be read, a token is not a finite number, or the
+ * count is wrong. */
 int cc_router_load(const char* path);
 /* Set router weights from host memory (float32[CC_ROUTER_NPARAMS]); NULL unloads. */
 int cc_router_set(const float* host_params);
@@ -376,6 +388,31 @@ int cc_release_workspace(void);
  * use).  Waits for those devices first.  No call may be running; later calls
  * work as on first use. */
 int cc_shutdown(void);
+
+/* ------------------------------------------------------------ checking */
+
+/* Checks a labelling on the device against the invariants every exact
+ * result meets: I1, the two ends of each edge carry the same label, and
+ * I2, labels[x] <= x and labels[labels[x]] == labels[x].  They hold for the
+ * component-minimum labelling, and any labelling that breaks one is wrong;
+ * a labelling that merged two components into one can still pass (only a
+ * comparison with the exact result sees that).
+ *  u, v, m, n as for cc_label; labels device int32[n], read only.
+ *  bad        host int64[3], written: edges whose ends carry different
+ *             labels, vertices breaking I2, edges with an end outside [0, n).
+ * Returns CC_OK whatever the counts (they are the result); CC_EINVAL for bad
+ * arguments, CC_EHIP.  Uses the cached per-device workspace. */
+int cc_check_labels(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const int32_t* labels, void* stream,
+                    int64_t* bad);
+
+/* Test hook for the failure paths: the nth device or pinned-host allocation
+ * the library makes from now on (workspace growth, pool allocation, pinned
+ * staging, router copies) fails as if memory were exhausted, so the call
+ * making it returns CC_ENOMEM; the count is process-wide and fires once.
+ * nth = 0 turns a pending failure off.  Returns CC_OK, or CC_EINVAL for
+ * nth < 0.  A call that failed this way leaves the library usable: the next
+ * call allocates afresh. */
+int cc_debug_fail_alloc(int64_t nth);
 
 #ifdef __cplusplus
 }

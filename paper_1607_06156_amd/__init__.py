@@ -47,7 +47,7 @@ class Options(ctypes.Structure):
     _fields_ = [("route", ctypes.c_int32), ("max_passes", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("theta", ctypes.c_double), ("profile", ctypes.c_int32), ("scratch", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_int64),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("check", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
                 ("ms_filter", ctypes.c_double), ("ms_sv", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("algorithmic_bytes", ctypes.c_double), ("kernel_ms", ctypes.c_double * 8),
                 ("kernel_launches", ctypes.c_int32 * 8), ("kernel_bytes", ctypes.c_double * 8),
-                ("sv_atomics", ctypes.c_int64), ("sv_chase_reads", ctypes.c_int64), ("giant_dropped", ctypes.c_int64)]
+                ("sv_atomics", ctypes.c_int64), ("sv_chase_reads", ctypes.c_int64), ("giant_dropped", ctypes.c_int64),
+                ("check_flags", ctypes.c_int32), ("check_pass_limit", ctypes.c_int32)]
 
     def to_dict(self) -> dict:
         d = {}
@@ -136,6 +137,9 @@ def lib():
             "cc_workspace_size": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
             "cc_shutdown": (ctypes.c_int, []),
             "cc_label_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP]),
+            "cc_check_labels": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP,
+                                               ctypes.POINTER(ctypes.c_int64)]),
+            "cc_debug_fail_alloc": (ctypes.c_int, [ctypes.c_int64]),
             "cc_label_tuples": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
                                                ctypes.POINTER(TupleStats)]),
             "cc_label64": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP,
@@ -189,13 +193,14 @@ def version() -> int:
 
 def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tensor | None = None,
           stats: bool = False, max_passes: int = 0, tau: float = 0.05, theta: float = 8.0,
-          profile: bool = False, workspace: torch.Tensor | None = None, scratch=None):
+          profile: bool = False, workspace: torch.Tensor | None = None, scratch=None, check: bool = False):
     """labels[x] = min vertex id of x's component; (u[i], v[i]) are undirected edges.
 
     workspace: a uint8 device tensor of at least workspace_size(m, n, route)
     bytes used as the call's only device scratch; scratch: "cached" (default:
     the library's kept per-device workspace, calls serialise on it) or "pool"
-    (stream-ordered allocations from the library's pool, no lock)."""
+    (stream-ordered allocations from the library's pool, no lock); check:
+    the library's device-side invariant checks (cc_options.check)."""
     m = int(u.numel())
     if int(v.numel()) != m:
         raise ValueError("u and v differ in length")
@@ -209,6 +214,7 @@ def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tenso
     opt.theta = theta
     opt.profile = 1 if profile else 0
     opt.scratch = _SCRATCH_ARG[scratch]
+    opt.check = 1 if check else 0
     if workspace is not None:
         opt.workspace = _dev(workspace, torch.uint8, "workspace")
         opt.workspace_bytes = int(workspace.numel())
@@ -218,6 +224,23 @@ def label(u: torch.Tensor, v: torch.Tensor, n: int, route=None, out: torch.Tenso
                            ctypes.byref(st) if stats else None)
     _check(rc)
     return (out, st.to_dict()) if stats else out
+
+
+def check_labels(u: torch.Tensor, v: torch.Tensor, n: int, labels: torch.Tensor) -> dict:
+    """Device check of a labelling (cc_check_labels): counts of edges whose
+    ends differ in label (I1), vertices breaking I2, and out-of-range edges."""
+    m = int(u.numel())
+    if int(v.numel()) != m:
+        raise ValueError("u and v differ in length")
+    bad = (ctypes.c_int64 * 3)()
+    _check(lib().cc_check_labels(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n,
+                                 _dev(labels, torch.int32, "labels"), _stream(), bad))
+    return {"edges_split": int(bad[0]), "vertices_bad": int(bad[1]), "edges_out_of_range": int(bad[2])}
+
+
+def debug_fail_alloc(nth: int) -> None:
+    """Make the library's nth allocation from now fail (cc_debug_fail_alloc); 0 cancels."""
+    _check(lib().cc_debug_fail_alloc(int(nth)))
 
 
 def label_tuples(u: torch.Tensor, v: torch.Tensor, n: int, out: torch.Tensor | None = None, exclude: bool = False):

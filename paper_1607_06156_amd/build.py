@@ -61,9 +61,62 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Host-side sanitizer build: the host code of every source is compiled with
+# AddressSanitizer and UndefinedBehaviorSanitizer (the device code as in the
+# normal build), into _build/san/libccmi_san.so.  The library leaves the
+# sanitizer runtimes to the program that loads it, which must itself be built
+# with -fsanitize=address,undefined by the same compiler.
+SAN_DIR = os.path.join(BUILD_DIR, "san")
+SAN_OUT = os.path.join(SAN_DIR, "libccmi_san.so")
+SAN_FLAGS = []
+for _f in ("-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer"):
+    SAN_FLAGS += ["-Xarch_host", _f]
+
+
+def _compile_san(src: str) -> str:
+    obj = os.path.join(SAN_DIR, os.path.basename(src) + ".o")
+    if os.path.exists(obj) and os.path.getmtime(obj) >= max(
+            os.path.getmtime(p) for p in [src] + _headers()):
+        return obj
+    cmd = [HIPCC] + COMMON + ["-O1"] + SAN_FLAGS + (["-x", "hip"] if src.endswith(".cpp") else []) + [
+        "-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc (sanitized) failed for {src}:\n" + r.stdout + r.stderr)
+    return obj
+
+
+def _headers():
+    inc = os.path.join(os.path.dirname(PKG), "include")
+    return [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")] + \
+        [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """Builds _build/san/libccmi_san.so (objects are reused while newer than
+    their sources and headers)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    srcs = sources()
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(_compile_san, srcs))
+    tmp = SAN_OUT + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, SAN_OUT)
+    if verbose:
+        print("built", SAN_OUT)
+    return SAN_OUT
+
+
 def clean():
     shutil.rmtree(BUILD_DIR, ignore_errors=True)
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitize" in sys.argv:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)

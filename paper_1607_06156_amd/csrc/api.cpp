@@ -41,6 +41,16 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(CC_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// ------------------------------------------------------- failure injection
+static std::atomic<int64_t> g_fail_alloc{0};
+
+bool alloc_fault() {
+    int64_t k = g_fail_alloc.load();
+    while (k > 0)
+        if (g_fail_alloc.compare_exchange_weak(k, k - 1)) return k == 1;
+    return false;
+}
+
 // --------------------------------------------------------------- workspace
 // Shared pool of pinned staging buffers for the calls that do not use the
 // device's cached workspace: a call leases one and returns it at its end, so
@@ -59,7 +69,7 @@ static int lease_stage(void** out) {
         }
     }
     void* p = nullptr;
-    hipError_t e = hipHostMalloc(&p, Workspace::kHostBytes, hipHostMallocDefault);
+    hipError_t e = alloc_fault() ? hipErrorOutOfMemory : hipHostMalloc(&p, Workspace::kHostBytes, hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
     std::lock_guard<std::mutex> g(g_stage_mu);
     g_stage_all.push_back(p);
@@ -130,7 +140,7 @@ int Workspace::get(int slot, size_t bytes, void** out) {
             b.bytes = 0;
             if (e != hipSuccess) return hip_fail(e, "hipFreeAsync(workspace)");
         }
-        hipError_t e = hipMallocFromPoolAsync(&b.ptr, bytes, pool, stream);
+        hipError_t e = alloc_fault() ? hipErrorOutOfMemory : hipMallocFromPoolAsync(&b.ptr, bytes, pool, stream);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             b.ptr = nullptr;
@@ -147,7 +157,7 @@ int Workspace::get(int slot, size_t bytes, void** out) {
         b.bytes = 0;
     }
     size_t want = bytes + bytes / 8;  // headroom against repeated growth
-    hipError_t e = hipMalloc(&b.ptr, want);
+    hipError_t e = alloc_fault() ? hipErrorOutOfMemory : hipMalloc(&b.ptr, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         b.ptr = nullptr;
@@ -161,7 +171,7 @@ int Workspace::get(int slot, size_t bytes, void** out) {
 int Workspace::pinned(void** out) {
     if (!host) {
         if (mode == kCached) {
-            hipError_t e = hipHostMalloc(&host, kHostBytes, hipHostMallocDefault);
+            hipError_t e = alloc_fault() ? hipErrorOutOfMemory : hipHostMalloc(&host, kHostBytes, hipHostMallocDefault);
             if (e != hipSuccess) {
                 host = nullptr;
                 return hip_fail(e, "hipHostMalloc");
@@ -576,6 +586,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             c.kadd(rec_pass, rest);
         }
         ++pass;
+        if (c.opt.check && (rc = check_parent(ws, c.stream, c.parent, c.n, pass))) return rc;
         if (kept == 0) break;
         in = out;
         in_soa = false;
@@ -585,6 +596,12 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
     }
     if ((rc = flatten_all(c, totals + 5, htot + 8, &deep_rounds))) return rc;
     if (c.stats) c.stats->sv_deep_rounds = deep_rounds;
+    if (c.opt.check && c.stats) {
+        // Section III-A: O(log n) iterations; far more marks a regression
+        const int limit = 8 * (int)std::ceil(std::log2((double)c.n + 1.0)) + 64;
+        c.stats->check_pass_limit = limit;
+        if (pass > limit) c.stats->check_flags |= 2;
+    }
     return CC_OK;
 }
 
@@ -633,6 +650,7 @@ CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
     if (opt.workspace && opt.workspace_bytes <= 0) return fail(CC_EINVAL, "workspace given with no size");
     if (opt.scratch != CC_SCRATCH_POOL && opt.scratch != CC_SCRATCH_CACHED)
         return fail(CC_EINVAL, "bad scratch mode %d", opt.scratch);
+    opt.check = check_enabled(opt);
     if (stats) stats_reset(stats);
     if (n == 0) return CC_OK;
 
@@ -677,6 +695,14 @@ CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
     rc = run_label(c);
     int t1 = tm.mark();
     if (rc) return rc;
+    if (opt.check) {
+        if ((rc = check_result(*ws, c.stream, u, v, m, n, labels))) return rc;
+        if (stats) {
+            stats->check_flags |= 1;
+            if (!stats->check_pass_limit)
+                stats->check_pass_limit = 8 * (int)std::ceil(std::log2((double)n + 1.0)) + 64;
+        }
+    }
     if (stats) {
         stats->ms_total = tm.ms(t0, t1);
         stats->algorithmic_bytes = c.bytes;
@@ -689,6 +715,12 @@ CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
     }
     hipError_t e = hipStreamSynchronize(c.stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return CC_OK;
+}
+
+CC_API int cc_debug_fail_alloc(int64_t nth) {
+    if (nth < 0) return fail(CC_EINVAL, "negative allocation count");
+    g_fail_alloc.store(nth);
     return CC_OK;
 }
 

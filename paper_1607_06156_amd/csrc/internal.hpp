@@ -97,6 +97,18 @@ size_t workspace_bound(int64_t m, int32_t n, bool sv_only, size_t* per_slot);
 int pool_workspace(Workspace* ws, hipStream_t s);
 
 int acquire_workspace(Workspace** out);
+
+// true when a pending cc_debug_fail_alloc countdown makes this allocation fail
+bool alloc_fault();
+
+// debug checks (check.hip); counters live in the totals block from this word
+constexpr int kCheckWords = 48;
+int check_enabled(const cc_options& opt);
+int check_parent(Workspace& ws, hipStream_t s, const int32_t* parent, int32_t n, int pass);
+int check_labels(Workspace& ws, hipStream_t s, const int32_t* u, const int32_t* v, int64_t m, int32_t n,
+                 const int32_t* labels, int64_t bad[3], int64_t first[3]);
+int check_result(Workspace& ws, hipStream_t s, const int32_t* u, const int32_t* v, int64_t m, int32_t n,
+                 const int32_t* labels);
 // frees the router weights' device copies (router.cpp)
 void router_release_all();
 

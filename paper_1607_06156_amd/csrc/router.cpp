@@ -1,7 +1,10 @@
 // Router weights, the learned route decision, and the C ABI of the MLP kernels.
 #include <hip/hip_runtime.h>
 
+#include <cerrno>
+#include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -34,7 +37,7 @@ static int router_device_params(float** out, hipStream_t s) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     float*& p = g_router_dev[dev];
     if (!p) {
-        e = hipMalloc(&p, kNParams * sizeof(float));
+        e = alloc_fault() ? hipErrorOutOfMemory : hipMalloc(&p, kNParams * sizeof(float));
         if (e != hipSuccess) {
             p = nullptr;
             return hip_fail(e, "hipMalloc(router)");
@@ -104,24 +107,46 @@ CC_API int cc_router_set(const float* host_params) {
     return CC_OK;
 }
 
+// Text weights: lines starting with '#' are comments; every other token,
+// separated by blanks, is one number, and all kNParams of them must be
+// finite.  Lines may be of any length.
 CC_API int cc_router_load(const char* path) {
     if (!path) return fail(CC_EINVAL, "NULL path");
     FILE* f = fopen(path, "r");
     if (!f) return fail(CC_EINVAL, "cannot open %s", path);
     std::vector<float> w;
-    char line[4096];
-    while (fgets(line, sizeof line, f)) {
-        if (line[0] == '#') continue;
-        char* p = line;
-        while (*p) {
-            char* end;
-            float x = strtof(p, &end);
-            if (end == p) break;
+    std::string tok;
+    bool comment = false, line_start = true;
+    int rc = CC_OK;
+    auto flush = [&]() {
+        if (tok.empty() || rc) return;
+        char* end = nullptr;
+        errno = 0;
+        const float x = strtof(tok.c_str(), &end);
+        if (end == tok.c_str() || *end != '\0' || !std::isfinite(x) || errno == ERANGE)
+            rc = fail(CC_EINVAL, "%s: '%.40s' after %zu numbers is not a finite number", path, tok.c_str(),
+                      w.size());
+        else
             w.push_back(x);
-            p = end;
+        tok.clear();
+    };
+    for (int ch; (ch = fgetc(f)) != EOF && !rc;) {
+        if (line_start && ch == '#') comment = true;
+        line_start = ch == '\n';
+        if (ch == '\n') {
+            flush();
+            comment = false;
+        } else if (comment) {
+            continue;
+        } else if (ch == ' ' || ch == '\t' || ch == '\r') {
+            flush();
+        } else {
+            tok.push_back((char)ch);
         }
     }
+    flush();
     fclose(f);
+    if (rc) return rc;
     if ((int)w.size() != kNParams)
         return fail(CC_EINVAL, "%s holds %zu numbers, expected %d", path, w.size(), kNParams);
     return cc_router_set(w.data());

@@ -41,17 +41,18 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_defaults(lib):
-    assert lib.cc_version() == 10100
+    assert lib.cc_version() == 10200
     import paper_1607_06156_amd as ccmi
     opt = ccmi.Options()
     lib.cc_default_options(ctypes.byref(opt))
     assert opt.route == 0 and opt.max_passes == 0 and abs(opt.tau - 0.05) < 1e-15 and abs(opt.theta - 8.0) < 1e-15
+    assert opt.check == 0 and list(opt.reserved) == [0, 0, 0]
 
 
 def test_struct_layouts_match_header(lib):
     """The Python mirrors of cc_options / cc_stats have the C sizes."""
     import paper_1607_06156_amd as ccmi
-    # cc_options: 2 int32, 2 double, 2 int32, a pointer, an int64, 4 int32
+    # cc_options: 2 int32, 2 double, 2 int32, a pointer, an int64, check + 3 reserved int32
     assert ctypes.sizeof(ccmi.Options) == 8 + 16 + 8 + 8 + 8 + 16
     st = ccmi.Stats()
     assert ctypes.sizeof(st) % 8 == 0
@@ -138,6 +139,23 @@ def test_workspace_size_and_checks(lib):
     assert L.cc_label_ex(8, 8, 1000, 100, 8, None, ctypes.byref(opt), None) == -1
 
 
+def test_check_and_failure_hook_reject_bad_arguments_on_host(lib):
+    """cc_check_labels and cc_debug_fail_alloc validate on the host before
+    any device work; an empty vertex set with edges reports every edge out of
+    range without touching the device."""
+    import paper_1607_06156_amd as ccmi
+    L = ccmi.lib()
+    bad = (ctypes.c_int64 * 3)(7, 7, 7)
+    assert L.cc_check_labels(None, None, 0, 5, None, None, None) == -1          # NULL result
+    assert L.cc_check_labels(None, None, -1, 5, None, None, bad) == -1
+    assert L.cc_check_labels(None, None, 3, 5, 8, None, bad) == -1               # NULL edges
+    assert L.cc_check_labels(8, 8, 3, 5, None, None, bad) == -1                  # NULL labels
+    assert L.cc_check_labels(8, 8, 3, 0, None, None, bad) == 0 and list(bad) == [0, 0, 3]
+    assert L.cc_check_labels(None, None, 0, 0, None, None, bad) == 0 and list(bad) == [0, 0, 0]
+    assert L.cc_debug_fail_alloc(-1) == -1 and b"negative" in L.cc_last_error()
+    assert L.cc_debug_fail_alloc(0) == 0
+
+
 def test_label64_and_tuples_reject_bad_arguments_on_host(lib):
     import paper_1607_06156_amd as ccmi
     L = ccmi.lib()
@@ -165,6 +183,19 @@ def test_router_weights_file_roundtrip(lib, tmp_path):
     bad = tmp_path / "bad.txt"
     bad.write_text("1 2 3\n")
     assert lib.cc_router_load(str(bad).encode()) == -1
+    # one line far longer than any line buffer, CRLF ends, a comment in between
+    one = tmp_path / "one_line.txt"
+    one.write_text("# all on one line\r\n" + " ".join(f"{x:.9g}" for x in w[:-1]) + "\r\n# last\r\n"
+                   + f"{w[-1]:.9g}\r\n")
+    assert lib.cc_router_load(str(one).encode()) == 0, lib.cc_last_error()
+    # a token that is not a finite number is refused, naming it
+    for text, word in ((" ".join(["0.5"] * (ccmi.ROUTER_NPARAMS - 1)) + " nan\n", b"nan"),
+                       (" ".join(["0.5"] * (ccmi.ROUTER_NPARAMS - 1)) + " 1.5e99\n", b"1.5e99"),
+                       ("0.5 0.5x " + " ".join(["0.5"] * (ccmi.ROUTER_NPARAMS - 2)) + "\n", b"0.5x")):
+        bad.write_text(text)
+        assert lib.cc_router_load(str(bad).encode()) == -1
+        assert word in lib.cc_last_error()
+    assert lib.cc_router_loaded() == 1          # the weights loaded before stay
     lib.cc_router_set.argtypes = [ctypes.c_void_p]
     assert lib.cc_router_set(None) == 0 and lib.cc_router_loaded() == 0
 
