@@ -82,6 +82,8 @@ def main():
                     help="skip the batched (batch4096 vs per-graph launches) and router-vs-heuristic legs")
     ap.add_argument("--router-graphs", type=int, default=200,
                     help="held-out graphs of the router-vs-heuristic leg")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the measured ceilings (cc_measure_peaks: copy, random gathers, atomicMin)")
     ap.add_argument("--tuples", default="",
                     help="comma-separated workloads: time Algorithm 1 with radix sorts (cc_label_tuples) against "
                          "the atomic-hooking SV route, one JSON line each, and exit")
@@ -197,6 +199,22 @@ def main():
                                       "ms_csr", "ms_bfs", "ms_filter", "ms_sv", "ms_total"]},
         "forced_routes": extra,
     }
+    if not args.no_peaks:
+        # measured ceilings, outside the timed region, and the SV passes'
+        # random-access rates against them: parent[] is 4n bytes (64 MiB at
+        # scale 24, Infinity-Cache sized), every hook attempt is a returning
+        # atomicMin on it
+        pk = ccmi.measure_peaks()
+        sv_ms = float(np.sum([s["kernel_ms"][0] for s in stats])) / len(stats)
+        nat = float(np.mean([s["sv_atomics"] for s in stats]))
+        key = "mall_64MiB" if 4 * g.n > (2 << 20) and 4 * g.n <= (256 << 20) else \
+            ("l2_2MiB" if 4 * g.n <= (2 << 20) else "hbm_4GiB")
+        rec["measured_ceilings"] = pk
+        rec["sv_atomics"] = {"per_step": int(nat), "sv_pass_ms_per_step": round(sv_ms, 4),
+                             "Gps_over_sv_pass_time": round(nat / (sv_ms * 1e-3) / 1e9, 3) if sv_ms else None,
+                             "ceiling_table": key, "ceiling_Gps": pk["atomicmin_Gps"][key]}
+        log(f"[bench] ceilings: copy {pk['copy_GBps']} GB/s, gathers {pk['gather_Gps']} G/s, "
+            f"atomicMin {pk['atomicmin_Gps']} G/s")
     if not args.no_extras:
         # the other targets, outside the timed region: batched mode against
         # per-graph launches on the 4096-graph batch (every graph checked

@@ -389,6 +389,27 @@ int cc_release_workspace(void);
  * work as on first use. */
 int cc_shutdown(void);
 
+/* ------------------------------------------------------- measured ceilings */
+
+/* What the device sustains, measured now on `stream` (about a second; it
+ * allocates and frees about 6 GiB).  The kernels' rates are compared with
+ * these besides the published HBM peak: the SV pass's parent[] gathers and
+ * hooks are random 4-byte accesses, its largest-tree probes hit a bitmap in
+ * L2, and neither streams. */
+typedef struct cc_peaks {
+    double copy_gbps;          /* streaming 16-byte copy of 1 GiB: bytes read + written per second / 1e9
+                                  (best of a plain, a 4-in-flight and a non-temporal form) */
+    double copy_bytes;         /* bytes moved per copy launch (read + written) */
+    double read_gbps;          /* streaming read of 1 GiB (best of a plain and a non-temporal form) */
+    int64_t table_bytes[3];    /* table sizes: 2 MiB (fits one XCD's L2), 64 MiB (Infinity Cache), 4 GiB (HBM) */
+    double gather_gps[3];      /* random 4-byte loads per second / 1e9, per table */
+    double atomic_gps[3];      /* random agent-scope atomicMin with the old value returned, per second / 1e9 */
+    double accesses;           /* random accesses per launch (8 in flight per thread) */
+} cc_peaks;
+/* Errors: CC_EINVAL (NULL out), CC_ENOMEM, CC_EHIP.  Best of five launches
+ * after a warm-up for each figure. */
+int cc_measure_peaks(cc_peaks* out, void* stream);
+
 /* ------------------------------------------------------------ checking */
 
 /* Checks a labelling on the device against the invariants every exact

@@ -96,6 +96,12 @@ class BatchStats(ctypes.Structure):
                 ("survivors_written", ctypes.c_int64)]
 
 
+class Peaks(ctypes.Structure):
+    _fields_ = [("copy_gbps", ctypes.c_double), ("copy_bytes", ctypes.c_double), ("read_gbps", ctypes.c_double),
+                ("table_bytes", ctypes.c_int64 * 3), ("gather_gps", ctypes.c_double * 3),
+                ("atomic_gps", ctypes.c_double * 3), ("accesses", ctypes.c_double)]
+
+
 _lib = None
 _VP = ctypes.c_void_p
 
@@ -140,6 +146,7 @@ def lib():
             "cc_check_labels": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP,
                                                ctypes.POINTER(ctypes.c_int64)]),
             "cc_debug_fail_alloc": (ctypes.c_int, [ctypes.c_int64]),
+            "cc_measure_peaks": (ctypes.c_int, [ctypes.POINTER(Peaks), _VP]),
             "cc_label_tuples": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _VP, ctypes.c_int32,
                                                ctypes.POINTER(TupleStats)]),
             "cc_label64": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP,
@@ -236,6 +243,19 @@ def check_labels(u: torch.Tensor, v: torch.Tensor, n: int, labels: torch.Tensor)
     _check(lib().cc_check_labels(_dev(u, torch.int32, "u"), _dev(v, torch.int32, "v"), m, n,
                                  _dev(labels, torch.int32, "labels"), _stream(), bad))
     return {"edges_split": int(bad[0]), "vertices_bad": int(bad[1]), "edges_out_of_range": int(bad[2])}
+
+
+def measure_peaks() -> dict:
+    """Measured ceilings of the current device (cc_measure_peaks): copy GB/s,
+    and random gathers / returning atomicMin (G/s) on L2-, Infinity-Cache- and
+    HBM-sized tables."""
+    p = Peaks()
+    _check(lib().cc_measure_peaks(ctypes.byref(p), _stream()))
+    names = ("l2_2MiB", "mall_64MiB", "hbm_4GiB")
+    return {"copy_GBps": round(p.copy_gbps, 1), "read_GBps": round(p.read_gbps, 1),
+            "gather_Gps": {nm: round(p.gather_gps[k], 2) for k, nm in enumerate(names)},
+            "atomicmin_Gps": {nm: round(p.atomic_gps[k], 2) for k, nm in enumerate(names)},
+            "table_bytes": [int(x) for x in p.table_bytes], "accesses_per_launch": int(p.accesses)}
 
 
 def debug_fail_alloc(nth: int) -> None:

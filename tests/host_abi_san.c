@@ -139,6 +139,8 @@ int main(int argc, char** argv) {
     EXPECT(cc_debug_fail_alloc(5), CC_OK);
     EXPECT(cc_debug_fail_alloc(0), CC_OK);
 
+    EXPECT(cc_measure_peaks(NULL, NULL), CC_EINVAL);
+
     /* step entry points */
     EXPECT(cc_degree(P, P, -1, 5, P, NULL), CC_EINVAL);
     EXPECT(cc_degree(NULL, P, 4, 5, P, NULL), CC_EINVAL);

@@ -70,7 +70,7 @@ def test_struct_layouts_match_compiled_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     mirrors = {"cc_options": ccmi.Options, "cc_stats": ccmi.Stats, "cc_batch_stats": ccmi.BatchStats,
-               "cc_tuple_stats": ccmi.TupleStats}
+               "cc_tuple_stats": ccmi.TupleStats, "cc_peaks": ccmi.Peaks}
     lines = []
     for cname, py in mirrors.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -154,6 +154,7 @@ def test_check_and_failure_hook_reject_bad_arguments_on_host(lib):
     assert L.cc_check_labels(None, None, 0, 0, None, None, bad) == 0 and list(bad) == [0, 0, 0]
     assert L.cc_debug_fail_alloc(-1) == -1 and b"negative" in L.cc_last_error()
     assert L.cc_debug_fail_alloc(0) == 0
+    assert L.cc_measure_peaks(None, None) == -1
 
 
 def test_label64_and_tuples_reject_bad_arguments_on_host(lib):

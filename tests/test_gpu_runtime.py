@@ -202,3 +202,19 @@ def test_threads_with_their_own_workspaces():
         t.join(timeout=180)
     assert not any(t.is_alive() for t in ts)
     assert not errors, errors
+
+
+def test_measured_ceilings():
+    """cc_measure_peaks: every figure positive and below what the chip could
+    ever do (copy under 9 TB/s), and random access slows as the table leaves
+    the L2 and then the Infinity Cache."""
+    say("[gpu] measured ceilings")
+    pk = ccmi.measure_peaks()
+    assert 100.0 < pk["copy_GBps"] < 9000.0, pk
+    g, a = pk["gather_Gps"], pk["atomicmin_Gps"]
+    assert all(x > 0 for x in list(g.values()) + list(a.values())), pk
+    assert g["l2_2MiB"] > g["hbm_4GiB"] and a["l2_2MiB"] > a["hbm_4GiB"], pk
+    assert pk["table_bytes"] == [2 << 20, 64 << 20, 4 << 30]
+    # the device still labels correctly afterwards
+    gr = gen.workload("rmat16")
+    assert_labels_equal(ccmi.label(to_dev(gr.u), to_dev(gr.v), gr.n, route="sv"), oracle_labels(gr), "after peaks")
