@@ -129,6 +129,36 @@ def test_dense_and_deep_graphs():
         assert np.array_equal(run_batch(b, **kw).cpu().numpy(), exp), kw
 
 
+def test_large_mixed_batch():
+    """A batch of 5.8 M edges: Kronecker graphs, G(n,m) graphs, ordered
+    paths (ids and edge order follow the path: deep chains within the first
+    pass) and permuted paths, every graph against the oracle, with the
+    autotuned shape and with one hook attempt per pass; the byte model's
+    read count covers every edge once plus the survivors."""
+    graphs = []
+    for s in range(3):
+        g = gen.rmat(16, 16, seed=70 + s)
+        graphs.append((g.u, g.v, g.n))
+        g = gen.gnm(1 << 17, 3 << 17, seed=80 + s)
+        graphs.append((g.u, g.v, g.n))
+    for s in range(2):
+        n = 400_000 + 1234 * s
+        ids = np.arange(n, dtype=np.int32)
+        graphs.append((ids[:-1], ids[1:], n))
+        pi = gen.permutation(n, seed=90 + s)
+        graphs.append((pi[:-1], pi[1:], n))
+    b = _manual(graphs)
+    m = int(b.edge_off[-1])
+    assert m >= 1 << 22
+    exp = expected(b)
+    for kw in [{}, {"max_link": 1}]:
+        lab, st = run_batch(b, stats=True, **kw)
+        say(f"   passes={st['passes']} blocks={st['blocks']} chase={st['chase_reads']} ms={st['ms_total']:.3f}")
+        assert st["blocks"] > 0
+        assert np.array_equal(lab.cpu().numpy(), exp), kw
+        assert st["edges_read"] == m + st["survivors_written"]
+
+
 def test_barrier_timeout_falls_back_to_union(monkeypatch):
     """A grid barrier that waits past its spin limit (here forced from the
     host: a limit of one 100 MHz tick, so every early workgroup gives up and
