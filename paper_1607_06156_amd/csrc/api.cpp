@@ -254,7 +254,7 @@ size_t workspace_bound(int64_t m, int32_t n, bool sv_only, size_t* per_slot) {
         BucketPlan p;
         if (bucket_plan(n, m, &p) == 0 && m < ((int64_t)1 << 31)) {
             const size_t counts = align256((size_t)p.nblk * p.B * sizeof(uint32_t));
-            b[WS_HIST] = counts + (size_t)(2 * p.B + 2) * sizeof(unsigned long long) +
+            b[WS_HIST] = counts + (size_t)(2 * p.B + 3) * sizeof(unsigned long long) +
                          (size_t)p.B * kGroups * sizeof(uint32_t);
             b[WS_CURSOR] = 16 * M;   // two-level scatter with the other ends, CSR regroup, the rest's arrays
             b[WS_QUEUE] = align256(2 * M * sizeof(uint16_t)) + 2 * M * sizeof(int32_t);

@@ -180,11 +180,20 @@ static_assert(StageCfg<false>::kSlots <= 65536 && StageCfg<true>::kSlots <= 6553
 // Each block walks G consecutive edge chunks (their runs are consecutive in
 // the prefix layout, so the cursors simply continue).  The next tile's edges
 // are loaded while the current tile is staged and written out.
-template <bool OTHER, bool SUPER>
+//
+// CAP (degrees only, one level): no count pass runs first.  Block b's run in
+// bucket k starts at slot (k * gridDim + b) * cap and holds at most cap
+// entries; the block writes how many it filled to runcnt[k * gridDim + b],
+// counts the edges with an id outside [0, n) into err[0], and sets err[1]
+// if some run would have outgrown cap (the entries that did not fit are not
+// written; the caller then runs the counted layout instead).
+template <bool OTHER, bool SUPER, bool CAP = false>
 __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m, int32_t n, int64_t chunk, int32_t G,
     int32_t B, int32_t nblk, const uint32_t* __restrict__ prefix, const unsigned long long* __restrict__ base,
-    uint16_t* __restrict__ loc, uint32_t* __restrict__ loc32, int32_t* __restrict__ other) {
+    uint16_t* __restrict__ loc, uint32_t* __restrict__ loc32, int32_t* __restrict__ other, uint32_t cap = 0,
+    uint32_t* __restrict__ runcnt = nullptr, unsigned long long* __restrict__ err = nullptr) {
+    static_assert(!CAP || (!OTHER && !SUPER), "the capped layout is for one-level degree passes");
     constexpr int E = StageCfg<OTHER>::kEdges;
     constexpr int kSh = SUPER ? kSuperShift : kShift;      // staging bucket = id >> kSh
     constexpr int kKeyShift = SUPER ? kSuperShift : 16;    // key = staging bucket << kKeyShift | local
@@ -203,6 +212,7 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
     // their cursors.  Output positions are below 2m < 2^32 (m < 2^31 is
     // checked by bucket_plan), so 32-bit slot arithmetic is exact.
     auto first_slot = [&](int k) -> uint32_t {
+        if (CAP) return ((uint32_t)k * gridDim.x + blockIdx.x) * cap;
         if (SUPER) {
             // chunk c0's first slot in super-bucket k: its first bucket's start
             // plus what the chunks before c0 put into each of its buckets
@@ -226,6 +236,8 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
         a[j] = i < end ? u[i] : -1;
         c[j] = i < end ? v[i] : -1;
     }
+    uint32_t nbad = 0;     // CAP: edges of this thread with an id outside [0, n)
+    bool spill = false;    // CAP: an entry did not fit its run
     for (int64_t t0 = beg; t0 < end; t0 += kTile) {
         for (int k = t; k <= NB; k += kStageThreads) toff[k] = 0;
         __syncthreads();
@@ -239,6 +251,8 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
             if ((uint32_t)a[j] < (uint32_t)n && (uint32_t)c[j] < (uint32_t)n) {
                 okm |= 1u << j;
                 r[j] = atomicAdd(&toff[a[j] >> kSh], 1u) | (atomicAdd(&toff[c[j] >> kSh], 1u) << 16);
+            } else if (CAP && t0 + t + (int64_t)j * kStageThreads < end) {
+                ++nbad;
             }
         }
         __syncthreads();
@@ -303,11 +317,30 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
         for (uint32_t i = t; i < total; i += kStageThreads) {
             const uint32_t q = stage[i];
             const uint64_t pos = (uint32_t)(rb[q >> kKeyShift] + i);
+            if (CAP) {
+                // the run of bucket k ends where block b + 1's begins
+                const uint32_t lim = ((q >> kKeyShift) * gridDim.x + blockIdx.x + 1) * cap;
+                if (pos < lim) loc[pos] = (uint16_t)(q & kLocalMask);
+                else spill = true;
+                continue;
+            }
             if (SUPER) loc32[pos] = q & kLocalMask;
             else loc[pos] = (uint16_t)(q & kLocalMask);
             if (OTHER) other[pos] = stage_o[i];
         }
         __syncthreads();
+    }
+    if (CAP) {
+        // fill counts of this block's runs (thread t owns buckets 2t, 2t + 1)
+        for (int k = 2 * t; k < 2 * t + 2 && k < NB; ++k) {
+            const uint32_t used = run[k] - first_slot(k);
+            runcnt[(int64_t)k * gridDim.x + blockIdx.x] = used < cap ? used : cap;
+            spill |= used > cap;
+        }
+        for (int o = 32; o > 0; o >>= 1) nbad += __shfl_xor(nbad, o);
+        if (lane_id() == 0 && nbad) atomic_add_agent(&err[0], (unsigned long long)nbad);
+        if (ballot(spill) && lane_id() == 0)
+            __hip_atomic_store(&err[1], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -501,13 +534,29 @@ __device__ __forceinline__ void count8_hot(uint32_t* cnt, uint4 w, uint32_t& hot
     count_hot(cnt, w.w >> 16, hot);
 }
 
+// Like count8_hot for the capped layout: entries at or past `valid` (0..8)
+// of this 8-entry group count into the spare counter cnt[kBsz].
+__device__ __forceinline__ void count8_hot_masked(uint32_t* cnt, uint4 w, uint32_t valid, uint32_t& hot) {
+    const uint32_t x[8] = {w.x & 0xffffu, w.x >> 16, w.y & 0xffffu, w.y >> 16,
+                           w.z & 0xffffu, w.z >> 16, w.w & 0xffffu, w.w >> 16};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) count_hot(cnt, (uint32_t)e < valid ? x[e] : (uint32_t)kBsz, hot);
+}
+
+constexpr int kMaxRuns = 1024;   // scatter blocks of a capped layout
+
+// runcnt != nullptr: the capped layout of bucket_scatter_staged_kernel<.., CAP>
+// (nruns runs of up to cap entries, cap a multiple of 8); base is unused then.
 __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     const uint16_t* __restrict__ loc, const unsigned long long* __restrict__ base, int32_t n,
     int32_t* __restrict__ deg, int count_pairs, int want_hist, unsigned long long* __restrict__ hist64,
     unsigned long long* __restrict__ histx, int32_t* __restrict__ tail, int64_t tail_cap,
     unsigned long long* __restrict__ tail_count, unsigned long long* __restrict__ argmax_key, int want_off,
-    int64_t* __restrict__ off, uint32_t* __restrict__ gcnt) {
-    __shared__ uint32_t cnt[kBsz];
+    int64_t* __restrict__ off, uint32_t* __restrict__ gcnt, const uint32_t* __restrict__ runcnt = nullptr,
+    int32_t nruns = 0, uint32_t cap = 0) {
+    __shared__ uint32_t cnt[kBsz + 1];   // + a spare counter for masked entries (capped layout)
+    __shared__ uint32_t rp[kMaxRuns + 1];
+    __shared__ uint32_t rc[kMaxRuns];
     __shared__ HistLds L;
     __shared__ uint32_t wsum[kBlockD / 64];
     const int k = blockIdx.x;
@@ -518,12 +567,65 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     for (int j = threadIdx.x; j < kExactBins; j += kBlockD) L.hx[j] = 0;
     if (threadIdx.x < 64) L.h64[threadIdx.x] = 0;
     __syncthreads();
-    const unsigned long long beg = base[k], end = base[k + 1];
+    if (threadIdx.x == 0) cnt[kBsz] = 0;
+    if (runcnt && count_pairs) {
+        // capped layout: run r of this bucket is ceil(runcnt / 8) groups of 8
+        // entries from group (k * nruns + r) * cap / 8; rp[] is the prefix of
+        // those group counts, so group j of the bucket lies in the run r with
+        // rp[r] <= j < rp[r + 1]
+        const int t = threadIdx.x;
+        const uint32_t rcnt = t < nruns ? runcnt[(int64_t)k * nruns + t] : 0u;
+        if (t < nruns) rc[t] = rcnt;
+        const uint32_t len = (rcnt + 7) / 8;
+        uint32_t incl = len;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (lane_id() >= o) incl += y;
+        }
+        if (lane_id() == 63) wsum[t >> 6] = incl;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < (t >> 6); ++w) before += wsum[w];
+        if (t < nruns) rp[t] = before + incl - len;
+        if (t == kBlockD - 1) rp[nruns] = before + incl;   // nruns <= kBlockD: the total
+        __syncthreads();
+        const uint32_t Q = rp[nruns];
+        const uint4* q4 = (const uint4*)loc;
+        const uint32_t gpr = cap / 8;   // groups per run slot
+        uint32_t hot = 0xffffffffu;
+        constexpr uint32_t kStep = (uint32_t)kBlockD * kUnrollD;
+        // The groups j of a thread only increase, so its run index `cur`
+        // only moves forward (runs hold about 500 groups, a thread's j
+        // advances by 1024 per slot: a few LDS reads per load).  Every lane
+        // runs every iteration (the bound is uniform); groups past Q count
+        // into the spare counter.
+        int cur = 0;
+        for (uint32_t j0 = 0; j0 < Q; j0 += kStep) {
+            uint4 w[kUnrollD];
+            uint32_t nv8[kUnrollD];
+#pragma unroll
+            for (int r = 0; r < kUnrollD; ++r) {
+                const uint32_t j = j0 + t + (uint32_t)r * kBlockD;
+                w[r] = make_uint4(0, 0, 0, 0);
+                nv8[r] = 0;
+                if (j < Q) {
+                    while (rp[cur + 1] <= j) ++cur;   // rp[nruns] = Q > j ends it
+                    const uint32_t within = j - rp[cur];
+                    const uint32_t c = rc[cur] - within * 8;
+                    nv8[r] = c < 8 ? c : 8;
+                    w[r] = q4[((uint64_t)k * nruns + cur) * gpr + within];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kUnrollD; ++r) count8_hot_masked(cnt, w[r], nv8[r], hot);
+        }
+    }
+    const unsigned long long beg = runcnt ? 0ull : base[k], end = runcnt ? 0ull : base[k + 1];
     if (!count_pairs) {
         // degrees already known (an earlier pass): only the offsets are wanted
         for (int j = threadIdx.x; j < nv; j += kBlockD) cnt[j] = (uint32_t)deg[x0 + j];
     }
-    if (count_pairs) {
+    if (count_pairs && !runcnt) {
         // 16-byte loads of eight ids between the first and last multiple of 8
         // (loc is 256-byte aligned), kUnrollD of them in flight per thread:
         // one block fills a CU, so the loads in flight must cover HBM latency
@@ -911,8 +1013,17 @@ static hipError_t launch_csr_fill(int64_t m, int32_t n, const BucketPlan& p, con
     return hipGetLastError();
 }
 
+static void count_and_scan(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
+                           BucketBufs& w, hipStream_t s);
+
 hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
                                       BucketBufs& w, int32_t* deg, int64_t* off, int32_t* adj, hipStream_t s) {
+    if (!w.counted) {
+        // the degree pass used the capped layout: count and scan first (the
+        // ids were checked then; the error counter only grows)
+        count_and_scan(u, v, m, n, p, w, s);
+        w.other_written = false;
+    }
     if (!w.other_written) {
         // the degree pass kept only the local ids: scatter again with the
         // other endpoints.  Both arrays are rewritten together, because the
@@ -927,11 +1038,28 @@ hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_
     return e != hipSuccess ? e : launch_csr_fill(m, n, p, w, off, adj, s);
 }
 
-hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
-                                BucketBufs& w, int32_t* deg, int want_hist, unsigned long long* hist64,
-                                unsigned long long* histx, int32_t* tail, int64_t tail_cap,
-                                unsigned long long* tail_count, unsigned long long* argmax_key, int want_csr,
-                                int64_t* off, int32_t* adj, hipStream_t s) {
+// Grid and run capacity of the capped layout, or false when it does not
+// apply: CSR builds and two-level passes take the counted layout, and so do
+// lists whose capped runs would not fit the loc buffer or 32-bit slots.  A
+// run holds twice its bucket's average share of the block's endpoints plus
+// 256: a hub of a third of its bucket's entries still fits.
+static bool capped_plan(int64_t m, const BucketPlan& p, const BucketBufs& w, int* grid, uint32_t* cap) {
+    if (p.B > kStagedMaxB || m < ((int64_t)1 << 20)) return false;
+    const int G = p.nblk >= 2 * kCUs ? p.nblk / kCUs : 1;
+    const int g = (p.nblk + G - 1) / G;
+    if (g > kMaxRuns) return false;
+    const int64_t per_block = 2 * (int64_t)G * p.chunk;   // endpoints of a block's edges (at most)
+    const int64_t c = ((2 * per_block / p.B + 256) + 7) & ~(int64_t)7;
+    const int64_t slots = (int64_t)g * p.B * c;
+    if (slots + per_block >= ((int64_t)1 << 32) || slots > w.loc_cap) return false;   // 32-bit slot arithmetic
+    *grid = g;
+    *cap = (uint32_t)c;
+    return true;
+}
+
+// pass A and the prefixes of the counted layout
+static void count_and_scan(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
+                           BucketBufs& w, hipStream_t s) {
     const size_t lds = (size_t)p.B * sizeof(uint32_t);
     if ((((uintptr_t)u | (uintptr_t)v) & 15) == 0)
         bucket_count_kernel<true><<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.counts, w.err);
@@ -939,6 +1067,31 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
         bucket_count_kernel<false><<<p.nblk, kBlock, lds, s>>>(u, v, m, n, p.chunk, p.B, w.counts, w.err);
     bucket_colscan_kernel<<<p.B, kScanThreads, 0, s>>>(w.counts, p.nblk, w.tot);
     bucket_scan_kernel<<<1, 1024, 0, s>>>(w.tot, p.B, w.base);
+    w.counted = true;
+}
+
+hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
+                                BucketBufs& w, int32_t* deg, int want_hist, unsigned long long* hist64,
+                                unsigned long long* histx, int32_t* tail, int64_t tail_cap,
+                                unsigned long long* tail_count, unsigned long long* argmax_key, int want_csr,
+                                int64_t* off, int32_t* adj, hipStream_t s, bool allow_capped) {
+    int grid = 0;
+    uint32_t cap = 0;
+    if (allow_capped && !want_csr && capped_plan(m, p, w, &grid, &cap)) {
+        // no count pass: each scatter block fills runs of fixed capacity
+        const int G = p.nblk >= 2 * kCUs ? p.nblk / kCUs : 1;
+        bucket_scatter_staged_kernel<false, false, true><<<grid, kStageThreads, 0, s>>>(
+            u, v, m, n, p.chunk, G, p.B, p.nblk, nullptr, nullptr, w.loc, nullptr, nullptr, cap, w.counts, w.err);
+        w.counted = false;
+        w.other_written = false;
+        bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, nullptr, n, deg, 1, want_hist, hist64, histx, tail,
+                                                      tail_cap, tail_count, argmax_key, 0, nullptr, nullptr,
+                                                      w.counts, grid, cap);
+        return hipGetLastError();
+    }
+    const size_t lds = (size_t)p.B * sizeof(uint32_t);
+    (void)lds;
+    count_and_scan(u, v, m, n, p, w, s);
     hipError_t e = launch_scatter(u, v, m, n, p, w, want_csr != 0, s);
     if (e != hipSuccess) return e;
     w.other_written = want_csr != 0;

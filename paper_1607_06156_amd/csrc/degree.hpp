@@ -32,7 +32,9 @@ struct BucketBufs {
     int32_t* tother;             // [2m]
     unsigned long long* err;     // range errors
     uint32_t* gcnt;              // [B * kGroups] CSR fill: entries of each group placed so far
+    int64_t loc_cap = 0;         // 16-bit entries loc can hold (the capped layout needs more than 2m)
     bool other_written = false;
+    bool counted = false;        // counts / tot / base hold the counted layout's prefixes
 };
 
 // returns -1 if n is too large for the bucketed pass or m >= 2^31 (the
@@ -41,11 +43,15 @@ int bucket_plan(int32_t n, int64_t m, BucketPlan* p);
 
 // deg[n] (+ histograms when want_hist, + CSR off[n+1]/adj[2m] when want_csr).
 // hist64/histx/tail_count/argmax_key must be zeroed by the caller.
+// Degrees-only passes (want_csr = 0, allow_capped) may take the capped
+// layout, which skips the count pass; err[1] (err must hold two words, both
+// zeroed) then reports whether a run overflowed its capacity, in which case
+// the results are void and the pass must be run again with allow_capped off.
 hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
                                 BucketBufs& w, int32_t* deg, int want_hist, unsigned long long* hist64,
                                 unsigned long long* histx, int32_t* tail, int64_t tail_cap,
                                 unsigned long long* tail_count, unsigned long long* argmax_key, int want_csr,
-                                int64_t* off, int32_t* adj, hipStream_t s);
+                                int64_t* off, int32_t* adj, hipStream_t s, bool allow_capped = false);
 
 // CSR from an earlier launch_bucket_degree's buckets and deg[] (no recount);
 // scatters the other endpoints first if that pass did not

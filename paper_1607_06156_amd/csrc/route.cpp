@@ -47,7 +47,7 @@ static void set_cursor_bufs(BucketBufs* w, void* po, int64_t m, bool csr) {
 // at the start, the tail prefetch (up to kTailPrefetch entries) at this offset.
 constexpr size_t kTailPrefetchOff = 64 * 1024;
 constexpr int64_t kTailPrefetch = 16 * 1024;
-static_assert((64 + kExactBins + 3) * sizeof(unsigned long long) <= kTailPrefetchOff, "staging overlap");
+static_assert((64 + kExactBins + 4) * sizeof(unsigned long long) <= kTailPrefetchOff, "staging overlap");
 static_assert(kTailPrefetchOff + kTailPrefetch * sizeof(int32_t) <= Workspace::kHostBytes, "staging size");
 
 int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
@@ -62,7 +62,7 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     // WS_HIST: per-block bucket counts, then (8-byte aligned) totals, bases,
     // error counter, then the CSR fill's per-group counters
     const size_t counts_bytes = ((size_t)p.nblk * p.B * sizeof(uint32_t) + 255) & ~(size_t)255;
-    const size_t tot_bytes = (size_t)(2 * p.B + 2) * sizeof(unsigned long long);
+    const size_t tot_bytes = (size_t)(2 * p.B + 3) * sizeof(unsigned long long);
     if ((rc = ws.get(WS_HIST, counts_bytes + tot_bytes + (size_t)p.B * kGroups * sizeof(uint32_t), &pc))) return rc;
     if (p.B > kStagedMaxB || want_csr) {
         // the first level of the two-level scatter (32-bit ids, + other ends
@@ -86,6 +86,8 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     set_cursor_bufs(&w, po, m, want_csr);
     w.loc = (uint16_t*)pp;
     w.other = (int32_t*)((char*)pp + loc_bytes);
+    // without a CSR the other ends' space is free: the capped layout may use it
+    w.loc_cap = want_csr ? 2 * m : (int64_t)((loc_bytes + (size_t)2 * m * sizeof(int32_t)) / sizeof(uint16_t));
     r->bufs = w;
     r->deg = c.deg_out ? c.deg_out : (int32_t*)pdeg;
     r->tail = (int32_t*)ptail;
@@ -98,9 +100,7 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     unsigned long long* tail_count = histx + kExactBins;
     unsigned long long* argmax_key = tail_count + 1;
     r->hist64_dev = hist64;
-    hipError_t e = hipMemsetAsync(ph, 0, (64 + kExactBins + 4) * sizeof(unsigned long long), c.stream);
-    if (e == hipSuccess) e = hipMemsetAsync(w.err, 0, sizeof(unsigned long long), c.stream);
-    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    hipError_t e;
     int64_t* off = nullptr;
     int32_t* adj = nullptr;
     if (want_csr) {
@@ -117,23 +117,30 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
         r->off = off;
         r->adj = adj;
     }
+    unsigned long long* host;
+    if ((rc = ws.pinned((void**)&host))) return rc;
+    // The capped layout (no count pass) first; if one of its runs overflowed
+    // (a hub far above its bucket's share), the counted layout again.
+    for (int attempt = 0;; ++attempt) {
+    e = hipMemsetAsync(ph, 0, (64 + kExactBins + 4) * sizeof(unsigned long long), c.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w.err, 0, 2 * sizeof(unsigned long long), c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
     int k0 = c.kbeg();
     e = launch_bucket_degree(c.u, c.v, m, c.n, p, w, r->deg, 1, hist64, histx, r->tail, tail_cap, tail_count,
-                             argmax_key, want_csr ? 1 : 0, off, adj, c.stream);
+                             argmax_key, want_csr ? 1 : 0, off, adj, c.stream, attempt == 0);
     if (e != hipSuccess) return hip_fail(e, "degree pass launch");
+    r->bufs = w;
     // algorithmic bytes: edges read (8 B), degrees written and histogrammed (8 B per vertex),
     // plus the CSR (8 B per adjacency entry written, 8 B per offset)
     c.kend(CC_K_DEGREE, k0, 8.0 * m + 8.0 * c.n + (want_csr ? 16.0 * m + 8.0 * c.n : 0.0));
     if (c.stats) c.bytes += 8.0 * m + 8.0 * c.n + (want_csr ? 16.0 * m + 8.0 * c.n : 0.0);
     r->csr_built = want_csr;
     // read back histograms + counters
-    unsigned long long* host;
-    if ((rc = ws.pinned((void**)&host))) return rc;
     e = hipMemcpyAsync(host, ph, (64 + kExactBins + 2) * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                        c.stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(host + 64 + kExactBins + 2, w.err, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                           c.stream);
+        e = hipMemcpyAsync(host + 64 + kExactBins + 2, w.err, 2 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, c.stream);
     // the route decision needs the tail too: its first entries come back in
     // the same round trip (the tail count is not known before it)
     r->tail_host = nullptr;
@@ -147,6 +154,8 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(hist)");
     e = hipStreamSynchronize(c.stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (host[64 + kExactBins + 3] == 0 || attempt > 0) break;
+    }
     if (host[64 + kExactBins + 2])
         return fail(CC_ERANGE, "%llu edges have an endpoint outside [0, n)", host[64 + kExactBins + 2]);
     for (int i = 0; i < 64; ++i) r->hist64[i] = (int64_t)host[i];

@@ -403,3 +403,37 @@ def test_small_frontiers_run_in_one_workgroup():
     lab, st = ccmi.label(to_dev(star.u), to_dev(star.v), star.n, route="bfs+sv", stats=True)
     assert_labels_equal(lab, np.zeros(star.n, np.int32), "star via bfs+sv")
     assert st["route"] == ccmi.R0_BFS_SV and st["bfs_levels"] == 2 and st["bfs_visited"] == star.n
+
+
+def test_degree_pass_without_count_pass():
+    """Degree passes of 2^20 edges or more that need no CSR skip the count
+    pass: each scatter block fills runs of fixed capacity.  Exact degrees and
+    histograms on a Kronecker graph; a star whose hub overflows every run
+    (the pass then runs again with the counted layout); an exact count of
+    ids out of range; and the BFS route after such a prediction (its CSR
+    needs the counted prefixes, built then)."""
+    g = gen.workload("rmat18noisy")
+    say("[gpu] capped degree pass rmat18noisy")
+    d = ccmi.degree(to_dev(g.u), to_dev(g.v), g.n)
+    assert np.array_equal(d.cpu().numpy(), odeg.degree(g.u, g.v, g.n))
+    leaves = 1 << 21
+    star = gen.Graph(np.zeros(leaves, np.int32), np.arange(1, leaves + 1, dtype=np.int32), leaves + 1, "star")
+    say("[gpu] capped degree pass, star (overflow)")
+    d = ccmi.degree(to_dev(star.u), to_dev(star.v), star.n)
+    assert np.array_equal(d.cpu().numpy(), odeg.degree(star.u, star.v, star.n))
+    lab, st = ccmi.label(to_dev(star.u), to_dev(star.v), star.n, route="heuristic", stats=True)
+    assert_labels_equal(lab, np.zeros(star.n, np.int32), "star heuristic")
+    assert st["max_degree"] == leaves
+    # three edges out of range, counted exactly by the scatter
+    u, v = g.u.copy(), g.v.copy()
+    u[[5, 70_000, 3_000_000]] = [g.n, -1, g.n + 7]
+    with pytest.raises(ccmi.CCError) as ei:
+        ccmi.degree(to_dev(u), to_dev(v), g.n)
+    assert ei.value.code == ccmi.CC_ERANGE and "3 edges" in str(ei.value)
+    with pytest.raises(ccmi.CCError) as ei:
+        ccmi.label(to_dev(u), to_dev(v), g.n, route="heuristic")
+    assert ei.value.code == ccmi.CC_ERANGE
+    # the heuristic made to pick the BFS route: its CSR after a capped pass
+    lab, st = ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route="heuristic", tau=1e300, stats=True)
+    assert st["route"] == ccmi.R0_BFS_SV
+    assert_labels_equal(lab, oracle_labels(g), "rmat18noisy heuristic")
