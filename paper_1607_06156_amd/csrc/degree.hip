@@ -553,7 +553,8 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     unsigned long long* __restrict__ histx, int32_t* __restrict__ tail, int64_t tail_cap,
     unsigned long long* __restrict__ tail_count, unsigned long long* __restrict__ argmax_key, int want_off,
     int64_t* __restrict__ off, uint32_t* __restrict__ gcnt, const uint32_t* __restrict__ runcnt = nullptr,
-    int32_t nruns = 0, uint32_t cap = 0) {
+    int32_t nruns = 0, uint32_t cap = 0, const int32_t* __restrict__ du = nullptr,
+    const int32_t* __restrict__ dv = nullptr, int64_t dm = 0, unsigned long long* __restrict__ derr = nullptr) {
     __shared__ uint32_t cnt[kBsz + 1];   // + a spare counter for masked entries (capped layout)
     __shared__ uint32_t rp[kMaxRuns + 1];
     __shared__ uint32_t rc[kMaxRuns];
@@ -568,6 +569,34 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     if (threadIdx.x < 64) L.h64[threadIdx.x] = 0;
     __syncthreads();
     if (threadIdx.x == 0) cnt[kBsz] = 0;
+    if (du && count_pairs) {
+        // direct (small lists): every block reads the whole edge list and
+        // counts the endpoints in its bucket; the others go to the spare
+        // counter, so every lane of a wave stays in count_hot.  Block 0
+        // counts the edges with an id outside [0, n).
+        __syncthreads();
+        uint32_t hot = 0xffffffffu, bad = 0;
+        constexpr int kU = 4;
+        for (int64_t i0 = 0; i0 < dm; i0 += (int64_t)kBlockD * kU) {
+            int32_t a[kU], c[kU];
+#pragma unroll
+            for (int r = 0; r < kU; ++r) {
+                const int64_t i = i0 + threadIdx.x + (int64_t)r * kBlockD;
+                a[r] = i < dm ? du[i] : -1;
+                c[r] = i < dm ? dv[i] : -1;
+                if (k == 0 && i < dm && ((uint32_t)a[r] >= (uint32_t)n || (uint32_t)c[r] >= (uint32_t)n)) ++bad;
+            }
+#pragma unroll
+            for (int r = 0; r < kU; ++r) {
+                const bool ok = (uint32_t)a[r] < (uint32_t)n && (uint32_t)c[r] < (uint32_t)n;
+                const uint32_t la = (uint32_t)(a[r] - x0), lc = (uint32_t)(c[r] - x0);
+                count_hot(cnt, ok && la < (uint32_t)nv ? la : (uint32_t)kBsz, hot);
+                count_hot(cnt, ok && lc < (uint32_t)nv ? lc : (uint32_t)kBsz, hot);
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o);
+        if (lane_id() == 0 && bad) atomic_add_agent(derr, (unsigned long long)bad);
+    }
     if (runcnt && count_pairs) {
         // capped layout: run r of this bucket is ceil(runcnt / 8) groups of 8
         // entries from group (k * nruns + r) * cap / 8; rp[] is the prefix of
@@ -620,12 +649,13 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
             for (int r = 0; r < kUnrollD; ++r) count8_hot_masked(cnt, w[r], nv8[r], hot);
         }
     }
-    const unsigned long long beg = runcnt ? 0ull : base[k], end = runcnt ? 0ull : base[k + 1];
+    const bool laid = runcnt || du;   // counted above, not from a counted layout
+    const unsigned long long beg = laid ? 0ull : base[k], end = laid ? 0ull : base[k + 1];
     if (!count_pairs) {
         // degrees already known (an earlier pass): only the offsets are wanted
         for (int j = threadIdx.x; j < nv; j += kBlockD) cnt[j] = (uint32_t)deg[x0 + j];
     }
-    if (count_pairs && !runcnt) {
+    if (count_pairs && !laid) {
         // 16-byte loads of eight ids between the first and last multiple of 8
         // (loc is 256-byte aligned), kUnrollD of them in flight per thread:
         // one block fills a CU, so the loads in flight must cover HBM latency
@@ -1038,6 +1068,11 @@ hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_
     return e != hipSuccess ? e : launch_csr_fill(m, n, p, w, off, adj, s);
 }
 
+// Lists this small take the direct count (every bucket's block reads all of
+// the edges: at most 4 x 2 MB).
+constexpr int kDirectMaxB = 4;
+constexpr int64_t kDirectMaxM = (int64_t)1 << 18;
+
 // Grid and run capacity of the capped layout, or false when it does not
 // apply: CSR builds and two-level passes take the counted layout, and so do
 // lists whose capped runs would not fit the loc buffer or 32-bit slots.  A
@@ -1077,6 +1112,15 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
                                 int64_t* off, int32_t* adj, hipStream_t s, bool allow_capped) {
     int grid = 0;
     uint32_t cap = 0;
+    if (allow_capped && !want_csr && p.B <= kDirectMaxB && m <= kDirectMaxM) {
+        // small lists: one launch, each bucket's block counting straight from the edges
+        w.counted = false;
+        w.other_written = false;
+        bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(nullptr, nullptr, n, deg, 1, want_hist, hist64, histx, tail,
+                                                      tail_cap, tail_count, argmax_key, 0, nullptr, nullptr, nullptr,
+                                                      0, 0, u, v, m, w.err);
+        return hipGetLastError();
+    }
     if (allow_capped && !want_csr && capped_plan(m, p, w, &grid, &cap)) {
         // no count pass: each scatter block fills runs of fixed capacity
         const int G = p.nblk >= 2 * kCUs ? p.nblk / kCUs : 1;

@@ -43,10 +43,11 @@ int bucket_plan(int32_t n, int64_t m, BucketPlan* p);
 
 // deg[n] (+ histograms when want_hist, + CSR off[n+1]/adj[2m] when want_csr).
 // hist64/histx/tail_count/argmax_key must be zeroed by the caller.
-// Degrees-only passes (want_csr = 0, allow_capped) may take the capped
-// layout, which skips the count pass; err[1] (err must hold two words, both
-// zeroed) then reports whether a run overflowed its capacity, in which case
-// the results are void and the pass must be run again with allow_capped off.
+// Degrees-only passes (want_csr = 0, allow_capped) may skip the count pass:
+// small lists are counted straight from the edges in one launch, larger ones
+// take the capped layout; err[1] (err must hold two words, both zeroed) then
+// reports whether a run overflowed its capacity, in which case the results
+// are void and the pass must be run again with allow_capped off.
 hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
                                 BucketBufs& w, int32_t* deg, int want_hist, unsigned long long* hist64,
                                 unsigned long long* histx, int32_t* tail, int64_t tail_cap,
