@@ -150,21 +150,29 @@ __global__ __launch_bounds__(kBlock) void topdown_kernel(const int32_t* __restri
 // top-down levels with workgroup barriers between them, from the frontier in
 // q (qn vertices, their bits already set in vis), and stops before a level
 // whose frontier has more than max_entries entries (the multi-launch levels
-// take it), after max_levels levels, or when the frontier is empty.  Per
-// level: a block scan of the frontier's degrees into pre[], then each thread
-// expands a contiguous share of the entries (one binary search for its first
-// vertex, then a forward walk, four entries' reads in flight at a time),
-// appending new vertices to the other queue through an LDS counter.  The
-// frontier it stops at is left in q.
+// take it), after max_levels levels, or when the frontier is empty.
+//
+// Per level: the frontier's degrees are scanned into a prefix, then each
+// thread expands a contiguous share of the entries (a binary search for its
+// first vertex, then a forward walk, four entries' reads in flight at a
+// time) and appends new vertices to the other queue through an LDS counter.
+// A frontier of at most kFewLds vertices lives in LDS as (row start, degree
+// -> prefix), filled when its vertices are discovered (their offsets are read
+// then anyway), so its scan, search and walk touch no global memory; larger
+// frontiers use the global prefix array pre[].  The frontier it stops at is
+// left in qa (vertex ids).
 // out: [0] levels expanded, [1] vertices visited, [2] entries examined,
 // [3] degree sum of the vertices visited, [4] vertices of the frontier left,
 // [5] their degree sum.
 constexpr int kFewThreads = 1024;
+constexpr int kFewLds = 4096;
 __global__ __launch_bounds__(kFewThreads) void bfs_few_kernel(const int64_t* __restrict__ off,
                                                               const int32_t* __restrict__ adj, int32_t* qa,
                                                               int32_t* qb, int64_t qn0, int64_t max_entries,
                                                               int32_t max_levels, uint32_t* vis, int64_t* pre,
                                                               unsigned long long* __restrict__ out) {
+    __shared__ uint32_t s_pre[2][kFewLds + 1];   // degrees, then their exclusive prefix (entries <= 2^31)
+    __shared__ int64_t s_row[2][kFewLds];        // row start of each frontier vertex
     __shared__ uint32_t s_found;
     __shared__ int64_t s_wsum[kFewThreads / 64];
     __shared__ int64_t s_carry;
@@ -176,16 +184,25 @@ __global__ __launch_bounds__(kFewThreads) void bfs_few_kernel(const int64_t* __r
     unsigned long long fdeg_all = 0;
     int32_t levels = 0;
     int64_t total = 0;
+    int cb = 0;            // LDS buffer of the current frontier
+    bool inl = false;      // the current frontier's degrees and rows are in s_pre[cb] / s_row[cb]
     for (;;) {
-        // exclusive scan of the frontier's degrees into pre[0..qn]
+        // ---- exclusive scan of the frontier's degrees
+        const bool lds = qn <= kFewLds;
         if (tid == 0) s_carry = 0;
         __syncthreads();
         for (int64_t r0 = 0; r0 < qn; r0 += kFewThreads) {
             const int64_t i = r0 + tid;
             int64_t d = 0;
             if (i < qn) {
-                const int32_t x = q[i];
-                d = off[x + 1] - off[x];
+                if (inl) {
+                    d = s_pre[cb][i];
+                } else {
+                    const int32_t x = q[i];
+                    const int64_t o0 = off[x];
+                    d = off[x + 1] - o0;
+                    if (lds) s_row[cb][i] = o0;
+                }
             }
             int64_t x = d;
             for (int o = 1; o < 64; o <<= 1) {
@@ -196,7 +213,10 @@ __global__ __launch_bounds__(kFewThreads) void bfs_few_kernel(const int64_t* __r
             __syncthreads();
             int64_t before = s_carry;
             for (int k = 0; k < w; ++k) before += s_wsum[k];
-            if (i < qn) pre[i] = before + x - d;
+            if (i < qn) {
+                if (lds) s_pre[cb][i] = (uint32_t)(before + x - d);
+                else pre[i] = before + x - d;
+            }
             __syncthreads();
             if (tid == 0) {
                 int64_t t = 0;
@@ -208,47 +228,73 @@ __global__ __launch_bounds__(kFewThreads) void bfs_few_kernel(const int64_t* __r
         total = s_carry;
         if (qn == 0 || total > max_entries || levels >= max_levels) break;   // uniform: every thread read it
         if (tid == 0) {
-            pre[qn] = total;
+            if (lds) s_pre[cb][qn] = (uint32_t)total;
+            else pre[qn] = total;
             s_found = 0;
             s_fdeg = 0;
         }
         __syncthreads();
+        // ---- expansion: thread tid takes entries [e0, e1)
+        const int nb = cb ^ 1;
         const int64_t e0 = total * tid / kFewThreads, e1 = total * (tid + 1) / kFewThreads;
+        auto P = [&](int64_t i) -> int64_t { return lds ? (int64_t)s_pre[cb][i] : pre[i]; };
+        auto R = [&](int64_t i) -> int64_t { return lds ? s_row[cb][i] : off[q[i]]; };
         unsigned long long fdeg = 0;
         if (e0 < e1) {
-            int64_t lo = 0, hi = qn - 1;   // last i with pre[i] <= e0
+            int64_t lo = 0, hi = qn - 1;   // last i with prefix <= e0
             while (lo < hi) {
                 const int64_t mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= e0) lo = mid; else hi = mid - 1;
+                if (P(mid) <= e0) lo = mid; else hi = mid - 1;
             }
-            int64_t i = lo, next = pre[i + 1], base = off[q[i]] - pre[i];
-            for (int64_t e = e0; e < e1; e += 4) {
-                int32_t y[4];
-                bool ok[4];
+            int64_t i = lo, next = P(i + 1), base = R(i) - P(i);
+            // eight entries per step, in three rounds of memory accesses:
+            // their neighbours, the neighbours' bitmap words, then the
+            // claiming atomics together with the candidates' row offsets
+            constexpr int kG = 8;
+            for (int64_t e = e0; e < e1; e += kG) {
+                int32_t y[kG];
+                bool ok[kG];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < kG; ++k) {
                     ok[k] = e + k < e1;
                     y[k] = 0;
                     if (ok[k]) {
                         while (e + k >= next) {
                             ++i;
-                            next = pre[i + 1];
-                            base = off[q[i]] - pre[i];
+                            next = P(i + 1);
+                            base = R(i) - P(i);
                         }
                         y[k] = adj[base + e + k];
                     }
                 }
-                uint32_t wv[4];
+                uint32_t wv[kG];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) wv[k] = ok[k] ? vis[y[k] >> 5] : ~0u;
+                for (int k = 0; k < kG; ++k) wv[k] = ok[k] ? vis[y[k] >> 5] : ~0u;
+                bool cand[kG];
+                uint32_t old[kG];
+                int64_t o0[kG], o1[kG];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t bit = 1u << (y[k] & 31);
-                    if (!ok[k] || (wv[k] & bit)) continue;
-                    const uint32_t old = atomic_or_agent(&vis[y[k] >> 5], bit);
-                    if (old & bit) continue;
-                    nq[atomicAdd(&s_found, 1u)] = y[k];
-                    fdeg += (unsigned long long)(off[y[k] + 1] - off[y[k]]);
+                for (int k = 0; k < kG; ++k) {
+                    cand[k] = ok[k] && !(wv[k] & (1u << (y[k] & 31)));
+                    old[k] = ~0u;
+                    o0[k] = o1[k] = 0;
+                    if (cand[k]) {
+                        old[k] = atomic_or_agent(&vis[y[k] >> 5], 1u << (y[k] & 31));
+                        o0[k] = off[y[k]];
+                        o1[k] = off[y[k] + 1];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kG; ++k) {
+                    if (!cand[k] || (old[k] & (1u << (y[k] & 31)))) continue;
+                    const uint32_t slot = atomicAdd(&s_found, 1u);
+                    nq[slot] = y[k];
+                    const int64_t dy = o1[k] - o0[k];
+                    fdeg += (unsigned long long)dy;
+                    if (slot < (uint32_t)kFewLds) {
+                        s_row[nb][slot] = o0[k];
+                        s_pre[nb][slot] = (uint32_t)dy;
+                    }
                 }
             }
         }
@@ -263,6 +309,8 @@ __global__ __launch_bounds__(kFewThreads) void bfs_few_kernel(const int64_t* __r
         int32_t* t = q;
         q = nq;
         nq = t;
+        inl = qn <= kFewLds;   // every new vertex's degree and row went to s_pre[nb] / s_row[nb]
+        cb = nb;
         __syncthreads();   // every thread has read s_found and s_fdeg before the next level resets them
     }
     // the frontier left behind goes back to qa

@@ -1043,11 +1043,101 @@ static hipError_t launch_csr_fill(int64_t m, int32_t n, const BucketPlan& p, con
     return hipGetLastError();
 }
 
+// Lists this small take the direct count (every bucket's block reads all of
+// the edges: at most 4 x 2 MB) and the direct CSR.
+constexpr int kDirectMaxB = 4;
+constexpr int64_t kDirectMaxM = (int64_t)1 << 18;
+
+// CSR of a small list in one launch (degrees known): block k owns bucket k.
+// It sums the degrees below its bucket, scans its bucket's degrees in LDS
+// into row cursors (writing off[]), then reads every edge and places the
+// endpoints in its bucket through those cursors (returning LDS atomics).
+// Rows come out in no particular order, as the contract allows.
+__global__ __launch_bounds__(kBlockD) void csr_direct_kernel(const int32_t* __restrict__ u,
+                                                             const int32_t* __restrict__ v, int64_t m, int32_t n,
+                                                             const int32_t* __restrict__ deg,
+                                                             int64_t* __restrict__ off, int32_t* __restrict__ adj) {
+    __shared__ uint32_t cur[kBsz];
+    __shared__ unsigned long long wred[kBlockD / 64];
+    __shared__ uint32_t wsum[kBlockD / 64];
+    const int k = blockIdx.x, t = threadIdx.x;
+    const int32_t x0 = k << kShift;
+    int32_t nv = n - x0;
+    if (nv > kBsz) nv = kBsz;
+    // degrees of the vertices below this bucket
+    unsigned long long below = 0;
+    for (int32_t x = t; x < x0; x += kBlockD) below += (unsigned long long)deg[x];
+    for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
+    if (lane_id() == 0) wred[t >> 6] = below;
+    // exclusive scan of this bucket's degrees: coalesced loads into LDS,
+    // then 32 consecutive entries per thread
+    constexpr int per = kBsz / kBlockD;
+#pragma unroll 8
+    for (int j = 0; j < per; ++j) {
+        const int32_t x = t + j * kBlockD;
+        cur[x] = x < nv ? (uint32_t)deg[x0 + x] : 0u;
+    }
+    __syncthreads();
+    uint32_t d[per], sum = 0;
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        d[j] = cur[t * per + j];
+        sum += d[j];
+    }
+    uint32_t incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane_id() >= o) incl += y;
+    }
+    if (lane_id() == 63) wsum[t >> 6] = incl;
+    __syncthreads();   // also: every thread has read its degrees from cur[] before they are overwritten
+    unsigned long long base = 0;
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < kBlockD / 64; ++w) {
+        base += wred[w];
+        if (w < (t >> 6)) before += wsum[w];
+        total += wsum[w];
+    }
+    uint32_t run = before + incl - sum;
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        const int32_t x = t * per + j;
+        cur[x] = run;
+        if (x < nv) off[x0 + x] = (int64_t)(base + run);
+        run += d[j];
+    }
+    if (x0 + nv == n && t == 0) off[n] = (int64_t)(base + total);
+    __syncthreads();
+    int32_t* row = adj + base;   // this bucket's rows, relative to its first
+    // eight edges' reads in flight per thread, then their placements
+    constexpr int kU = 8;
+    for (int64_t i0 = 0; i0 < m; i0 += (int64_t)kBlockD * kU) {
+        int32_t a[kU], c[kU];
+#pragma unroll
+        for (int r = 0; r < kU; ++r) {
+            const int64_t i = i0 + t + (int64_t)r * kBlockD;
+            a[r] = i < m ? u[i] : -1;
+            c[r] = i < m ? v[i] : -1;
+        }
+#pragma unroll
+        for (int r = 0; r < kU; ++r) {
+            const uint32_t la = (uint32_t)(a[r] - x0), lc = (uint32_t)(c[r] - x0);
+            if (a[r] >= 0 && la < (uint32_t)nv) row[atomicAdd(&cur[la], 1u)] = c[r];
+            if (c[r] >= 0 && lc < (uint32_t)nv) row[atomicAdd(&cur[lc], 1u)] = a[r];
+        }
+    }
+}
+
+
 static void count_and_scan(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
                            BucketBufs& w, hipStream_t s);
 
 hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
                                       BucketBufs& w, int32_t* deg, int64_t* off, int32_t* adj, hipStream_t s) {
+    if (p.B <= kDirectMaxB && m <= kDirectMaxM) {
+        csr_direct_kernel<<<p.B, kBlockD, 0, s>>>(u, v, m, n, deg, off, adj);
+        return hipGetLastError();
+    }
     if (!w.counted) {
         // the degree pass used the capped layout: count and scan first (the
         // ids were checked then; the error counter only grows)
@@ -1067,11 +1157,6 @@ hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_
     hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : launch_csr_fill(m, n, p, w, off, adj, s);
 }
-
-// Lists this small take the direct count (every bucket's block reads all of
-// the edges: at most 4 x 2 MB).
-constexpr int kDirectMaxB = 4;
-constexpr int64_t kDirectMaxM = (int64_t)1 << 18;
 
 // Grid and run capacity of the capped layout, or false when it does not
 // apply: CSR builds and two-level passes take the counted layout, and so do
@@ -1112,13 +1197,15 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
                                 int64_t* off, int32_t* adj, hipStream_t s, bool allow_capped) {
     int grid = 0;
     uint32_t cap = 0;
-    if (allow_capped && !want_csr && p.B <= kDirectMaxB && m <= kDirectMaxM) {
-        // small lists: one launch, each bucket's block counting straight from the edges
+    if (p.B <= kDirectMaxB && m <= kDirectMaxM) {
+        // small lists: each bucket's block counts straight from the edges
+        // (one launch), and a CSR takes one more
         w.counted = false;
         w.other_written = false;
         bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(nullptr, nullptr, n, deg, 1, want_hist, hist64, histx, tail,
                                                       tail_cap, tail_count, argmax_key, 0, nullptr, nullptr, nullptr,
                                                       0, 0, u, v, m, w.err);
+        if (want_csr) csr_direct_kernel<<<p.B, kBlockD, 0, s>>>(u, v, m, n, deg, off, adj);
         return hipGetLastError();
     }
     if (allow_capped && !want_csr && capped_plan(m, p, w, &grid, &cap)) {
