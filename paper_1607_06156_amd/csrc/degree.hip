@@ -1164,7 +1164,7 @@ hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_
 // run holds twice its bucket's average share of the block's endpoints plus
 // 256: a hub of a third of its bucket's entries still fits.
 static bool capped_plan(int64_t m, const BucketPlan& p, const BucketBufs& w, int* grid, uint32_t* cap) {
-    if (p.B > kStagedMaxB || m < ((int64_t)1 << 20)) return false;
+    if (p.B > kStagedMaxB || m < ((int64_t)1 << 16)) return false;
     const int G = p.nblk >= 2 * kCUs ? p.nblk / kCUs : 1;
     const int g = (p.nblk + G - 1) / G;
     if (g > kMaxRuns) return false;

@@ -416,6 +416,14 @@ def test_degree_pass_without_count_pass():
     say("[gpu] capped degree pass rmat18noisy")
     d = ccmi.degree(to_dev(g.u), to_dev(g.v), g.n)
     assert np.array_equal(d.cpu().numpy(), odeg.degree(g.u, g.v, g.n))
+    # sparse lists over many buckets: 2^16 edges and more take the capped layout
+    rng = np.random.default_rng(17)
+    for n, m in ((600_000, 1 << 16), (600_000, 100_003), (3_000_000, 400_000)):
+        u = rng.integers(0, n, m).astype(np.int32)
+        v = rng.integers(0, n, m).astype(np.int32)
+        say(f"[gpu] capped degree pass n={n} m={m}")
+        d = ccmi.degree(to_dev(u), to_dev(v), n)
+        assert np.array_equal(d.cpu().numpy(), odeg.degree(u, v, n)), (n, m)
     leaves = 1 << 21
     star = gen.Graph(np.zeros(leaves, np.int32), np.arange(1, leaves + 1, dtype=np.int32), leaves + 1, "star")
     say("[gpu] capped degree pass, star (overflow)")
