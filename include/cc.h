@@ -90,7 +90,8 @@ extern "C" {
 
 typedef struct cc_options {
     int32_t route;       /* CC_ROUTE_* */
-    int32_t max_passes;  /* 0: no cap; else CC_EINTERNAL once this many SV passes ran without converging */
+    int32_t max_passes;  /* 0: no cap (unless CCMI_MAX_PASSES=k is set in the environment, for failure
+                            tests); else CC_EINTERNAL once this many SV passes ran without converging */
     double tau;          /* K-S threshold; <= 0 selects 0.05 (Section V, Table "tab:ks_stat") */
     double theta;        /* R2: hook attempts per edge per pass (an edge whose hook finds the root already
                             linked follows the link and retries); < 1 selects 8 */
@@ -432,7 +433,8 @@ int cc_check_labels(const int32_t* u, const int32_t* v, int64_t m, int32_t n, co
  * making it returns CC_ENOMEM; the count is process-wide and fires once.
  * nth = 0 turns a pending failure off.  Returns CC_OK, or CC_EINVAL for
  * nth < 0.  A call that failed this way leaves the library usable: the next
- * call allocates afresh. */
+ * call allocates afresh.  The environment variable CCMI_FAIL_ALLOC=k arms
+ * the same countdown once, at the process's first allocation. */
 int cc_debug_fail_alloc(int64_t nth);
 
 #ifdef __cplusplus

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -43,8 +44,16 @@ int hip_fail(hipError_t e, const char* what) {
 
 // ------------------------------------------------------- failure injection
 static std::atomic<int64_t> g_fail_alloc{0};
+static std::once_flag g_fail_alloc_env;
 
 bool alloc_fault() {
+    // CCMI_FAIL_ALLOC=k in the environment arms the countdown once, at the
+    // process's first allocation check
+    std::call_once(g_fail_alloc_env, [] {
+        const char* e = getenv("CCMI_FAIL_ALLOC");
+        const long long k = e ? atoll(e) : 0;
+        if (k > 0) g_fail_alloc.store((int64_t)k);
+    });
     int64_t k = g_fail_alloc.load();
     while (k > 0)
         if (g_fail_alloc.compare_exchange_weak(k, k - 1)) return k == 1;
@@ -651,6 +660,12 @@ CC_API int cc_label_ex(const int32_t* u, const int32_t* v, int64_t m, int32_t n,
     if (opt.scratch != CC_SCRATCH_POOL && opt.scratch != CC_SCRATCH_CACHED)
         return fail(CC_EINVAL, "bad scratch mode %d", opt.scratch);
     opt.check = check_enabled(opt);
+    if (opt.max_passes == 0) {
+        // CCMI_MAX_PASSES=k caps the SV passes of calls that set no cap (failure tests)
+        const char* e = getenv("CCMI_MAX_PASSES");
+        const int k = e ? atoi(e) : 0;
+        if (k > 0) opt.max_passes = k;
+    }
     if (stats) stats_reset(stats);
     if (n == 0) return CC_OK;
 

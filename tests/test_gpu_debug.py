@@ -154,3 +154,48 @@ def test_allocation_failure_reports_enomem_and_recovers():
         assert np.array_equal(labs, expect[x].astype(np.int64) * 1000003 + 7)
     finally:
         ccmi.debug_fail_alloc(0)
+
+
+_FAIL_CHILD = """
+import sys
+sys.path.insert(0, {root!r})
+import numpy as np, torch
+import gen, oracle, paper_1607_06156_amd as ccmi
+g = gen.workload("rmat16")
+u, v = torch.from_numpy(g.u).cuda(), torch.from_numpy(g.v).cuda()
+try:
+    ccmi.label(u, v, g.n, route="sv")
+    print("no failure")
+except ccmi.CCError as e:
+    print("failed", e.code)
+lab = ccmi.label(u, v, g.n, route="sv").cpu().numpy()
+print("exact", bool(np.array_equal(lab, oracle.labels_uf(g.u, g.v, g.n))))
+"""
+
+
+def test_failure_hooks_from_the_environment(monkeypatch):
+    """CCMI_FAIL_ALLOC=1 (read once, at the first allocation) makes a fresh
+    process's first call fail with CC_ENOMEM and its second succeed;
+    CCMI_MAX_PASSES=1 (read per call) caps the passes of calls that set no
+    cap, so a graph that needs more fails with CC_EINTERNAL."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, CCMI_FAIL_ALLOC="1")
+    say("[gpu] child with CCMI_FAIL_ALLOC=1")
+    r = subprocess.run([sys.executable, "-c", _FAIL_CHILD.format(root=root)], capture_output=True, text=True,
+                       env=env, timeout=240)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert f"failed {ccmi.CC_ENOMEM}" in r.stdout and "exact True" in r.stdout, r.stdout
+    # a permuted path needs several passes
+    n = 100_000
+    pi = gen.permutation(n, seed=5)
+    u, v = to_dev(pi[:-1]), to_dev(pi[1:])
+    monkeypatch.setenv("CCMI_MAX_PASSES", "1")
+    say("[gpu] CCMI_MAX_PASSES=1")
+    with pytest.raises(ccmi.CCError) as ei:
+        ccmi.label(u, v, n, route="sv")
+    assert ei.value.code == ccmi.CC_EINTERNAL
+    monkeypatch.delenv("CCMI_MAX_PASSES")
+    assert torch.all(ccmi.label(u, v, n, route="sv") == 0)
