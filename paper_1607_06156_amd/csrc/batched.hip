@@ -168,12 +168,20 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
     uint32_t natom = 0, nchase = 0;   // per thread, over all passes
     unsigned long long block_kept = 0, block_hooks = 0;
     unsigned long long tot_read = 0, tot_kept = 0;   // this block, over all passes (thread 0's count)
+    int32_t tg = -1;   // thread 0: graph of the last tile's first edge
     for (int64_t t = tw.first; t < tw.end; t += tw.step) {
         const int64_t e0 = t * kTileE;
         int64_t len = A.m - e0;
         if (len > kTileE) len = kTileE;
         __syncthreads();   // every thread has read the previous tile's sh_g
-        if (threadIdx.x == 0) sh_g = graph_of(A.edge_off, A.G, e0);
+        if (threadIdx.x == 0) {
+            // this block's tiles come in increasing order: from the last
+            // tile's graph, walk forward (one binary search for the first)
+            if (tg < 0) tg = graph_of(A.edge_off, A.G, e0);
+            else
+                while (A.edge_off[tg + 1] <= e0) ++tg;
+            sh_g = tg;
+        }
         __syncthreads();
         int32_t g = sh_g;
         // All of the thread's edge reads go out first (non-temporal: the
@@ -404,14 +412,45 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
     // the labels global; the host then finishes the flatten and the shift.
     const TileWalk vw(TV, b, nb);
     bool left = false;
+    // a tile's kTileE / kBlock vertices per thread walk up in lock-step, so
+    // their dependent reads overlap
+    constexpr int kV = (int)(kTileE / kBlock);
     for (int64_t t = vw.first; t < vw.end; t += vw.step) {
-        for (int64_t x = t * kTileE + threadIdx.x; x < (t + 1) * kTileE && x < A.n; x += kBlock) {
-            const int32_t p = A.parent[x];
-            if (p == (int32_t)x) continue;
-            bool root;
-            const int32_t q = find_bounded(A.parent, p, &root);
-            if (q != p) A.parent[x] = q;
-            left |= !root;
+        int32_t x[kV], p[kV], q[kV];
+        bool act[kV];
+#pragma unroll
+        for (int k = 0; k < kV; ++k) {
+            const int64_t xi = t * kTileE + threadIdx.x + (int64_t)k * kBlock;
+            act[k] = xi < A.n;
+            x[k] = act[k] ? (int32_t)xi : 0;
+            p[k] = act[k] ? A.parent[xi] : 0;
+            act[k] = act[k] && p[k] != x[k];
+            q[k] = p[k];
+        }
+        // q[k] walks from p[k]; r[k] is the next link read
+        int32_t r[kV];
+#pragma unroll
+        for (int k = 0; k < kV; ++k) r[k] = act[k] ? A.parent[q[k]] : q[k];
+        for (int hop = 0; hop < kMaxHops; ++hop) {
+            bool more = false, mv[kV];
+#pragma unroll
+            for (int k = 0; k < kV; ++k) {
+                mv[k] = act[k] && r[k] != q[k];
+                more |= mv[k];
+            }
+            if (!more) break;
+#pragma unroll
+            for (int k = 0; k < kV; ++k)
+                if (mv[k]) q[k] = r[k];
+#pragma unroll
+            for (int k = 0; k < kV; ++k)
+                if (mv[k]) r[k] = A.parent[q[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kV; ++k) {
+            if (!act[k]) continue;
+            if (q[k] != p[k]) A.parent[x[k]] = q[k];
+            left |= r[k] != q[k];   // stopped at the hop bound short of a root
         }
     }
     if (ballot(left) && lane_id() == 0)
@@ -419,10 +458,16 @@ __global__ __launch_bounds__(kBlock, 6) void batched_kernel(BatchArgs A) {
     grid_barrier(A.bar, A.status, A.barrier_ticks);
     if (load_status(A.status) || load_status(&A.status[kDeep])) return;
     stamp(A.status, pass + 1);
+    int32_t vg = -1;   // thread 0: graph of the last vertex tile's first vertex
     for (int64_t t = vw.first; t < vw.end; t += vw.step) {
         const int64_t x0 = t * kTileE;
         __syncthreads();
-        if (threadIdx.x == 0) sh_g = graph_of(A.vert_off, A.G, x0);
+        if (threadIdx.x == 0) {
+            if (vg < 0) vg = graph_of(A.vert_off, A.G, x0);   // then forward, as in pass 0
+            else
+                while (A.vert_off[vg + 1] <= x0) ++vg;
+            sh_g = vg;
+        }
         __syncthreads();
         int32_t g = sh_g;
         for (int64_t x = x0 + threadIdx.x; x < x0 + kTileE && x < A.n; x += kBlock) {
