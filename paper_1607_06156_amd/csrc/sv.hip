@@ -326,18 +326,49 @@ __global__ __launch_bounds__(kTotThreads) void sv_totals_kernel(const uint32_t* 
 // (one store per wave).  No hook may run concurrently.  Each round moves every
 // vertex of a deep chain at least kMaxHops links up, so depth d takes about
 // log(d) / log(kMaxHops) rounds; shallow forests finish in one.
+// Each thread walks kFinV vertices up in lock-step (every step issues the
+// next read of each unfinished walk before using any), so the dependent
+// reads of different walks overlap.
+constexpr int kFinV = 4;
 __global__ __launch_bounds__(kBlock) void sv_finalize_kernel(int32_t* parent, int32_t n,
                                                              unsigned long long* open) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * kFinV;
     bool left = false;
-    for (; i < n; i += stride) {
-        int32_t p = parent[i];
-        if (p == (int32_t)i) continue;
-        bool root;
-        int32_t r = find_bounded(parent, p, &root);
-        if (r != p) parent[i] = r;
-        left |= !root;
+    for (int64_t b0 = (int64_t)blockIdx.x * kBlock * kFinV + threadIdx.x; b0 < n; b0 += stride) {
+        int32_t p[kFinV], q[kFinV], r[kFinV];
+        bool act[kFinV];
+#pragma unroll
+        for (int k = 0; k < kFinV; ++k) {
+            const int64_t x = b0 + (int64_t)k * kBlock;
+            act[k] = x < n;
+            p[k] = act[k] ? parent[x] : 0;
+            act[k] = act[k] && p[k] != (int32_t)x;
+            q[k] = p[k];
+        }
+        // q: the vertex reached, r: its parent as read
+#pragma unroll
+        for (int k = 0; k < kFinV; ++k) r[k] = act[k] ? parent[q[k]] : q[k];
+        for (int hop = 0; hop < kMaxHops; ++hop) {
+            bool more = false, mv[kFinV];
+#pragma unroll
+            for (int k = 0; k < kFinV; ++k) {
+                mv[k] = act[k] && r[k] != q[k];
+                more |= mv[k];
+            }
+            if (!more) break;
+#pragma unroll
+            for (int k = 0; k < kFinV; ++k)
+                if (mv[k]) q[k] = r[k];
+#pragma unroll
+            for (int k = 0; k < kFinV; ++k)
+                if (mv[k]) r[k] = parent[q[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < kFinV; ++k) {
+            if (!act[k]) continue;
+            if (q[k] != p[k]) parent[b0 + (int64_t)k * kBlock] = q[k];
+            left |= r[k] != q[k];   // stopped at the hop bound short of a root
+        }
     }
     if (ballot(left) && lane_id() == 0) __hip_atomic_store(open, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
