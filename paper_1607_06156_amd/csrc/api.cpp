@@ -554,6 +554,8 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         const int64_t kept = (int64_t)htot[0];
         const int64_t hooks = (int64_t)htot[1];
         const int64_t fresh = (int64_t)htot[3];   // hooked since the last full flatten
+        // the byte model's counts, read before a deep flatten reuses htot[8]
+        const int64_t natom = (int64_t)htot[7], nchase = (int64_t)htot[8], ndrop = (int64_t)htot[9];
         // Finds that stopped at the hop bound: the pass left deep chains, so
         // the forest is flattened completely before the next pass.
         const bool deep = kept > 0 && htot[4] > 0;
@@ -580,7 +582,6 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             if (c.stats->sv_passes < 64) c.stats->active_edges[c.stats->sv_passes] = m_in;
             c.stats->sv_passes++;
             c.stats->hooks_total += hooks;
-            const int64_t natom = (int64_t)htot[7], nchase = (int64_t)htot[8], ndrop = (int64_t)htot[9];
             c.stats->sv_atomics += natom;
             c.stats->sv_chase_reads += nchase;
             c.stats->giant_dropped += ndrop;
