@@ -1,0 +1,112 @@
+"""A seeded randomized sweep of GPU parity: many small graphs of every
+generator family, with random sizes, degrees, duplicate edges, self-loops
+and edge orders, through every route (with the device checks on), the
+64-bit entry point, the tuple ablation and one batched launch, each result
+against the oracle bit for bit.  Sizes straddle the thresholds where the
+library switches strategy (one or several degree buckets, direct or capped
+or counted degree layouts, one or several first-pass chunks)."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+ccmi = pytest.importorskip("paper_1607_06156_amd")
+
+ROUTES = ("sv", "sv-theta", "bfs+sv", "heuristic")
+
+
+def _graph(rng, i):
+    fam = ("gnm", "rmat", "rmat-noisy", "grid", "plcomp", "star", "paths")[i % 7]
+    if fam == "gnm":
+        n = int(2 ** rng.uniform(4, 18))
+        return gen.gnm(n, int(n * rng.uniform(0.3, 8)), seed=100 + i)
+    if fam == "rmat":
+        return gen.rmat(int(rng.integers(6, 19)), float(rng.uniform(1, 16)), seed=200 + i)
+    if fam == "rmat-noisy":
+        return gen.rmat(int(rng.integers(6, 19)), float(rng.uniform(1, 16)), seed=300 + i, noise=0.1)
+    if fam == "grid":
+        return gen.grid(int(rng.integers(4, 600)), float(rng.uniform(0.3, 1.0)), seed=400 + i)
+    if fam == "plcomp":
+        return gen.plcomp(int(2 ** rng.uniform(8, 19)), seed=500 + i)
+    if fam == "star":
+        n = int(2 ** rng.uniform(3, 18))
+        hub = int(rng.integers(0, n))
+        others = np.setdiff1d(np.arange(n, dtype=np.int32), [hub])
+        keep = others[rng.random(others.size) < 0.9]
+        return gen.Graph(np.full(keep.size, hub, np.int32), keep.astype(np.int32), n, "star")
+    # disjoint ordered and permuted paths (deep chains) over part of the ids
+    n = int(2 ** rng.uniform(4, 18))
+    pi = rng.permutation(n).astype(np.int32)
+    cut = int(rng.integers(1, n))
+    ordered = np.arange(cut, dtype=np.int32)
+    u = np.concatenate([ordered[:-1], pi[cut:][:-1]])
+    v = np.concatenate([ordered[1:], pi[cut:][1:]])
+    return gen.Graph(u.astype(np.int32), v.astype(np.int32), n, "paths")
+
+
+def _mutate(rng, g):
+    """Random edge order and direction, duplicate edges, self-loops."""
+    u, v = g.u.copy(), g.v.copy()
+    if u.size:
+        k = int(rng.integers(0, max(1, u.size // 10)))
+        pick = rng.integers(0, u.size, k)
+        u = np.concatenate([u, v[pick]])
+        v = np.concatenate([v, u[pick]])
+        loops = rng.integers(0, g.n, int(rng.integers(0, 20)))
+        u = np.concatenate([u, loops]).astype(np.int32)
+        v = np.concatenate([v, loops]).astype(np.int32)
+        order = rng.permutation(u.size)
+        swap = rng.random(u.size) < 0.5
+        u, v = np.where(swap, v, u)[order], np.where(swap, u, v)[order]
+    return gen.Graph(u.astype(np.int32), v.astype(np.int32), g.n, g.name)
+
+
+def test_random_sweep_single_graph_routes():
+    rng = np.random.default_rng(20261203)
+    for i in range(210):
+        g = _mutate(rng, _graph(rng, i))
+        expect = oracle.labels_uf(g.u, g.v, g.n)
+        u, v = to_dev(g.u), to_dev(g.v)
+        for route in ROUTES:
+            lab, st = ccmi.label(u, v, g.n, route=route, stats=True, check=True)
+            got = lab.cpu().numpy()
+            if not np.array_equal(got, expect):
+                bad = np.flatnonzero(got != expect)
+                raise AssertionError(f"graph {i} ({g.name}, n={g.n}, m={g.m}) route {route}: "
+                                     f"{bad.size} labels differ, first {bad[:5].tolist()}")
+            assert st["check_flags"] & 1
+        if i % 30 == 0:
+            say(f"[gpu] random sweep {i}: {g.name} n={g.n} m={g.m}")
+
+
+def test_random_sweep_other_entry_points():
+    """The same kind of graphs through cc_label64 (ids spread over the int64
+    range by an increasing map), cc_label_tuples and one batched launch."""
+    rng = np.random.default_rng(77)
+    graphs = [_mutate(rng, _graph(rng, i)) for i in range(56)]
+    for i, g in enumerate(graphs):
+        expect = oracle.labels_uf(g.u, g.v, g.n)
+        if g.m:
+            # an increasing map keeps the component minima
+            scale = np.int64(1) << np.int64(rng.integers(0, 40))
+            off = np.int64(rng.integers(-(1 << 60), 1 << 60))
+            u64 = torch.from_numpy(g.u.astype(np.int64) * scale + off).cuda()
+            v64 = torch.from_numpy(g.v.astype(np.int64) * scale + off).cuda()
+            ids, labs = ccmi.label64(u64, v64)
+            x = (ids.cpu().numpy() - off) // scale
+            assert np.array_equal(labs.cpu().numpy(), expect[x].astype(np.int64) * scale + off), (i, g.name)
+        if 2 * g.m + 2 * g.n < (1 << 31) and g.m <= (1 << 20):
+            lab, _ = ccmi.label_tuples(to_dev(g.u), to_dev(g.v), g.n)
+            assert np.array_equal(lab.cpu().numpy(), expect), (i, g.name, "tuples")
+    say(f"[gpu] random batch of {len(graphs)} graphs")
+    eo = np.concatenate([[0], np.cumsum([g.m for g in graphs])]).astype(np.int64)
+    vo = np.concatenate([[0], np.cumsum([g.n for g in graphs])]).astype(np.int64)
+    args = [torch.from_numpy(a).cuda() for a in (np.concatenate([g.u for g in graphs]).astype(np.int32),
+                                                 np.concatenate([g.v for g in graphs]).astype(np.int32), eo, vo)]
+    got = ccmi.label_batched(*args).cpu().numpy()
+    want = np.concatenate([oracle.labels_uf(g.u, g.v, g.n) for g in graphs])
+    assert np.array_equal(got, want)
