@@ -185,8 +185,8 @@ static_assert(StageCfg<false>::kSlots <= 65536 && StageCfg<true>::kSlots <= 6553
 // bucket k starts at slot (k * gridDim + b) * cap and holds at most cap
 // entries; the block writes how many it filled to runcnt[k * gridDim + b],
 // counts the edges with an id outside [0, n) into err[0], and sets err[1]
-// if some run would have outgrown cap (the entries that did not fit are not
-// written; the caller then runs the counted layout instead).
+// if some run would have outgrown cap (from the tile where that happens on,
+// the block writes nothing; the caller then runs the counted layout instead).
 template <bool OTHER, bool SUPER, bool CAP = false>
 __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
     const int32_t* __restrict__ u, const int32_t* __restrict__ v, int64_t m, int32_t n, int64_t chunk, int32_t G,
@@ -199,12 +199,15 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
     constexpr int kKeyShift = SUPER ? kSuperShift : 16;    // key = staging bucket << kKeyShift | local
     constexpr uint32_t kLocalMask = (1u << kSh) - 1u;
     constexpr int64_t kTile = (int64_t)kStageThreads * E;
-    __shared__ uint32_t stage[StageCfg<OTHER>::kSlots];
-    __shared__ int32_t stage_o[OTHER ? StageCfg<OTHER>::kSlots : 1];
-    __shared__ uint32_t toff[kStagedMaxB + 1];
+    constexpr uint32_t kJunk = kStagedMaxB + 1;            // toff slot of edges with an id out of range
+    constexpr uint32_t kJunkSlot = StageCfg<OTHER>::kSlots;  // their stage slot
+    __shared__ uint32_t stage[StageCfg<OTHER>::kSlots + 1];
+    __shared__ int32_t stage_o[OTHER ? StageCfg<OTHER>::kSlots + 1 : 1];
+    __shared__ uint32_t toff[kStagedMaxB + 2];
     __shared__ uint32_t run[kStagedMaxB];  // next free output slot of each staging bucket
     __shared__ uint32_t rb[kStagedMaxB];   // per tile: output slot of staged slot 0, per staging bucket
     __shared__ uint32_t wsum[kStageThreads / 64];
+    __shared__ uint32_t s_full;            // CAP: some run of this block is full
     const int t = threadIdx.x;
     const int c0 = blockIdx.x * G;                         // first edge chunk of this block
     const int NB = SUPER ? (B + kSub - 1) / kSub : B;     // staging buckets (<= 2 * kStageThreads)
@@ -225,35 +228,61 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
     };
     if (2 * t < NB) run[2 * t] = first_slot(2 * t);
     if (2 * t + 1 < NB) run[2 * t + 1] = first_slot(2 * t + 1);
+    if (t == 0) s_full = 0;
     const int64_t beg = (int64_t)c0 * chunk;
     int64_t end = beg + (int64_t)G * chunk;
     if (end > m) end = m;
-    // the thread's edges of the current tile (-1: past the end)
+    // the thread's edges of the tile at t0 (-1: past the end); the bound
+    // is tested per edge only in a tile that reaches past the end
     int32_t a[E], c[E];
+    auto load_tile = [&](int64_t t0) {
+        const int32_t* pu = u + (t0 + t);
+        const int32_t* pv = v + (t0 + t);
+        if (t0 + kTile <= end) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int64_t i = beg + t + (int64_t)j * kStageThreads;
-        a[j] = i < end ? u[i] : -1;
-        c[j] = i < end ? v[i] : -1;
-    }
+            for (int j = 0; j < E; ++j) {
+                a[j] = pu[j * kStageThreads];
+                c[j] = pv[j * kStageThreads];
+            }
+        } else {
+            const int64_t rem = end - (t0 + t);   // edge j of the thread is before the end iff j * 1024 < rem
+#pragma unroll
+            for (int j = 0; j < E; ++j) {
+                const bool in = (int64_t)j * kStageThreads < rem;
+                a[j] = in ? pu[j * kStageThreads] : -1;
+                c[j] = in ? pv[j * kStageThreads] : -1;
+            }
+        }
+    };
+    load_tile(beg);
     uint32_t nbad = 0;     // CAP: edges of this thread with an id outside [0, n)
     bool spill = false;    // CAP: an entry did not fit its run
     for (int64_t t0 = beg; t0 < end; t0 += kTile) {
         for (int k = t; k <= NB; k += kStageThreads) toff[k] = 0;
         __syncthreads();
         // rank of each endpoint within its bucket's part of the tile (16 bits
-        // each, both ends of edge j packed in r[j])
+        // each, both ends of edge j packed in r[j]); an edge with an id out
+        // of range (or past the end) ranks in the junk slot and stages nothing
         uint32_t r[E];
         uint32_t okm = 0;
 #pragma unroll
         for (int j = 0; j < E; ++j) {
-            r[j] = 0;
-            if ((uint32_t)a[j] < (uint32_t)n && (uint32_t)c[j] < (uint32_t)n) {
-                okm |= 1u << j;
-                r[j] = atomicAdd(&toff[a[j] >> kSh], 1u) | (atomicAdd(&toff[c[j] >> kSh], 1u) << 16);
-            } else if (CAP && t0 + t + (int64_t)j * kStageThreads < end) {
-                ++nbad;
-            }
+            const bool ok = (uint32_t)a[j] < (uint32_t)n && (uint32_t)c[j] < (uint32_t)n;
+            okm |= ok ? 1u << j : 0u;
+            const uint32_t ba = ok ? (uint32_t)a[j] >> kSh : kJunk;
+            const uint32_t bc = ok ? (uint32_t)c[j] >> kSh : kJunk;
+            r[j] = atomicAdd(&toff[ba], 1u) | (atomicAdd(&toff[bc], 1u) << 16);
+            // groups of four edges: eight ranks in flight at a time, and
+            // their results live only until packed
+            if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        if (CAP) {
+            // edges of this tile before the end, less those in range
+            const int64_t rem = end - (t0 + t);
+            const int inr = rem <= 0 ? 0
+                                     : (rem >= (int64_t)E * kStageThreads ? E
+                                                                          : (int)((rem + kStageThreads - 1) / kStageThreads));
+            nbad += (uint32_t)(inr - __popc(okm));
         }
         __syncthreads();
         // exclusive scan of the tile's bucket counts (NB <= 2 * 1024 entries)
@@ -276,57 +305,55 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
             __syncthreads();
             const uint32_t ex = wsum[t >> 6] + incl - s;
             // staged slot i of bucket k goes to output slot rb[k] + i
+            bool full = false;
             if (2 * t < NB) {
                 const uint32_t q = run[2 * t];
                 toff[2 * t] = ex;
                 rb[2 * t] = q - ex;
                 run[2 * t] = q + n0;
+                if (CAP) full |= q + n0 - first_slot(2 * t) > cap;
             }
             if (2 * t + 1 < NB) {
                 const uint32_t q = run[2 * t + 1];
                 toff[2 * t + 1] = ex + n0;
                 rb[2 * t + 1] = q - (ex + n0);
                 run[2 * t + 1] = q + n1;
+                if (CAP) full |= q + n1 - first_slot(2 * t + 1) > cap;
             }
+            // a full run: nothing more of this block is written (the caller
+            // sees err[1] and takes the counted layout)
+            if (CAP && full) s_full = 1;
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < E; ++j)
-            if (okm & (1u << j)) {
-                const uint32_t ka = ((uint32_t)(a[j] >> kSh) << kKeyShift) | ((uint32_t)a[j] & kLocalMask);
-                const uint32_t kc = ((uint32_t)(c[j] >> kSh) << kKeyShift) | ((uint32_t)c[j] & kLocalMask);
-                const uint32_t sa = toff[a[j] >> kSh] + (r[j] & 0xffffu);
-                const uint32_t sc = toff[c[j] >> kSh] + (r[j] >> 16);
-                stage[sa] = ka;
-                stage[sc] = kc;
-                if (OTHER) {
-                    stage_o[sa] = c[j];
-                    stage_o[sc] = a[j];
-                }
-            }
-        // the next tile's edges: in flight during the barrier and the write-out
-#pragma unroll
         for (int j = 0; j < E; ++j) {
-            const int64_t i = t0 + kTile + t + (int64_t)j * kStageThreads;
-            a[j] = i < end ? u[i] : -1;
-            c[j] = i < end ? v[i] : -1;
+            const bool ok = (okm >> j) & 1u;
+            const uint32_t ba = ok ? (uint32_t)a[j] >> kSh : kJunk;
+            const uint32_t bc = ok ? (uint32_t)c[j] >> kSh : kJunk;
+            const uint32_t ka = ((uint32_t)(a[j] >> kSh) << kKeyShift) | ((uint32_t)a[j] & kLocalMask);
+            const uint32_t kc = ((uint32_t)(c[j] >> kSh) << kKeyShift) | ((uint32_t)c[j] & kLocalMask);
+            const uint32_t sa = ok ? toff[ba] + (r[j] & 0xffffu) : kJunkSlot;
+            const uint32_t sc = ok ? toff[bc] + (r[j] >> 16) : kJunkSlot;
+            stage[sa] = ka;
+            stage[sc] = kc;
+            if (OTHER) {
+                stage_o[sa] = c[j];
+                stage_o[sc] = a[j];
+            }
         }
+        // the next tile's edges: in flight during the barrier and the write-out
+        load_tile(t0 + kTile);
         __syncthreads();
         // contiguous runs per bucket: staged slot i -> its bucket's next free slot
         const uint32_t total = toff[NB];
-        for (uint32_t i = t; i < total; i += kStageThreads) {
-            const uint32_t q = stage[i];
-            const uint64_t pos = (uint32_t)(rb[q >> kKeyShift] + i);
-            if (CAP) {
-                // the run of bucket k ends where block b + 1's begins
-                const uint32_t lim = ((q >> kKeyShift) * gridDim.x + blockIdx.x + 1) * cap;
-                if (pos < lim) loc[pos] = (uint16_t)(q & kLocalMask);
-                else spill = true;
-                continue;
+        if (!CAP || !s_full) {
+            for (uint32_t i = t; i < total; i += kStageThreads) {
+                const uint32_t q = stage[i];
+                const uint32_t pos = rb[q >> kKeyShift] + i;
+                if (SUPER) loc32[pos] = q & kLocalMask;
+                else loc[pos] = (uint16_t)(q & kLocalMask);
+                if (OTHER) other[pos] = stage_o[i];
             }
-            if (SUPER) loc32[pos] = q & kLocalMask;
-            else loc[pos] = (uint16_t)(q & kLocalMask);
-            if (OTHER) other[pos] = stage_o[i];
         }
         __syncthreads();
     }
@@ -463,18 +490,22 @@ struct HistLds {
 
 __device__ __forceinline__ void hist_vertex(HistLds& L, uint32_t d, int32_t x, int32_t* tail, int64_t tail_cap,
                                             unsigned long long* tail_count, unsigned long long& best) {
-    if (d < (uint32_t)kExactBins) lds_inc_agg(L.hx, d);
-    else {
+    if (d < (uint32_t)kExactBins) {
+        lds_inc_agg(L.hx, d);   // its log bin is taken from hx[d] at the flush
+    } else {
         unsigned long long slot = atomic_add_agent(tail_count, 1ull);
         if ((int64_t)slot < tail_cap) tail[slot] = (int32_t)d;
+        atomicAdd(&L.h64[log_bin(d)], 1u);
     }
-    lds_inc_agg(L.h64, (uint32_t)log_bin(d));
     unsigned long long key = ((unsigned long long)d << 32) | (unsigned long long)(~(uint32_t)x);
     best = key > best ? key : best;
 }
 
 __device__ __forceinline__ void hist_flush(HistLds& L, unsigned long long best, unsigned long long* hist64,
                                            unsigned long long* histx, unsigned long long* argmax_key, int nthreads) {
+    // the log bins of the degrees below kExactBins, from the exact bins
+    for (int d = threadIdx.x; d < kExactBins; d += nthreads)
+        if (L.hx[d]) atomicAdd(&L.h64[log_bin((uint32_t)d)], L.hx[d]);
     for (int off = 32; off > 0; off >>= 1) {
         unsigned long long o = __shfl_xor(best, off);
         best = o > best ? o : best;
@@ -493,54 +524,141 @@ __device__ __forceinline__ void hist_flush(HistLds& L, unsigned long long best, 
 
 // ------------------------------------------------------------------ pass D
 constexpr int kUnrollD = 8;
+constexpr uint32_t kNoId = 0xffffffffu;   // matches no id of a bucket
+// Lanes of one instruction that add to the same LDS counter serialise, and a
+// hub can hold a large share of its bucket's entries (over 40% on R-MAT
+// scale 24).  So past the kBsz counters each lane has private slots: the
+// entries of the block's two hubs (found from a sample) go to slot
+// kHubSlots + 64 h + lane, entries that count nowhere (another bucket's, in
+// the small-list path) to kJunkSlots + lane.  Every lane of an instruction
+// then adds to its own counter for them; the hub slots are folded into the
+// hubs' counters at the end.
+constexpr int kHubSlots = kBsz;
+constexpr int kJunkSlots = kBsz + 128;
+constexpr int kCntWords = kBsz + 192;
+constexpr int kSampleThreads = 256;   // threads that draw 8 sample ids each
+constexpr uint32_t kHubMin = kSampleThreads * 8 / 16;   // a hub holds >= 1/16 of the sample
+// Buckets of fewer entries skip the sample (its cost, a few microseconds,
+// is what a hub could cost them); so do lists of fewer edges in the
+// small-list path, where every block reads the whole list.
+constexpr uint64_t kSampleMinEntries = 1u << 17;
+constexpr int64_t kSampleMinEdges = 1 << 13;
 
-__device__ __forceinline__ void count8(uint32_t* cnt, uint4 w) {
-    atomicAdd(&cnt[w.x & 0xffffu], 1u);
-    atomicAdd(&cnt[w.x >> 16], 1u);
-    atomicAdd(&cnt[w.y & 0xffffu], 1u);
-    atomicAdd(&cnt[w.y >> 16], 1u);
-    atomicAdd(&cnt[w.z & 0xffffu], 1u);
-    atomicAdd(&cnt[w.z >> 16], 1u);
-    atomicAdd(&cnt[w.w & 0xffffu], 1u);
-    atomicAdd(&cnt[w.w >> 16], 1u);
+struct Hubs {
+    uint32_t h0 = kNoId, h1 = kNoId;   // hub ids within the bucket (h1 only with h0)
+    uint32_t s0, s1, sj;               // this lane's slots
+    __device__ Hubs() : s0(kHubSlots + lane_id()), s1(kHubSlots + 64 + lane_id()), sj(kJunkSlots + lane_id()) {}
+};
+
+// the counting loops are compiled for 0, 1 and 2 hubs
+template <int NH>
+struct HubSet {
+    Hubs h;
+};
+
+template <int NH>
+__device__ __forceinline__ uint32_t slot_of(uint32_t x, const HubSet<NH>& hb) {
+    uint32_t a = x;
+    if constexpr (NH >= 1) a = x == hb.h.h0 ? hb.h.s0 : a;
+    if constexpr (NH >= 2) a = x == hb.h.h1 ? hb.h.s1 : a;
+    return a;
 }
 
-// One id per lane, all 64 lanes active.  A hub can hold a large share of its
-// bucket's entries (over 40% on R-MAT scale 24), and lanes of one instruction
-// that hit the same LDS counter serialise.  The wave keeps a candidate id
-// `hot` (wave-uniform): lanes holding it add their number through one lane.
-// When fewer than two lanes held it, the candidate moves to the first lane's
-// id, so a hub is picked up within a few instructions and then kept.
-__device__ __forceinline__ void count_hot(uint32_t* cnt, uint32_t x, uint32_t& hot) {
-    const bool h = x == hot;
-    const uint64_t m = ballot(h);
-    const uint32_t c = (uint32_t)__popcll(m);
-    if (c >= 2) {
-        if (!h || lanes_below(m) == 0) atomicAdd(&cnt[x], h ? c : 1u);
-    } else {
-        atomicAdd(&cnt[x], 1u);
-        hot = __builtin_amdgcn_readfirstlane(x);
-    }
+template <int NH>
+__device__ __forceinline__ void count_id(uint32_t* cnt, uint32_t x, const HubSet<NH>& hb) {
+    atomicAdd(&cnt[slot_of(x, hb)], 1u);
 }
 
-__device__ __forceinline__ void count8_hot(uint32_t* cnt, uint4 w, uint32_t& hot) {
-    count_hot(cnt, w.x & 0xffffu, hot);
-    count_hot(cnt, w.x >> 16, hot);
-    count_hot(cnt, w.y & 0xffffu, hot);
-    count_hot(cnt, w.y >> 16, hot);
-    count_hot(cnt, w.z & 0xffffu, hot);
-    count_hot(cnt, w.z >> 16, hot);
-    count_hot(cnt, w.w & 0xffffu, hot);
-    count_hot(cnt, w.w >> 16, hot);
+// x counts when ok, else it goes to the lane's junk slot
+template <int NH>
+__device__ __forceinline__ void count_or_junk(uint32_t* cnt, uint32_t x, bool ok, const HubSet<NH>& hb) {
+    atomicAdd(&cnt[ok ? slot_of(x, hb) : hb.h.sj], 1u);
 }
 
-// Like count8_hot for the capped layout: entries at or past `valid` (0..8)
-// of this 8-entry group count into the spare counter cnt[kBsz].
-__device__ __forceinline__ void count8_hot_masked(uint32_t* cnt, uint4 w, uint32_t valid, uint32_t& hot) {
+template <int NH>
+__device__ __forceinline__ void count8(uint32_t* cnt, uint4 w, const HubSet<NH>& hb) {
+    count_id(cnt, w.x & 0xffffu, hb);
+    count_id(cnt, w.x >> 16, hb);
+    count_id(cnt, w.y & 0xffffu, hb);
+    count_id(cnt, w.y >> 16, hb);
+    count_id(cnt, w.z & 0xffffu, hb);
+    count_id(cnt, w.z >> 16, hb);
+    count_id(cnt, w.w & 0xffffu, hb);
+    count_id(cnt, w.w >> 16, hb);
+}
+
+// the first `valid` (< 8) entries of an 8-entry group
+template <int NH>
+__device__ __forceinline__ void count8_masked(uint32_t* cnt, uint4 w, uint32_t valid, const HubSet<NH>& hb) {
     const uint32_t x[8] = {w.x & 0xffffu, w.x >> 16, w.y & 0xffffu, w.y >> 16,
                            w.z & 0xffffu, w.z >> 16, w.w & 0xffffu, w.w >> 16};
 #pragma unroll
-    for (int e = 0; e < 8; ++e) count_hot(cnt, (uint32_t)e < valid ? x[e] : (uint32_t)kBsz, hot);
+    for (int e = 0; e < 8; ++e)
+        if ((uint32_t)e < valid) count_id(cnt, x[e], hb);
+}
+
+// f(HubSet<number of hubs>{hb}); the number is uniform over the block
+template <class F>
+__device__ __forceinline__ void with_hubs(const Hubs& hb, F f) {
+    const int nh = __builtin_amdgcn_readfirstlane((int)(hb.h0 != kNoId) + (int)(hb.h1 != kNoId));
+    if (nh == 0) f(HubSet<0>{hb});
+    else if (nh == 1) f(HubSet<1>{hb});
+    else f(HubSet<2>{hb});
+}
+
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x, unsigned long long* red) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o);
+        x = y > x ? y : x;
+    }
+    if (lane_id() == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    unsigned long long r = 0;
+    for (int w = 0; w < kBlockD / 64; ++w) r = red[w] > r ? red[w] : r;
+    __syncthreads();
+    return r;
+}
+
+// The block's hubs: the two most frequent ids of a sample of the bucket's
+// entries (sample(t, id) gives thread t < kSampleThreads up to 8 ids, kNoId
+// for none), each kept when it holds at least kHubMin of the sample.  Which
+// ids are taken changes only how fast the count runs, never its result.
+// cnt[0, kBsz) is zero on entry and on return.
+template <class F>
+__device__ Hubs find_hubs(uint32_t* cnt, unsigned long long* red, F sample) {
+    const int t = threadIdx.x;
+    uint32_t id[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) id[e] = kNoId;
+    if (t < kSampleThreads) sample(t, id);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (id[e] != kNoId) atomicAdd(&cnt[id[e]], 1u);
+    __syncthreads();
+    unsigned long long k0 = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (id[e] != kNoId) {
+            const unsigned long long key = ((unsigned long long)cnt[id[e]] << 32) | id[e];
+            k0 = key > k0 ? key : k0;
+        }
+    k0 = block_max_u64(k0, red);
+    unsigned long long k1 = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (id[e] != kNoId && id[e] != (uint32_t)k0) {
+            const unsigned long long key = ((unsigned long long)cnt[id[e]] << 32) | id[e];
+            k1 = key > k1 ? key : k1;
+        }
+    k1 = block_max_u64(k1, red);   // its barriers also end every read of the sample counts
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (id[e] != kNoId) cnt[id[e]] = 0;
+    __syncthreads();
+    Hubs hb;
+    if ((k0 >> 32) >= kHubMin) hb.h0 = (uint32_t)k0;
+    if ((k1 >> 32) >= kHubMin) hb.h1 = (uint32_t)k1;
+    return hb;
 }
 
 constexpr int kMaxRuns = 1024;   // scatter blocks of a capped layout
@@ -555,7 +673,7 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     int64_t* __restrict__ off, uint32_t* __restrict__ gcnt, const uint32_t* __restrict__ runcnt = nullptr,
     int32_t nruns = 0, uint32_t cap = 0, const int32_t* __restrict__ du = nullptr,
     const int32_t* __restrict__ dv = nullptr, int64_t dm = 0, unsigned long long* __restrict__ derr = nullptr) {
-    __shared__ uint32_t cnt[kBsz + 1];   // + a spare counter for masked entries (capped layout)
+    __shared__ uint32_t cnt[kCntWords];   // the bucket's counters, then the lanes' hub and junk slots
     __shared__ uint32_t rp[kMaxRuns + 1];
     __shared__ uint32_t rc[kMaxRuns];
     __shared__ HistLds L;
@@ -564,36 +682,48 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     const int32_t x0 = k << kShift;
     int32_t nv = n - x0;
     if (nv > kBsz) nv = kBsz;
-    for (int j = threadIdx.x; j < kBsz; j += kBlockD) cnt[j] = 0;
+    for (int j = threadIdx.x; j < kCntWords; j += kBlockD) cnt[j] = 0;
     for (int j = threadIdx.x; j < kExactBins; j += kBlockD) L.hx[j] = 0;
     if (threadIdx.x < 64) L.h64[threadIdx.x] = 0;
     __syncthreads();
-    if (threadIdx.x == 0) cnt[kBsz] = 0;
+    Hubs hb;
     if (du && count_pairs) {
         // direct (small lists): every block reads the whole edge list and
-        // counts the endpoints in its bucket; the others go to the spare
-        // counter, so every lane of a wave stays in count_hot.  Block 0
-        // counts the edges with an id outside [0, n).
-        __syncthreads();
-        uint32_t hot = 0xffffffffu, bad = 0;
-        constexpr int kU = 4;
-        for (int64_t i0 = 0; i0 < dm; i0 += (int64_t)kBlockD * kU) {
-            int32_t a[kU], c[kU];
-#pragma unroll
-            for (int r = 0; r < kU; ++r) {
-                const int64_t i = i0 + threadIdx.x + (int64_t)r * kBlockD;
-                a[r] = i < dm ? du[i] : -1;
-                c[r] = i < dm ? dv[i] : -1;
-                if (k == 0 && i < dm && ((uint32_t)a[r] >= (uint32_t)n || (uint32_t)c[r] >= (uint32_t)n)) ++bad;
+        // counts the endpoints in its bucket; the others go to the lanes'
+        // junk slots.  Block 0 counts the edges with an id outside [0, n).
+        if (dm >= kSampleMinEdges) hb = find_hubs(cnt, L.best, [&](int t, uint32_t* id) {
+            const int64_t i0 = (dm * t) / kSampleThreads;
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + r;
+                if (i >= dm) break;
+                const int32_t a = du[i], c = dv[i];
+                if ((uint32_t)a >= (uint32_t)n || (uint32_t)c >= (uint32_t)n) continue;
+                const uint32_t la = (uint32_t)(a - x0), lc = (uint32_t)(c - x0);
+                id[2 * r] = la < (uint32_t)nv ? la : kNoId;
+                id[2 * r + 1] = lc < (uint32_t)nv ? lc : kNoId;
             }
+        });
+        uint32_t bad = 0;
+        with_hubs(hb, [&](const auto& hs) {
+            constexpr int kU = 4;
+            for (int64_t i0 = 0; i0 < dm; i0 += (int64_t)kBlockD * kU) {
+                int32_t a[kU], c[kU];
 #pragma unroll
-            for (int r = 0; r < kU; ++r) {
-                const bool ok = (uint32_t)a[r] < (uint32_t)n && (uint32_t)c[r] < (uint32_t)n;
-                const uint32_t la = (uint32_t)(a[r] - x0), lc = (uint32_t)(c[r] - x0);
-                count_hot(cnt, ok && la < (uint32_t)nv ? la : (uint32_t)kBsz, hot);
-                count_hot(cnt, ok && lc < (uint32_t)nv ? lc : (uint32_t)kBsz, hot);
+                for (int r = 0; r < kU; ++r) {
+                    const int64_t i = i0 + threadIdx.x + (int64_t)r * kBlockD;
+                    a[r] = i < dm ? du[i] : -1;
+                    c[r] = i < dm ? dv[i] : -1;
+                    if (k == 0 && i < dm && ((uint32_t)a[r] >= (uint32_t)n || (uint32_t)c[r] >= (uint32_t)n)) ++bad;
+                }
+#pragma unroll
+                for (int r = 0; r < kU; ++r) {
+                    const bool ok = (uint32_t)a[r] < (uint32_t)n && (uint32_t)c[r] < (uint32_t)n;
+                    const uint32_t la = (uint32_t)(a[r] - x0), lc = (uint32_t)(c[r] - x0);
+                    count_or_junk(cnt, la, ok && la < (uint32_t)nv, hs);
+                    count_or_junk(cnt, lc, ok && lc < (uint32_t)nv, hs);
+                }
             }
-        }
+        });
         for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o);
         if (lane_id() == 0 && bad) atomic_add_agent(derr, (unsigned long long)bad);
     }
@@ -621,33 +751,53 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
         const uint32_t Q = rp[nruns];
         const uint4* q4 = (const uint4*)loc;
         const uint32_t gpr = cap / 8;   // groups per run slot
-        uint32_t hot = 0xffffffffu;
+        if ((uint64_t)Q * 8 >= kSampleMinEntries) hb = find_hubs(cnt, L.best, [&](int ts, uint32_t* id) {
+            // one group at an even spread over the bucket's groups
+            const uint32_t j = (uint32_t)(((uint64_t)Q * ts) / kSampleThreads);
+            if (j >= Q) return;
+            int lo = 0, hi = nruns;   // the last run r with rp[r] <= j
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) / 2;
+                if (rp[mid] <= j) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t within = j - rp[lo];
+            const uint32_t c = rc[lo] - within * 8;
+            const uint4 w = q4[((uint64_t)k * nruns + lo) * gpr + within];
+            const uint32_t x[8] = {w.x & 0xffffu, w.x >> 16, w.y & 0xffffu, w.y >> 16,
+                                   w.z & 0xffffu, w.z >> 16, w.w & 0xffffu, w.w >> 16};
+            for (int e = 0; e < 8; ++e) id[e] = (uint32_t)e < c ? x[e] : kNoId;
+        });
         constexpr uint32_t kStep = (uint32_t)kBlockD * kUnrollD;
         // The groups j of a thread only increase, so its run index `cur`
         // only moves forward (runs hold about 500 groups, a thread's j
-        // advances by 1024 per slot: a few LDS reads per load).  Every lane
-        // runs every iteration (the bound is uniform); groups past Q count
-        // into the spare counter.
-        int cur = 0;
-        for (uint32_t j0 = 0; j0 < Q; j0 += kStep) {
-            uint4 w[kUnrollD];
-            uint32_t nv8[kUnrollD];
+        // advances by 1024 per slot: a few LDS reads per load).  Only the
+        // last group of a run can be partly filled.
+        with_hubs(hb, [&](const auto& hs) {
+            int cur = 0;
+            for (uint32_t j0 = 0; j0 < Q; j0 += kStep) {
+                uint4 w[kUnrollD];
+                uint32_t nv8[kUnrollD];
 #pragma unroll
-            for (int r = 0; r < kUnrollD; ++r) {
-                const uint32_t j = j0 + t + (uint32_t)r * kBlockD;
-                w[r] = make_uint4(0, 0, 0, 0);
-                nv8[r] = 0;
-                if (j < Q) {
-                    while (rp[cur + 1] <= j) ++cur;   // rp[nruns] = Q > j ends it
-                    const uint32_t within = j - rp[cur];
-                    const uint32_t c = rc[cur] - within * 8;
-                    nv8[r] = c < 8 ? c : 8;
-                    w[r] = q4[((uint64_t)k * nruns + cur) * gpr + within];
+                for (int r = 0; r < kUnrollD; ++r) {
+                    const uint32_t j = j0 + t + (uint32_t)r * kBlockD;
+                    w[r] = make_uint4(0, 0, 0, 0);
+                    nv8[r] = 0;
+                    if (j < Q) {
+                        while (rp[cur + 1] <= j) ++cur;   // rp[nruns] = Q > j ends it
+                        const uint32_t within = j - rp[cur];
+                        const uint32_t c = rc[cur] - within * 8;
+                        nv8[r] = c < 8 ? c : 8;
+                        w[r] = q4[((uint64_t)k * nruns + cur) * gpr + within];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < kUnrollD; ++r) {
+                    if (nv8[r] == 8) count8(cnt, w[r], hs);
+                    else if (nv8[r]) count8_masked(cnt, w[r], nv8[r], hs);
                 }
             }
-#pragma unroll
-            for (int r = 0; r < kUnrollD; ++r) count8_hot_masked(cnt, w[r], nv8[r], hot);
-        }
+        });
     }
     const bool laid = runcnt || du;   // counted above, not from a counted layout
     const unsigned long long beg = laid ? 0ull : base[k], end = laid ? 0ull : base[k + 1];
@@ -659,29 +809,45 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
         // 16-byte loads of eight ids between the first and last multiple of 8
         // (loc is 256-byte aligned), kUnrollD of them in flight per thread:
         // one block fills a CU, so the loads in flight must cover HBM latency
-        // by themselves.  The few entries outside go one at a time.  Plain LDS
-        // atomics: a hub's entries are spread over its bucket's range, so
-        // lanes of one wave rarely share a counter.
+        // by themselves.  The few entries outside go one at a time.
+        if (end - beg >= kSampleMinEntries) hb = find_hubs(cnt, L.best, [&](int t, uint32_t* id) {
+            const unsigned long long i0 = beg + ((end - beg) * (unsigned long long)t) / kSampleThreads;
+            for (int e = 0; e < 8; ++e)
+                if (i0 + e < end) id[e] = loc[i0 + e];
+        });
         const unsigned long long a8 = (beg + 7) & ~7ull, e8 = end & ~7ull;
-        if (a8 >= e8) {
-            for (unsigned long long i = beg + threadIdx.x; i < end; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
-        } else {
-            for (unsigned long long i = beg + threadIdx.x; i < a8; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
-            for (unsigned long long i = e8 + threadIdx.x; i < end; i += kBlockD) atomicAdd(&cnt[loc[i]], 1u);
+        with_hubs(hb, [&](const auto& hs) {
+            if (a8 >= e8) {
+                for (unsigned long long i = beg + threadIdx.x; i < end; i += kBlockD) count_id(cnt, loc[i], hs);
+                return;
+            }
+            for (unsigned long long i = beg + threadIdx.x; i < a8; i += kBlockD) count_id(cnt, loc[i], hs);
+            for (unsigned long long i = e8 + threadIdx.x; i < end; i += kBlockD) count_id(cnt, loc[i], hs);
             const uint4* q = (const uint4*)(loc + a8);
             const long long nq = (long long)((e8 - a8) >> 3);
             constexpr long long kStep = (long long)kBlockD * kUnrollD;
             long long j0 = 0;
-            uint32_t hot = 0xffffffffu;   // no 16-bit id matches it
-            // every lane of every wave runs these iterations (j0 is uniform)
             for (; j0 + kStep <= nq; j0 += kStep) {
                 uint4 w[kUnrollD];
 #pragma unroll
                 for (int r = 0; r < kUnrollD; ++r) w[r] = q[j0 + threadIdx.x + (long long)r * kBlockD];
 #pragma unroll
-                for (int r = 0; r < kUnrollD; ++r) count8_hot(cnt, w[r], hot);
+                for (int r = 0; r < kUnrollD; ++r) count8(cnt, w[r], hs);
             }
-            for (long long j = j0 + threadIdx.x; j < nq; j += kBlockD) count8(cnt, q[j]);
+            for (long long j = j0 + threadIdx.x; j < nq; j += kBlockD) count8(cnt, q[j], hs);
+        });
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        // fold the lanes' hub slots into the hubs' counters
+        uint32_t c0 = cnt[kHubSlots + threadIdx.x], c1 = cnt[kHubSlots + 64 + threadIdx.x];
+        for (int o = 32; o > 0; o >>= 1) {
+            c0 += __shfl_xor(c0, o);
+            c1 += __shfl_xor(c1, o);
+        }
+        if (threadIdx.x == 0) {
+            if (hb.h0 != kNoId) cnt[hb.h0] += c0;
+            if (hb.h1 != kNoId) cnt[hb.h1] += c1;
         }
     }
     __syncthreads();

@@ -445,3 +445,49 @@ def test_degree_pass_without_count_pass():
     lab, st = ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route="heuristic", tau=1e300, stats=True)
     assert st["route"] == ccmi.R0_BFS_SV
     assert_labels_equal(lab, oracle_labels(g), "rmat18noisy heuristic")
+
+
+def _with_hubs(rng, n, m, hubs):
+    """Uniform random edges plus, for each (hub, share), share * m more
+    edges from that hub to random vertices."""
+    u = [rng.integers(0, n, m)]
+    v = [rng.integers(0, n, m)]
+    for h, share in hubs:
+        k = int(share * m)
+        u.append(np.full(k, h))
+        v.append(rng.integers(0, n, k))
+    u, v = np.concatenate(u).astype(np.int32), np.concatenate(v).astype(np.int32)
+    order = rng.permutation(u.size)
+    return u[order], v[order]
+
+
+def test_degree_with_hubs():
+    """The degree count sends the entries of up to two hubs per bucket (found
+    from a sample) to per-lane slots and folds them back: exact degrees,
+    histograms and offsets with no hub, one, two and three hubs in one
+    bucket (the third counts the ordinary way), hubs on a bucket's first and
+    last id and a hub holding most of its bucket; through the small-list,
+    the capped and the counted (CSR) layouts."""
+    rng = np.random.default_rng(29)
+    B = 1 << 15   # vertices per bucket
+    cases = [
+        # small lists (at most 4 buckets, 2^18 edges): the direct path
+        (100_000, 60_000, [(0, 0.3)]),
+        (100_000, 60_000, [(B - 1, 0.2), (B, 0.2), (3, 0.1), (B + 9, 0.05)]),
+        # capped layout (2^16 edges and more, no CSR)
+        (1 << 20, 1 << 20, []),
+        (1 << 20, 1 << 20, [(5, 0.01)]),
+        (1 << 20, 1 << 20, [(7 * B, 0.006), (8 * B - 1, 0.006), (7 * B + 100, 0.004)]),
+        (3_000_000, 1 << 20, [(2_999_999, 0.02), (B * 40 + 1, 0.001)]),
+    ]
+    for n, m, hubs in cases:
+        u, v = _with_hubs(rng, n, m, hubs)
+        want = odeg.degree(u, v, n)
+        say(f"[gpu] degree with hubs n={n} m={u.size} hubs={hubs}")
+        d = ccmi.degree(to_dev(u), to_dev(v), n)
+        assert np.array_equal(d.cpu().numpy(), want), (n, hubs)
+        off, _, deg = ccmi.csr(to_dev(u), to_dev(v), n)
+        assert np.array_equal(deg.cpu().numpy(), want), (n, hubs, "csr")
+        assert np.array_equal(np.diff(off.cpu().numpy()), want), (n, hubs, "offsets")
+        _, st = ccmi.label(to_dev(u), to_dev(v), n, route="heuristic", stats=True)
+        assert st["max_degree"] == int(want.max())
