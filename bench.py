@@ -178,7 +178,7 @@ def main():
         exact = bool(np.array_equal(labels.cpu().numpy(), expect))
         cpu = {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
                "sample": f"full workload ({g.m} edges), sequential union-find, one thread, {dt:.2f} s",
-               "host_nproc": os.cpu_count()}
+               "host_nproc": os.cpu_count(), "host_cpu": host_cpu()}
         log(f"[bench] oracle {dt:.2f}s  {g.m / dt / 1e6:.1f} M edges/s; labels exact: {exact}")
 
     rec = {
@@ -397,7 +397,7 @@ def bench_batched(args, config, steps, warmup):
     if not args.no_cpu:
         cpu = {"value": m / dt, "unit": "edges/s", "cores": workers, "kind": "oracle",
                "sample": f"all {b.G} graphs ({m} edges), union-find per graph on a pool of {workers} threads, "
-                         f"{dt:.2f} s", "host_nproc": os.cpu_count()}
+                         f"{dt:.2f} s", "host_nproc": os.cpu_count(), "host_cpu": host_cpu()}
     return {
         "metric": METRIC,
         "value": value, "unit": "edges/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -415,6 +415,18 @@ def bench_batched(args, config, steps, warmup):
         "per_graph_loop": loop,
         "cpu_baseline": cpu,
     }
+
+
+def host_cpu() -> str | None:
+    """The host CPU's model name, as /proc/cpuinfo gives it."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":
