@@ -293,6 +293,8 @@ size_t workspace_bound(int64_t m, int32_t n, bool sv_only, size_t* per_slot) {
 }
 
 // ------------------------------------------------------------------ timing
+hipError_t create_timing_event(hipEvent_t* ev) { return hipEventCreateWithFlags(ev, hipEventDisableSystemFence); }
+
 Timer::Timer(bool on, hipStream_t s) : enabled(on), stream(s) {}
 Timer::~Timer() {
     for (auto ev : events) (void)hipEventDestroy(ev);
@@ -300,7 +302,7 @@ Timer::~Timer() {
 int Timer::mark() {
     if (!enabled) return -1;
     hipEvent_t ev;
-    if (hipEventCreate(&ev) != hipSuccess) return -1;
+    if (create_timing_event(&ev) != hipSuccess) return -1;
     (void)hipEventRecord(ev, stream);
     events.push_back(ev);
     return (int)events.size() - 1;

@@ -112,6 +112,12 @@ int check_result(Workspace& ws, hipStream_t s, const int32_t* u, const int32_t* 
 // frees the router weights' device copies (router.cpp)
 void router_release_all();
 
+// An event that only times work: created without the system-scope fence a
+// default event performs when it is recorded (a cache writeback and
+// invalidation), so recording it between two kernels neither stalls the
+// stream nor empties the L2 the next kernel reads from.
+hipError_t create_timing_event(hipEvent_t* ev);
+
 struct Timer {
     bool enabled;
     hipStream_t stream;

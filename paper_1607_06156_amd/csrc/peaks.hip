@@ -166,8 +166,8 @@ CC_API int cc_measure_peaks(cc_peaks* out, void* stream) {
     if ((rc = table.alloc(kTables[2], "hipMalloc(peak table)"))) return rc;
     if ((rc = sink.alloc((size_t)kBlocks * kPeakBlock * sizeof(int32_t), "hipMalloc(peak sink)"))) return rc;
     Events ev;
-    hipError_t e = hipEventCreate(&ev.a);
-    if (e == hipSuccess) e = hipEventCreate(&ev.b);
+    hipError_t e = create_timing_event(&ev.a);
+    if (e == hipSuccess) e = create_timing_event(&ev.b);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     // best of kReps launches after one warm-up, in ms
     auto timed = [&](auto launch, double* best) -> int {

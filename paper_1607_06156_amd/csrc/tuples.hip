@@ -386,8 +386,8 @@ CC_API int cc_label_tuples(const int32_t* u, const int32_t* v, int64_t m, int32_
     hipEvent_t ev[2];
     const bool timing = st != nullptr;
     if (timing) {
-        (void)hipEventCreate(&ev[0]);
-        (void)hipEventCreate(&ev[1]);
+        (void)create_timing_event(&ev[0]);
+        (void)create_timing_event(&ev[1]);
     }
     double ms_sort = 0.0;
     auto t_host = std::chrono::steady_clock::now();
