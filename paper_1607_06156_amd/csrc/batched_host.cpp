@@ -147,8 +147,8 @@ static int run_once(Workspace& ws, BatchArgsHost h, int blocks, int link, hipStr
     h.max_link = link;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ms) {
-        (void)create_timing_event(&e0);
-        (void)create_timing_event(&e1);
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
     }
     hipError_t e = hipMemsetAsync(pb, 0, kBatchCtl, s);
     if (e == hipSuccess && ms) e = hipEventRecord(e0, s);
@@ -210,8 +210,8 @@ static int run_union(Workspace& ws, const BatchArgsHost& h, hipStream_t s, unsig
     unsigned long long* bad = (unsigned long long*)pf;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (stats) {
-        (void)create_timing_event(&e0);
-        (void)create_timing_event(&e1);
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
         (void)hipEventRecord(e0, s);
     }
     hipError_t e = hipMemsetAsync(bad, 0, sizeof(unsigned long long), s);
