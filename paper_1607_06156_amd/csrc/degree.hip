@@ -239,10 +239,19 @@ __global__ __launch_bounds__(kStageThreads) void bucket_scatter_staged_kernel(
         const int32_t* pu = u + (t0 + t);
         const int32_t* pv = v + (t0 + t);
         if (t0 + kTile <= end) {
+            // The ids-only scatter streams the edges with non-temporal loads,
+            // so they do not push the partly written lines of its runs out of
+            // L2 (R-MAT scale 24: 1.54 -> 1.51 ms per degree call); the
+            // two-level scatter ran 0.09 ms slower with them.
 #pragma unroll
             for (int j = 0; j < E; ++j) {
-                a[j] = pu[j * kStageThreads];
-                c[j] = pv[j * kStageThreads];
+                if (!OTHER && !SUPER) {
+                    a[j] = __builtin_nontemporal_load(pu + j * kStageThreads);
+                    c[j] = __builtin_nontemporal_load(pv + j * kStageThreads);
+                } else {
+                    a[j] = pu[j * kStageThreads];
+                    c[j] = pv[j * kStageThreads];
+                }
             }
         } else {
             const int64_t rem = end - (t0 + t);   // edge j of the thread is before the end iff j * 1024 < rem
