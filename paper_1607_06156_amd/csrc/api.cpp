@@ -476,6 +476,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             // appears only in its last chunks).
             const int merge_at = chunks > kMergeAfter + 2 ? kMergeAfter : chunks;
             last_lo = std::min(merge_at, chunks - 1) * nseg_chunk;
+            int chain = -1;   // end mark of the previous group of launches
             for (int k = 0; k < chunks; ++k) {
                 for (int part = 0; part < (k == 0 ? split : 1); ++part) {
                     const int s0 = k > 0 ? k * nseg_chunk : (part == 0 ? 0 : cut);
@@ -483,11 +484,11 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                                  : k > 0 ? (k + 1) * nseg_chunk : (split == 1 || part == 1 ? nseg_chunk : cut);
                     const bool filt = s0 > 0 && gbits;
                     if (s0 > 0) {
-                        int kf = c.kbeg();
+                        int kf = c.kbeg_after(chain);
                         e = launch_sv_finalize(c.parent, c.n, totals + 6, c.stream);
                         if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
                         // parent read + one gather per vertex, at most one write
-                        c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n);
+                        chain = c.kmark(c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n));
                         flat_bytes += 12.0 * c.n;
                     }
                     if (filt) {
@@ -497,15 +498,15 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                         // instead of two gathers of parent[].  Sampled roots
                         // pick the tree; none holding 1/16 of the samples
                         // turns the probes off.
-                        int kg = c.kbeg();
+                        int kg = c.kbeg_after(chain);
                         e = launch_giant_pick(c.parent, c.n, gflag, c.stream);
                         if (e == hipSuccess) e = launch_giant_bits(c.parent, c.n, gflag, gbits, c.stream);
                         if (e != hipSuccess) return hip_fail(e, "giant bitmap launch");
                         // sampled gathers, parent read per vertex, bitmap written
-                        c.kend(CC_K_SV_SHORTCUT, kg, 4.0 * c.n + c.n / 8.0);
+                        chain = c.kmark(c.kend(CC_K_SV_SHORTCUT, kg, 4.0 * c.n + c.n / 8.0));
                         flat_bytes += 4.0 * c.n + c.n / 8.0;
                     }
-                    int k0 = c.kbeg();
+                    int k0 = c.kbeg_after(chain);
                     e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, s0, s1 - s0, write ? 1 : 0, max_link,
                                            (int32_t*)phook, hooked_count, totals, segstat, filt ? gbits : nullptr,
                                            filt ? gflag : nullptr, c.stream);
@@ -516,6 +517,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                     const int64_t e0 = std::min<int64_t>(m0, (int64_t)s0 * cap);
                     const int64_t e1 = std::min<int64_t>(m0, (int64_t)s1 * cap);
                     rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)(e1 - e0));
+                    chain = c.kmark(rec_pass);
                     if (filt) filt_edges += e1 - e0;
                 }
                 if (k >= merge_at) break;
@@ -525,21 +527,23 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             // gets the same chunked first pass as the caller's list
             const int segchunks = pass == 0 ? pass0_chunks(m_in, c.n) : 1;
             const int per = (nseg + segchunks - 1) / segchunks;
+            int chain = -1;   // end mark of the previous group of launches
             for (int s0 = 0; s0 < nseg; s0 += per) {
                 if (s0 > 0) {
-                    int kf = c.kbeg();
+                    int kf = c.kbeg_after(chain);
                     e = launch_sv_finalize(c.parent, c.n, totals + 6, c.stream);
                     if (e != hipSuccess) return hip_fail(e, "sv_finalize launch");
-                    c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n);
+                    chain = c.kmark(c.kend(CC_K_SV_SHORTCUT, kf, 12.0 * c.n));
                     flat_bytes += 12.0 * c.n;
                 }
                 const int nb = std::min(per, nseg - s0);
-                int k0 = c.kbeg();
+                int k0 = c.kbeg_after(chain);
                 e = launch_sv_pass_seg(in, s0, nb, c.parent, out, write ? 1 : 0, max_link, (int32_t*)phook,
                                        hooked_count, totals, segstat, c.stream);
                 if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
                 // this chunk's share of the edges (segments hold about equal counts)
                 rec_pass = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)m_in * nb / nseg);
+                chain = c.kmark(rec_pass);
             }
         }
         // After a chunked first pass, the full flatten before each launch has

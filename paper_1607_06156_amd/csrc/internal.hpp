@@ -161,6 +161,11 @@ struct Call {
         krecs.push_back(KRec{cls, a, b, kbytes});
         return (int)krecs.size() - 1;
     }
+    // The end mark of record rec, or -1.  A group of kernels enqueued right
+    // after another (nothing else in between) starts at that mark: one event
+    // fewer on the stream per group.
+    int kmark(int rec) const { return rec >= 0 ? krecs[rec].b : -1; }
+    int kbeg_after(int mark) { return mark >= 0 ? mark : kbeg(); }
     void kbytes(int rec, double kbytes) {
         if (rec >= 0) krecs[rec].bytes = kbytes;
     }
