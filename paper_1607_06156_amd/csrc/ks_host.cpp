@@ -33,6 +33,17 @@ static void radix_sort_u32(std::vector<uint32_t>& a) {
     }
 }
 
+// ln d of every exact-bin degree, computed once per process (the same values
+// std::log gives on each call; a fit sums up to 4095 of them)
+static const double* ln_exact() {
+    static const std::vector<double> t = [] {
+        std::vector<double> v(kExactBins, 0.0);
+        for (int d = 1; d < kExactBins; ++d) v[d] = std::log((double)d);
+        return v;
+    }();
+    return t.data();
+}
+
 int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* tail, int64_t ntail, KsResult* out) {
     *out = KsResult{};
     // distinct positive degrees (ascending) and their vertex counts
@@ -59,10 +70,11 @@ int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* ta
     if (V < 2) return CC_OK;
     // suffix sums: vertices and sum of ln d at or above each distinct value
     std::vector<double> tn(V), ts(V);
+    const double* lnx = ln_exact();
     double an = 0, as = 0;
     for (int32_t i = V - 1; i >= 0; --i) {
         an += cnts[i];
-        as += cnts[i] * std::log(vals[i]);
+        as += cnts[i] * (vals[i] < kExactBins ? lnx[(int)vals[i]] : std::log(vals[i]));
         tn[i] = an;
         ts[i] = as;
     }
