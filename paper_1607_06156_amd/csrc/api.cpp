@@ -35,7 +35,6 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-void clear_error() { g_err.clear(); }
 
 int hip_fail(hipError_t e, const char* what) {
     if (e == hipErrorOutOfMemory) return fail(CC_ENOMEM, "%s: %s", what, hipGetErrorString(e));

@@ -171,7 +171,6 @@ using namespace ccmi;
 
 CC_API int cc_check_labels(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const int32_t* labels,
                            void* stream, int64_t* bad) {
-    clear_error();
     if (!bad) return fail(CC_EINVAL, "NULL bad");
     bad[0] = bad[1] = bad[2] = 0;
     if (m < 0 || n < 0) return fail(CC_EINVAL, "negative size (m=%lld, n=%d)", (long long)m, n);

@@ -13,7 +13,6 @@
 namespace ccmi {
 
 int fail(int code, const char* fmt, ...);
-void clear_error();   // empties this thread's message
 int hip_fail(hipError_t e, const char* what);
 
 // workspace slots (grow-only device buffers, one set per device)
@@ -56,7 +55,8 @@ enum WsSlot {
 //            (workspace_bound), so no request outgrows it.
 // Small readbacks go through `host`: pinned staging of kHostBytes (kCached:
 // the device's own; otherwise taken from a shared pool for the call), or a
-// caller buffer of at least kHostBytes marked host_external.
+// caller buffer marked host_external, large enough for the readbacks of the
+// route it serves (cc_label_noalloc: 64 words for the SV route's counters).
 struct Workspace {
     enum Mode { kCached = 0, kPool = 1, kArena = 2 };
     struct Buf {

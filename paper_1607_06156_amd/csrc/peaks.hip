@@ -150,7 +150,6 @@ struct Events {
 using namespace ccmi;
 
 CC_API int cc_measure_peaks(cc_peaks* out, void* stream) {
-    clear_error();
     if (!out) return fail(CC_EINVAL, "NULL out");
     memset(out, 0, sizeof *out);
     hipStream_t s = (hipStream_t)stream;

@@ -157,7 +157,6 @@ using namespace ccmi;
 
 CC_API int cc_label64_ex(const int64_t* u, const int64_t* v, int64_t m, int64_t n_max, int64_t* ids,
                          int64_t* labels, int64_t* n_out, void* stream, const cc_options* opt_in, cc_stats* stats) {
-    clear_error();
     if (!n_out) return fail(CC_EINVAL, "NULL n_out");
     *n_out = 0;
     if (m < 0) return fail(CC_EINVAL, "negative m");

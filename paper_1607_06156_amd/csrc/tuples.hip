@@ -333,7 +333,6 @@ using namespace ccmi;
 
 CC_API int cc_label_tuples(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* labels, void* stream,
                            int32_t exclude, cc_tuple_stats* st) {
-    clear_error();
     if (st) memset(st, 0, sizeof *st);
     if (m < 0 || n < 0) return fail(CC_EINVAL, "negative size (m=%lld, n=%d)", (long long)m, n);
     if (m > 0 && n == 0) return fail(CC_EINVAL, "edges given for an empty vertex set");
