@@ -491,19 +491,40 @@ __device__ __forceinline__ void lds_inc_agg(uint32_t* h, uint32_t b) {
 }
 
 // per-vertex histogram update shared by the bucket pass and the standalone kernel
+// Degrees >= kExactBins go to the tail list.  A block stages up to kTailLds
+// of them in LDS and reserves their slots with one global atomic when it
+// flushes; R-MAT scale 24 has about 13 000 such vertices, and one returning
+// atomic each on the shared counter serialised chip-wide.
+constexpr int kTailLds = 1024;
+
 struct HistLds {
     uint32_t hx[kExactBins];
     uint32_t h64[64];
     unsigned long long best[kBlockD / 64];
+    uint32_t tn;                 // tail degrees seen by the block
+    unsigned long long tbase;    // first slot the block reserved
+    int32_t tbuf[kTailLds];
 };
+
+__device__ __forceinline__ void hist_init(HistLds& L, int nthreads) {
+    for (int j = threadIdx.x; j < kExactBins; j += nthreads) L.hx[j] = 0;
+    if (threadIdx.x < 64) L.h64[threadIdx.x] = 0;
+    if (threadIdx.x == 0) L.tn = 0;
+}
 
 __device__ __forceinline__ void hist_vertex(HistLds& L, uint32_t d, int32_t x, int32_t* tail, int64_t tail_cap,
                                             unsigned long long* tail_count, unsigned long long& best) {
     if (d < (uint32_t)kExactBins) {
         lds_inc_agg(L.hx, d);   // its log bin is taken from hx[d] at the flush
     } else {
-        unsigned long long slot = atomic_add_agent(tail_count, 1ull);
-        if ((int64_t)slot < tail_cap) tail[slot] = (int32_t)d;
+        const uint32_t k = atomicAdd(&L.tn, 1u);
+        if (k < (uint32_t)kTailLds) {
+            L.tbuf[k] = (int32_t)d;
+        } else {
+            // past the block's staging: a slot of its own
+            unsigned long long slot = atomic_add_agent(tail_count, 1ull);
+            if ((int64_t)slot < tail_cap) tail[slot] = (int32_t)d;
+        }
         atomicAdd(&L.h64[log_bin(d)], 1u);
     }
     unsigned long long key = ((unsigned long long)d << 32) | (unsigned long long)(~(uint32_t)x);
@@ -511,7 +532,8 @@ __device__ __forceinline__ void hist_vertex(HistLds& L, uint32_t d, int32_t x, i
 }
 
 __device__ __forceinline__ void hist_flush(HistLds& L, unsigned long long best, unsigned long long* hist64,
-                                           unsigned long long* histx, unsigned long long* argmax_key, int nthreads) {
+                                           unsigned long long* histx, unsigned long long* argmax_key, int32_t* tail,
+                                           int64_t tail_cap, unsigned long long* tail_count, int nthreads) {
     // the log bins of the degrees below kExactBins, from the exact bins
     for (int d = threadIdx.x; d < kExactBins; d += nthreads)
         if (L.hx[d]) atomicAdd(&L.h64[log_bin((uint32_t)d)], L.hx[d]);
@@ -520,7 +542,12 @@ __device__ __forceinline__ void hist_flush(HistLds& L, unsigned long long best, 
         best = o > best ? o : best;
     }
     if (lane_id() == 0) L.best[threadIdx.x >> 6] = best;
+    // the staged tail degrees: one reservation for the block
+    const uint32_t nt = L.tn < (uint32_t)kTailLds ? L.tn : (uint32_t)kTailLds;
+    if (threadIdx.x == 0 && nt) L.tbase = atomic_add_agent(tail_count, (unsigned long long)nt);
     __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nt; i += nthreads)
+        if ((int64_t)(L.tbase + i) < tail_cap) tail[L.tbase + i] = L.tbuf[i];
     for (int d = threadIdx.x; d < kExactBins; d += nthreads)
         if (L.hx[d]) atomic_add_agent(&histx[d], L.hx[d]);
     if (threadIdx.x < 64 && L.h64[threadIdx.x]) atomic_add_agent(&hist64[threadIdx.x], L.h64[threadIdx.x]);
@@ -692,8 +719,7 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
     int32_t nv = n - x0;
     if (nv > kBsz) nv = kBsz;
     for (int j = threadIdx.x; j < kCntWords; j += kBlockD) cnt[j] = 0;
-    for (int j = threadIdx.x; j < kExactBins; j += kBlockD) L.hx[j] = 0;
-    if (threadIdx.x < 64) L.h64[threadIdx.x] = 0;
+    hist_init(L, kBlockD);
     __syncthreads();
     Hubs hb;
     if (du && count_pairs) {
@@ -867,7 +893,7 @@ __global__ __launch_bounds__(kBlockD) void bucket_degree_kernel(
         if (want_hist) hist_vertex(L, d, x0 + j, tail, tail_cap, tail_count, best);
     }
     __syncthreads();
-    if (want_hist && count_pairs) hist_flush(L, best, hist64, histx, argmax_key, kBlockD);
+    if (want_hist && count_pairs) hist_flush(L, best, hist64, histx, argmax_key, tail, tail_cap, tail_count, kBlockD);
     if (!want_off) return;
     __syncthreads();
     // exclusive scan of cnt[0..kBsz) in place: 32 entries per thread
@@ -1150,14 +1176,13 @@ __global__ __launch_bounds__(kBlockD) void degree_hist_kernel(const int32_t* __r
                                                               unsigned long long* __restrict__ tail_count,
                                                               unsigned long long* __restrict__ argmax_key) {
     __shared__ HistLds L;
-    for (int j = threadIdx.x; j < kExactBins; j += kBlockD) L.hx[j] = 0;
-    if (threadIdx.x < 64) L.h64[threadIdx.x] = 0;
+    hist_init(L, kBlockD);
     __syncthreads();
     unsigned long long best = 0;
     for (int64_t x = (int64_t)blockIdx.x * kBlockD + threadIdx.x; x < n; x += (int64_t)gridDim.x * kBlockD)
         hist_vertex(L, (uint32_t)deg[x], (int32_t)x, tail, tail_cap, tail_count, best);
     __syncthreads();
-    hist_flush(L, best, hist64, histx, argmax_key, kBlockD);
+    hist_flush(L, best, hist64, histx, argmax_key, tail, tail_cap, tail_count, kBlockD);
 }
 
 // ------------------------------------------------------------------ host

@@ -491,3 +491,45 @@ def test_degree_with_hubs():
         assert np.array_equal(np.diff(off.cpu().numpy()), want), (n, hubs, "offsets")
         _, st = ccmi.label(to_dev(u), to_dev(v), n, route="heuristic", stats=True)
         assert st["max_degree"] == int(want.max())
+
+
+def test_tail_staging_overflow():
+    """Degrees of 4096 and more are staged per block (1024 at most) and
+    reserved with one atomic per block; past that a vertex takes its own
+    slot.  Every vertex in the tail (far past a block's staging), a tail list
+    shorter than the tail, and a bucket of the degree pass holding 1500 tail
+    vertices (its K-S statistic against the oracle's fit of the exact
+    degree distribution)."""
+    n = 200_000
+    deg = (4096 + np.arange(n) % 5000).astype(np.int32)
+    say("[gpu] tail staging: every vertex in the tail")
+    h64, hx, tail, tcount, amax = ccmi.degree_histograms(to_dev(deg))
+    e64, ex, etail = odeg.histograms(deg)
+    assert tcount == n
+    assert np.array_equal(h64.cpu().numpy(), e64) and np.array_equal(hx.cpu().numpy(), ex)
+    assert np.array_equal(np.sort(tail.cpu().numpy()), etail)
+    assert amax == int(np.argmax(deg))
+    _, _, tail2, tcount2, _ = ccmi.degree_histograms(to_dev(deg), tail_cap=5000)
+    t2 = tail2.cpu().numpy()
+    assert tcount2 == n and t2.size == 5000
+    # each entry a tail degree, none more often than it occurs
+    vals, cnt = np.unique(t2, return_counts=True)
+    ev, ec = np.unique(etail, return_counts=True)
+    pos = np.searchsorted(ev, vals)
+    assert np.all(ev[pos] == vals) and np.all(cnt <= ec[pos])
+    # the fused degree pass: 1500 vertices of bucket 0 with degree 4100
+    rng = np.random.default_rng(41)
+    nv = 1 << 20
+    hubs = np.repeat(np.arange(1500, dtype=np.int32), 4100)
+    others = rng.integers(1 << 15, nv, hubs.size).astype(np.int32)
+    u = np.concatenate([hubs, rng.integers(0, nv, 1 << 20).astype(np.int32)])
+    v = np.concatenate([others, rng.integers(0, nv, 1 << 20).astype(np.int32)])
+    say(f"[gpu] tail staging: degree pass, m={u.size}")
+    d = ccmi.degree(to_dev(u), to_dev(v), nv)
+    want = odeg.degree(u, v, nv)
+    assert np.array_equal(d.cpu().numpy(), want)
+    _, st = ccmi.label(to_dev(u), to_dev(v), nv, route="heuristic", stats=True)
+    vals, cnts = odeg.distribution(want)
+    exp = ks.fit(vals, cnts)
+    assert abs(st["ks_statistic"] - exp["ks"]) <= KS_TOL, (st["ks_statistic"], exp["ks"])
+    assert st["max_degree"] == int(want.max())
