@@ -114,6 +114,33 @@ __global__ __launch_bounds__(kScanThreads) void bucket_colscan_kernel(uint32_t* 
     if (t == 0) tot[k] = wsum[kScanThreads / 64];
 }
 
+// one block per bucket k, from a capped layout's fill counts (runcnt[k][b],
+// g scatter blocks of G chunks each): the counted layout's prefix at each
+// block's first chunk, prefix[k * nblk + b * G], and tot[k].  The counted
+// scatter with the same G reads only those entries.  g <= kScanThreads.
+__global__ __launch_bounds__(kScanThreads) void bucket_prefix_from_runs_kernel(
+    const uint32_t* __restrict__ runcnt, int32_t g, int32_t G, int32_t nblk, uint32_t* __restrict__ prefix,
+    unsigned long long* __restrict__ tot) {
+    __shared__ uint32_t wsum[kScanThreads / 64 + 1];
+    const int k = blockIdx.x, t = threadIdx.x;
+    const uint32_t c = t < g ? runcnt[(int64_t)k * g + t] : 0u;
+    uint32_t incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o);
+        if (lane_id() >= o) incl += y;
+    }
+    if (lane_id() == 63) wsum[t >> 6] = incl;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) { uint32_t q = wsum[w]; wsum[w] = acc; acc += q; }
+        wsum[kScanThreads / 64] = acc;
+    }
+    __syncthreads();
+    if (t < g) prefix[(int64_t)k * nblk + (int64_t)t * G] = wsum[t >> 6] + incl - c;
+    if (t == 0) tot[k] = wsum[kScanThreads / 64];
+}
+
 // single block: base[k] = exclusive prefix of tot, base[B] = total
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(const unsigned long long* __restrict__ tot, int32_t B,
                                                            unsigned long long* __restrict__ base) {
@@ -1339,9 +1366,25 @@ hipError_t launch_bucket_csr_from_deg(const int32_t* u, const int32_t* v, int64_
         return hipGetLastError();
     }
     if (!w.counted) {
-        // the degree pass used the capped layout: count and scan first (the
-        // ids were checked then; the error counter only grows)
-        count_and_scan(u, v, m, n, p, w, s);
+        // The degree pass used the capped layout.  Its fill counts are the
+        // counted layout's per-block counts (the same blocks read the same
+        // edges), so their scan replaces a second count over the edge list;
+        // the prefixes go to the CSR fill's scratch, unused until the fill.
+        // Without that scratch, count and scan again (the ids were checked
+        // then; the error counter only grows).
+        const int G = p.nblk >= 2 * kCUs ? p.nblk / kCUs : 1;
+        if (w.capped_grid > 0 && w.capped_grid == (p.nblk + G - 1) / G && w.tloc &&
+            (size_t)p.B * p.nblk * sizeof(uint32_t) <= (size_t)2 * m * sizeof(uint16_t)) {
+            uint32_t* prefix = (uint32_t*)w.tloc;
+            bucket_prefix_from_runs_kernel<<<p.B, kScanThreads, 0, s>>>(w.counts, w.capped_grid, G, p.nblk, prefix,
+                                                                         w.tot);
+            bucket_scan_kernel<<<1, 1024, 0, s>>>(w.tot, p.B, w.base);
+            w.counts = prefix;
+            w.counted = true;
+        } else {
+            count_and_scan(u, v, m, n, p, w, s);
+        }
+        w.capped_grid = 0;
         w.other_written = false;
     }
     if (!w.other_written) {
@@ -1388,6 +1431,7 @@ static void count_and_scan(const int32_t* u, const int32_t* v, int64_t m, int32_
     bucket_colscan_kernel<<<p.B, kScanThreads, 0, s>>>(w.counts, p.nblk, w.tot);
     bucket_scan_kernel<<<1, 1024, 0, s>>>(w.tot, p.B, w.base);
     w.counted = true;
+    w.capped_grid = 0;
 }
 
 hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, int32_t n, const BucketPlan& p,
@@ -1402,6 +1446,7 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
         // (one launch), and a CSR takes one more
         w.counted = false;
         w.other_written = false;
+        w.capped_grid = 0;
         bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(nullptr, nullptr, n, deg, 1, want_hist, hist64, histx, tail,
                                                       tail_cap, tail_count, argmax_key, 0, nullptr, nullptr, nullptr,
                                                       0, 0, u, v, m, w.err);
@@ -1415,6 +1460,7 @@ hipError_t launch_bucket_degree(const int32_t* u, const int32_t* v, int64_t m, i
             u, v, m, n, p.chunk, G, p.B, p.nblk, nullptr, nullptr, w.loc, nullptr, nullptr, cap, w.counts, w.err);
         w.counted = false;
         w.other_written = false;
+        w.capped_grid = grid;
         bucket_degree_kernel<<<p.B, kBlockD, 0, s>>>(w.loc, nullptr, n, deg, 1, want_hist, hist64, histx, tail,
                                                       tail_cap, tail_count, argmax_key, 0, nullptr, nullptr,
                                                       w.counts, grid, cap);

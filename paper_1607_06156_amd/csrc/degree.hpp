@@ -33,6 +33,7 @@ struct BucketBufs {
     unsigned long long* err;     // range errors
     uint32_t* gcnt;              // [B * kGroups] CSR fill: entries of each group placed so far
     int64_t loc_cap = 0;         // 16-bit entries loc can hold (the capped layout needs more than 2m)
+    int32_t capped_grid = 0;     // scatter blocks of a capped layout in counts (0: none)
     bool other_written = false;
     bool counted = false;        // counts / tot / base hold the counted layout's prefixes
 };

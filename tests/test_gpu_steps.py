@@ -533,3 +533,16 @@ def test_tail_staging_overflow():
     exp = ks.fit(vals, cnts)
     assert abs(st["ks_statistic"] - exp["ks"]) <= KS_TOL, (st["ks_statistic"], exp["ks"])
     assert st["max_degree"] == int(want.max())
+
+
+def test_csr_after_capped_prediction():
+    """After a capped prediction the BFS route's CSR takes its per-block
+    prefixes from the prediction's fill counts instead of counting the edges
+    again: one chunk per scatter block (R-MAT scale 18) and two (scale 21,
+    512 chunks over 256 blocks).  Labels exact against the oracle."""
+    for scale in (18, 21):
+        g = gen.rmat(scale, 16.0, seed=61 + scale, noise=0.1)
+        say(f"[gpu] CSR after a capped prediction, R-MAT scale {scale}, m={g.m}")
+        lab, st = ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route="heuristic", tau=1e300, stats=True)
+        assert st["route"] == ccmi.R0_BFS_SV
+        assert_labels_equal(lab, oracle_labels(g), f"rmat{scale} R0 after capped prediction")
