@@ -156,6 +156,8 @@ typedef struct cc_stats {
     int32_t check_flags;          /* bit 0: the debug checks ran and passed; bit 1: more SV passes than
                                      check_pass_limit */
     int32_t check_pass_limit;     /* 8 ceil(log2(n + 1)) + 64 when the checks ran, else 0 */
+    int32_t sv_hubs;              /* vertices of highest degree whose largest-tree probes the first pass
+                                     answered from LDS (degrees known and a chunked first pass), else 0 */
 } cc_stats;
 
 /* Fills *opt with the defaults (route AUTO, no cap, tau 0.05, theta 8). */

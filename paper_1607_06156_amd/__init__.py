@@ -63,7 +63,7 @@ class Stats(ctypes.Structure):
                 ("algorithmic_bytes", ctypes.c_double), ("kernel_ms", ctypes.c_double * 8),
                 ("kernel_launches", ctypes.c_int32 * 8), ("kernel_bytes", ctypes.c_double * 8),
                 ("sv_atomics", ctypes.c_int64), ("sv_chase_reads", ctypes.c_int64), ("giant_dropped", ctypes.c_int64),
-                ("check_flags", ctypes.c_int32), ("check_pass_limit", ctypes.c_int32)]
+                ("check_flags", ctypes.c_int32), ("check_pass_limit", ctypes.c_int32), ("sv_hubs", ctypes.c_int32)]
 
     def to_dict(self) -> dict:
         d = {}

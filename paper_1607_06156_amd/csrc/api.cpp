@@ -16,6 +16,7 @@
 
 #include "../../include/cc.h"
 #include "common.hpp"
+#include "hubs.hpp"
 #include "internal.hpp"
 
 #define CC_API extern "C" __attribute__((visibility("default")))
@@ -267,6 +268,7 @@ size_t workspace_bound(int64_t m, int32_t n, bool sv_only, size_t* per_slot) {
             b[WS_CURSOR] = 16 * M;   // two-level scatter with the other ends, CSR regroup, the rest's arrays
             b[WS_QUEUE] = align256(2 * M * sizeof(uint16_t)) + 2 * M * sizeof(int32_t);
             b[WS_DEG] = 4 * N;
+            if (b[WS_GIANT]) b[WS_GIANT] = align256(b[WS_GIANT]) + kHubBytes;   // the hub arrays
             const size_t tail = std::min(N, 2 * M / kExactBins + 1);
             b[WS_TAIL] = 4 * tail;
             b[WS_HISTOUT] = (64 + kExactBins + 4) * sizeof(unsigned long long);
@@ -423,10 +425,24 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
     // an int32 word of the totals block, its membership bitmap in WS_GIANT.
     int32_t* gflag = (int32_t*)(totals + 10);
     uint32_t* gbits = nullptr;
+    // With the degrees known, the hubs' list, their table and the table of
+    // those in the largest tree follow the bitmap; their count is a word of
+    // the totals block.
+    int32_t* hub_list = nullptr;
+    int4 *hub_ids = nullptr, *hub_tree = nullptr;
+    uint32_t* hub_count = (uint32_t*)(totals + 11);
+    bool hubs_listed = false;
     if (in0.soa && chunks > 1) {
+        const size_t bits_bytes = (size_t)((c.n + 63) / 64) * 8;
+        const bool hubs = c.hub_deg && c.hub_min > 0;
         void* pg;
-        if ((rc = ws.get(WS_GIANT, (size_t)((c.n + 63) / 64) * 8, &pg))) return rc;
+        if ((rc = ws.get(WS_GIANT, hubs ? align256(bits_bytes) + kHubBytes : bits_bytes, &pg))) return rc;
         gbits = (uint32_t*)pg;
+        if (hubs) {
+            hub_list = (int32_t*)((char*)pg + align256(bits_bytes));
+            hub_ids = (int4*)(hub_list + kHubMax);
+            hub_tree = hub_ids + kHubBuckets;
+        }
     }
     int2* bufs[2] = {(int2*)pbuf0, (int2*)pbuf1};
 
@@ -498,17 +514,28 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                         // pick the tree; none holding 1/16 of the samples
                         // turns the probes off.
                         int kg = c.kbeg_after(chain);
-                        e = launch_giant_pick(c.parent, c.n, gflag, c.stream);
-                        if (e == hipSuccess) e = launch_giant_bits(c.parent, c.n, gflag, gbits, c.stream);
+                        double gbytes = 4.0 * c.n + c.n / 8.0;   // parent read per vertex, bitmap written
+                        e = hipSuccess;
+                        if (hub_list && !hubs_listed) {
+                            // once per call: the hubs (degree read per vertex) and their table
+                            e = launch_hub_list(c.hub_deg, c.n, c.hub_min, hub_list, hub_count, hub_ids, c.stream);
+                            hubs_listed = true;
+                            gbytes += 4.0 * c.n;
+                        }
+                        if (e == hipSuccess) e = launch_giant_pick(c.parent, c.n, gflag, c.stream);
+                        if (e == hipSuccess)
+                            e = hub_list ? launch_giant_bits_hubs(c.parent, c.n, gflag, gbits, hub_ids, hub_tree,
+                                                                  c.stream)
+                                         : launch_giant_bits(c.parent, c.n, gflag, gbits, c.stream);
                         if (e != hipSuccess) return hip_fail(e, "giant bitmap launch");
-                        // sampled gathers, parent read per vertex, bitmap written
-                        chain = c.kmark(c.kend(CC_K_SV_SHORTCUT, kg, 4.0 * c.n + c.n / 8.0));
-                        flat_bytes += 4.0 * c.n + c.n / 8.0;
+                        chain = c.kmark(c.kend(CC_K_SV_SHORTCUT, kg, gbytes));
+                        flat_bytes += gbytes;
                     }
                     int k0 = c.kbeg_after(chain);
-                    e = launch_sv_pass_soa(in0.u, in0.v, m0, c.n, c.parent, out, s0, s1 - s0, write ? 1 : 0, max_link,
-                                           (int32_t*)phook, hooked_count, totals, segstat, filt ? gbits : nullptr,
-                                           filt ? gflag : nullptr, c.stream);
+                    e = launch_sv_pass_soa_hubs(in0.u, in0.v, m0, c.n, c.parent, out, s0, s1 - s0, write ? 1 : 0,
+                                                max_link, (int32_t*)phook, hooked_count, totals, segstat,
+                                                filt ? gbits : nullptr, filt ? gflag : nullptr,
+                                                filt ? hub_tree : nullptr, c.stream);
                     if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
                     // this launch's edges (read + two 4-byte gathers or bit
                     // probes each); the rest of the pass's bytes go to the
@@ -551,7 +578,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         const int jump_lo = in_soa && chunks > 1 ? last_lo : 0;
         e = launch_sv_totals(hooked_count, out.count, nseg, jump_lo, segstat, totals, c.stream);
         if (e != hipSuccess) return hip_fail(e, "sv_totals launch");
-        e = hipMemcpyAsync(htot, totals, 10 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
+        e = hipMemcpyAsync(htot, totals, 12 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(totals)");
         e = hipStreamSynchronize(c.stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -590,6 +617,7 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
             c.stats->sv_atomics += natom;
             c.stats->sv_chase_reads += nchase;
             c.stats->giant_dropped += ndrop;
+            if (pass == 0 && hubs_listed) c.stats->sv_hubs = (int32_t)std::min<uint32_t>((uint32_t)htot[11], kHubMax);
             // edges read (8 B) with two 4 B gathers (or bit probes) each, the
             // two parent gathers of the edges that passed the bitmap, 8 B per
             // atomic issued, 4 B per read of the walks up the forest, and the

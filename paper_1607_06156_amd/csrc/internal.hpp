@@ -144,6 +144,10 @@ struct Call {
     bool range_checked = false;
     // step entry points may direct the degree pass's outputs into caller arrays
     int32_t* deg_out = nullptr;
+    // degrees known before SV (heuristic route): hubs are the vertices of
+    // degree >= hub_min, given a table in the first pass's filtered launches
+    const int32_t* hub_deg = nullptr;
+    int32_t hub_min = 0;
     int64_t* off_out = nullptr;
     int32_t* adj_out = nullptr;
     // per-kernel profiling (opt.profile with stats): event pairs per launch
@@ -200,6 +204,7 @@ struct DegreeResult {
     int64_t ntail = 0;
     int64_t max_degree = 0;
     int32_t argmax = -1;
+    int64_t hub_min = 0;               // hub threshold from the power-law fit (0: none)
     bool csr_built = false;
     bool prefetch_tail = false;        // set by the caller: read the tail back with the histograms
     const int32_t* tail_host = nullptr;   // the first tail_host_n tail entries, in pinned host memory

@@ -25,6 +25,9 @@ struct KsResult {
     int64_t dmin = 0;
     int64_t ntail = 0;
     int64_t candidates = 0;
+    // the smallest distinct degree d >= kHubMinDegree with at most kHubMax
+    // vertices of degree >= d (0: none), the hub threshold of the first SV pass
+    int64_t hub_min = 0;
 };
 
 struct Workspace;

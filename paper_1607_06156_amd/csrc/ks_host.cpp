@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "degree.hpp"
+#include "hubs.hpp"
 #include "internal.hpp"
 #include "ks.hpp"
 
@@ -78,6 +79,11 @@ int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* ta
         tn[i] = an;
         ts[i] = as;
     }
+    for (int32_t i = 0; i < V; ++i)
+        if (vals[i] >= (double)kHubMinDegree && tn[i] <= (double)kHubMax) {
+            out->hub_min = (int64_t)vals[i];
+            break;
+        }
     std::vector<int32_t> cand;
     for (int32_t i = 0; i < V; ++i)
         if (tn[i] >= (double)kMinTail && V - i >= 2) cand.push_back(i);

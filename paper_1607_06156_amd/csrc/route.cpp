@@ -205,6 +205,7 @@ int decide_heuristic(Call& c, DegreeResult& r, int* route) {
         c.stats->ks_alpha = k.alpha;
         c.stats->ks_dmin = k.dmin;
     }
+    r.hub_min = k.hub_min;
     *route = (k.ks < c.opt.tau) ? CC_R0_BFS_SV : CC_R1_SV;
     return CC_OK;
 }
@@ -551,6 +552,10 @@ int run_label(Call& c) {
     if (route == CC_R0_BFS_SV) {
         if (dr.argmax < 0) route = CC_R1_SV;   // no edge with a valid endpoint: nothing to traverse
         else return run_bfs_route(c, dr);
+    }
+    if (dr.deg && dr.hub_min > 0 && dr.hub_min < INT32_MAX) {
+        c.hub_deg = dr.deg;
+        c.hub_min = (int32_t)dr.hub_min;
     }
     SvInput in;
     in.soa = true;

@@ -29,6 +29,7 @@
 // The loop ends when no edge is active, and the forest roots are then the
 // component minima.
 #include "common.hpp"
+#include "hubs.hpp"
 #include "sv_device.hpp"
 
 namespace ccmi {
@@ -39,6 +40,18 @@ __global__ __launch_bounds__(kBlock) void sv_init_kernel(int32_t* __restrict__ p
     for (; i < n; i += stride) parent[i] = (int32_t)i;
 }
 
+// Hub tables: kHubBuckets buckets of 4 vertex ids (-1 = empty), bucket by a
+// multiplicative hash of the id.  A filtered launch of the first pass keeps
+// the table of the largest tree's hubs in LDS and answers their probes there;
+// an id that is not in it (its bucket was full, or it is no hub or not in the
+// tree) is probed in the bitmap as before.
+__device__ __forceinline__ uint32_t hub_bucket(int32_t x) { return ((uint32_t)x * 2654435761u) >> (32 - kHubBits); }
+
+__device__ __forceinline__ bool in_hubs(const int4* lhub, int32_t x) {
+    const int4 q = lhub[hub_bucket(x)];
+    return (q.x == x) | (q.y == x) | (q.z == x) | (q.w == x);
+}
+
 // One pass: hook + compact over one block segment of edges.
 // SOA: edges come from the caller's u[], v[] (dense); the block works on
 // segment b = seg0 + blockIdx.x, edges [b*cap, min((b+1)*cap, m)), and checks
@@ -46,6 +59,7 @@ __global__ __launch_bounds__(kBlock) void sv_init_kernel(int32_t* __restrict__ p
 // FILT (SOA only): while *gflag >= 0, an edge whose two endpoints both have
 // their bit set in gbits (vertices already in the largest tree when the
 // bitmap was built) is finished and dropped without touching parent[].
+// With hubt (FILT), the hubs that table lists take their bit from LDS.
 // segstat[3 b ...] receives the block's atomics issued, chase reads and edges
 // dropped by the bitmap.
 template <bool SOA, bool FILT>
@@ -57,9 +71,11 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
                                                          unsigned long long* __restrict__ totals,
                                                          const uint32_t* __restrict__ gbits,
                                                          const int32_t* __restrict__ gflag,
-                                                         uint32_t* __restrict__ segstat) {
+                                                         uint32_t* __restrict__ segstat,
+                                                         const int4* __restrict__ hubt) {
     __shared__ uint32_t lds[kWaves + 1];
     __shared__ uint32_t red[3][kWaves];
+    __shared__ int4 lhub[FILT ? kHubBuckets : 1];   // the largest tree's hubs (filtered launches)
     const int b = seg0 + blockIdx.x;
     int2* dst = out.buf + (int64_t)b * out.cap;
     int32_t* hdst = hooked + (int64_t)b * out.cap;
@@ -70,6 +86,13 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
         if (len > out.cap) len = out.cap;
         if (len < 0) len = 0;
         const bool filt = FILT && *gflag >= 0;
+        // hubs of the largest tree: their probes are answered from LDS
+        const bool hubs = filt && hubt != nullptr;
+        if (FILT) {
+            if (hubs)
+                for (int i = threadIdx.x; i < kHubBuckets; i += kBlock) lhub[i] = hubt[i];
+            __syncthreads();
+        }
         // Every read of a tile goes out before any is used: the edges (read
         // once, with non-temporal loads that keep them from displacing
         // parent[] and the bitmap in the caches), then the bit probes.
@@ -96,10 +119,16 @@ __global__ __launch_bounds__(kBlock) void sv_pass_kernel(const int32_t* __restri
             }
             if (filt) {
                 uint32_t wa[kEPT], wc[kEPT];
+                bool ha[kEPT], hc[kEPT];
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) {
-                    wa[k] = gbits[(uint32_t)(valid[k] ? a[k] : 0) >> 5];
-                    wc[k] = gbits[(uint32_t)(valid[k] ? c[k] : 0) >> 5];
+                    ha[k] = hubs && valid[k] && in_hubs(lhub, a[k]);
+                    hc[k] = hubs && valid[k] && in_hubs(lhub, c[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < kEPT; ++k) {
+                    wa[k] = valid[k] && !ha[k] ? gbits[(uint32_t)a[k] >> 5] : 0xffffffffu;
+                    wc[k] = valid[k] && !hc[k] ? gbits[(uint32_t)c[k] >> 5] : 0xffffffffu;
                 }
 #pragma unroll
                 for (int k = 0; k < kEPT; ++k) {
@@ -221,14 +250,25 @@ __global__ __launch_bounds__(kPickThreads) void giant_pick_kernel(const int32_t*
 // parent[x] is that tree's root, or x is the root.  Run right after a flatten,
 // with no hook in flight, so a set bit means x is in that tree; a vertex left
 // short of its root by the flatten's walk bound simply keeps a clear bit.
-// One wave covers 64 consecutive vertices and writes two words.
+// One wave covers 64 consecutive vertices and writes two words.  With ids
+// (a hub table), the last workgroup also writes tree_ids: ids with every hub
+// whose bit stays clear replaced by -1.
 __global__ __launch_bounds__(kBlock) void giant_bits_kernel(const int32_t* __restrict__ parent, int32_t n,
                                                             const int32_t* __restrict__ gflag,
-                                                            uint32_t* __restrict__ bits) {
+                                                            uint32_t* __restrict__ bits,
+                                                            const int4* __restrict__ ids,
+                                                            int4* __restrict__ tree_ids) {
     const int32_t g = *gflag;
     if (g < 0) return;
     bool root;
     const int32_t gr = find_bounded(parent, g, &root);
+    if (ids && blockIdx.x == gridDim.x - 1) {
+        auto keep = [&](int32_t x) { return x >= 0 && (x == gr || parent[x] == gr) ? x : -1; };
+        for (int i = threadIdx.x; i < kHubBuckets; i += kBlock) {
+            const int4 q = ids[i];
+            tree_ids[i] = make_int4(keep(q.x), keep(q.y), keep(q.z), keep(q.w));
+        }
+    }
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t x0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) & ~(int64_t)63; x0 < n; x0 += stride) {
         const int64_t x = x0 + lane_id();
@@ -236,6 +276,45 @@ __global__ __launch_bounds__(kBlock) void giant_bits_kernel(const int32_t* __res
         const uint64_t mk = ballot(in);
         if (lane_id() == 0) *(uint2*)(bits + (x0 >> 5)) = make_uint2((uint32_t)mk, (uint32_t)(mk >> 32));
     }
+}
+
+// Hub list: the ids x with deg[x] >= dmin, appended in wave order; at most
+// kHubMax are kept (the caller's dmin admits no more).
+__global__ __launch_bounds__(kBlock) void hub_list_kernel(const int32_t* __restrict__ deg, int32_t n, int32_t dmin,
+                                                          int32_t* __restrict__ list, uint32_t* __restrict__ count) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t x0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) & ~(int64_t)63; x0 < n; x0 += stride) {
+        const int64_t x = x0 + lane_id();
+        const bool hub = x < n && deg[x] >= dmin;
+        const uint64_t mk = ballot(hub);
+        if (mk == 0) continue;
+        uint32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(count, (uint32_t)__popcll(mk));
+        base = __shfl(base, 0);
+        const uint32_t at = base + (uint32_t)__popcll(mk & ((1ull << lane_id()) - 1));
+        if (hub && at < (uint32_t)kHubMax) list[at] = (int32_t)x;
+    }
+}
+
+// One workgroup: the hub table of the listed ids (first come, first placed
+// in its bucket; a fifth id of a bucket is left out).
+constexpr int kHubTableThreads = 1024;
+__global__ __launch_bounds__(kHubTableThreads) void hub_table_kernel(const int32_t* __restrict__ list,
+                                                                     const uint32_t* __restrict__ count,
+                                                                     int4* __restrict__ ids) {
+    __shared__ int32_t t[kHubBuckets * 4];
+    for (int i = threadIdx.x; i < kHubBuckets * 4; i += kHubTableThreads) t[i] = -1;
+    __syncthreads();
+    const uint32_t cnt = min(*count, (uint32_t)kHubMax);
+    for (uint32_t j = threadIdx.x; j < cnt; j += kHubTableThreads) {
+        const int32_t x = list[j];
+        int32_t* b = t + 4 * hub_bucket(x);
+        for (int k = 0; k < 4; ++k)
+            if (atomicCAS(&b[k], -1, x) == -1) break;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHubBuckets; i += kHubTableThreads)
+        ids[i] = make_int4(t[4 * i], t[4 * i + 1], t[4 * i + 2], t[4 * i + 3]);
 }
 
 // Pointer jumping for the roots hooked in the last pass: each is pointed at
@@ -386,21 +465,30 @@ hipError_t launch_sv_init(int32_t* parent, int32_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
-                              SegList out, int32_t seg0, int32_t nblocks, int write_out, int max_link,
-                              int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
-                              uint32_t* segstat, const uint32_t* gbits, const int32_t* gflag, hipStream_t s) {
+hipError_t launch_sv_pass_soa_hubs(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
+                                   SegList out, int32_t seg0, int32_t nblocks, int write_out, int max_link,
+                                   int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
+                                   uint32_t* segstat, const uint32_t* gbits, const int32_t* gflag,
+                                   const int4* tree_ids, hipStream_t s) {
     if (seg0 < 0 || nblocks < 1 || seg0 + nblocks > out.nseg) return hipErrorInvalidValue;
     SegList none{nullptr, 0, 0, nullptr};
     if (gbits && gflag)
         sv_pass_kernel<true, true><<<nblocks, kBlock, 0, s>>>(u, v, m, n, seg0, none, parent, out, write_out,
                                                               max_link, hooked, hooked_count, totals, gbits, gflag,
-                                                              segstat);
+                                                              segstat, tree_ids);
     else
         sv_pass_kernel<true, false><<<nblocks, kBlock, 0, s>>>(u, v, m, n, seg0, none, parent, out, write_out,
                                                                max_link, hooked, hooked_count, totals, nullptr,
-                                                               nullptr, segstat);
+                                                               nullptr, segstat, nullptr);
     return hipGetLastError();
+}
+
+hipError_t launch_sv_pass_soa(const int32_t* u, const int32_t* v, int64_t m, int32_t n, int32_t* parent,
+                              SegList out, int32_t seg0, int32_t nblocks, int write_out, int max_link,
+                              int32_t* hooked, uint32_t* hooked_count, unsigned long long* totals,
+                              uint32_t* segstat, const uint32_t* gbits, const int32_t* gflag, hipStream_t s) {
+    return launch_sv_pass_soa_hubs(u, v, m, n, parent, out, seg0, nblocks, write_out, max_link, hooked, hooked_count,
+                                   totals, segstat, gbits, gflag, nullptr, s);
 }
 
 hipError_t launch_sv_pass_seg(SegList in, int32_t seg0, int32_t nblocks, int32_t* parent, SegList out, int write_out,
@@ -409,7 +497,7 @@ hipError_t launch_sv_pass_seg(SegList in, int32_t seg0, int32_t nblocks, int32_t
     if (seg0 < 0 || nblocks < 1 || seg0 + nblocks > in.nseg || in.nseg > out.nseg) return hipErrorInvalidValue;
     sv_pass_kernel<false, false><<<nblocks, kBlock, 0, s>>>(nullptr, nullptr, 0, 0, seg0, in, parent, out, write_out,
                                                             max_link, hooked, hooked_count, totals, nullptr, nullptr,
-                                                            segstat);
+                                                            segstat, nullptr);
     return hipGetLastError();
 }
 
@@ -421,7 +509,22 @@ hipError_t launch_giant_pick(const int32_t* parent, int32_t n, int32_t* gflag, h
 
 hipError_t launch_giant_bits(const int32_t* parent, int32_t n, const int32_t* gflag, uint32_t* bits, hipStream_t s) {
     if (n <= 0) return hipErrorInvalidValue;
-    giant_bits_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(parent, n, gflag, bits);
+    giant_bits_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(parent, n, gflag, bits, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_giant_bits_hubs(const int32_t* parent, int32_t n, const int32_t* gflag, uint32_t* bits,
+                                  const int4* ids, int4* tree_ids, hipStream_t s) {
+    if (n <= 0 || !ids || !tree_ids) return hipErrorInvalidValue;
+    giant_bits_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(parent, n, gflag, bits, ids, tree_ids);
+    return hipGetLastError();
+}
+
+hipError_t launch_hub_list(const int32_t* deg, int32_t n, int32_t dmin, int32_t* list, uint32_t* count, int4* ids,
+                           hipStream_t s) {
+    if (n <= 0) return hipErrorInvalidValue;
+    hub_list_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(deg, n, dmin, list, count);
+    hub_table_kernel<<<1, kHubTableThreads, 0, s>>>(list, count, ids);
     return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ CSRC = os.path.join("paper_1607_06156_amd", "csrc")
 # source files that decide the work and memory traffic of each kernel class
 # (kernel body, shared device helpers, launch configuration)
 KERNEL_SOURCES = {
-    "sv_pass": ["sv.hip", "sv_device.hpp", "common.hpp", "api.cpp"],
+    "sv_pass": ["sv.hip", "sv_device.hpp", "common.hpp", "hubs.hpp", "api.cpp"],
     "degree": ["degree.hip", "degree.hpp", "common.hpp", "route.cpp"],
     "bfs": ["bfs.hip", "bfs.hpp", "common.hpp", "route.cpp"],
     "filter": ["bfs.hip", "common.hpp", "route.cpp"],

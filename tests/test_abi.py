@@ -22,7 +22,9 @@ def lib():
     if not os.path.exists(LIB):
         from paper_1607_06156_amd import build
         build.build()
-    return ctypes.CDLL(LIB)
+    lib = ctypes.CDLL(LIB)
+    lib.cc_last_error.restype = ctypes.c_char_p   # every test may read the message, in any order
+    return lib
 
 
 def test_header_declares_the_boundary():

@@ -165,7 +165,10 @@ def test_largest_tree_bitmap(route, name, drops):
     inside it.  R-MAT graphs drop most of their later chunks that way; a
     forest of small components has no tree holding 1/16 of the vertices and
     drops nothing.  Labels are exact either way, and the byte counters add
-    up (every atomic issued is a hook, a failed hook or a retry)."""
+    up (every atomic issued is a hook, a failed hook or a retry).  With the
+    degrees known (predicted-sv), the R-MAT hubs' probes come from the LDS
+    table; the other routes list no hubs, nor does the lattice (no degree
+    reaches the hub minimum)."""
     if name == "grid2048":
         g = gen.grid(2048, 0.7, seed=5)
     elif name == "plcomp4m":
@@ -181,3 +184,7 @@ def test_largest_tree_bitmap(route, name, drops):
     elif drops is False:
         assert st["giant_dropped"] == 0
     assert st["sv_atomics"] >= st["hooks_total"]
+    if route == "predicted-sv" and drops is True:
+        assert 0 < st["sv_hubs"] <= 2048
+    elif route != "predicted-sv" or name == "grid2048":
+        assert st["sv_hubs"] == 0
