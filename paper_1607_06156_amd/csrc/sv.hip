@@ -251,8 +251,9 @@ __global__ __launch_bounds__(kPickThreads) void giant_pick_kernel(const int32_t*
 // with no hook in flight, so a set bit means x is in that tree; a vertex left
 // short of its root by the flatten's walk bound simply keeps a clear bit.
 // One wave covers 64 consecutive vertices and writes two words.  With ids
-// (a hub table), the last workgroup also writes tree_ids: ids with every hub
-// whose bit stays clear replaced by -1.
+// (a hub table), the first workgroups (which start first) also write
+// tree_ids: ids with every hub whose bit stays clear replaced by -1, one
+// bucket per thread.
 __global__ __launch_bounds__(kBlock) void giant_bits_kernel(const int32_t* __restrict__ parent, int32_t n,
                                                             const int32_t* __restrict__ gflag,
                                                             uint32_t* __restrict__ bits,
@@ -262,9 +263,10 @@ __global__ __launch_bounds__(kBlock) void giant_bits_kernel(const int32_t* __res
     if (g < 0) return;
     bool root;
     const int32_t gr = find_bounded(parent, g, &root);
-    if (ids && blockIdx.x == gridDim.x - 1) {
+    if (ids && (int)blockIdx.x < kHubBuckets / kBlock) {
         auto keep = [&](int32_t x) { return x >= 0 && (x == gr || parent[x] == gr) ? x : -1; };
-        for (int i = threadIdx.x; i < kHubBuckets; i += kBlock) {
+        const int tb = min((int)gridDim.x, kHubBuckets / kBlock);   // workgroups writing the table
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < kHubBuckets; i += tb * kBlock) {
             const int4 q = ids[i];
             tree_ids[i] = make_int4(keep(q.x), keep(q.y), keep(q.z), keep(q.w));
         }
@@ -279,20 +281,31 @@ __global__ __launch_bounds__(kBlock) void giant_bits_kernel(const int32_t* __res
 }
 
 // Hub list: the ids x with deg[x] >= dmin, appended in wave order; at most
-// kHubMax are kept (the caller's dmin admits no more).
+// kHubMax are kept (the caller's dmin admits no more).  A wave reads
+// kHubU runs of 64 consecutive degrees before it tests any.
+constexpr int kHubU = 4;
 __global__ __launch_bounds__(kBlock) void hub_list_kernel(const int32_t* __restrict__ deg, int32_t n, int32_t dmin,
                                                           int32_t* __restrict__ list, uint32_t* __restrict__ count) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t x0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) & ~(int64_t)63; x0 < n; x0 += stride) {
-        const int64_t x = x0 + lane_id();
-        const bool hub = x < n && deg[x] >= dmin;
-        const uint64_t mk = ballot(hub);
-        if (mk == 0) continue;
-        uint32_t base = 0;
-        if (lane_id() == 0) base = atomicAdd(count, (uint32_t)__popcll(mk));
-        base = __shfl(base, 0);
-        const uint32_t at = base + (uint32_t)__popcll(mk & ((1ull << lane_id()) - 1));
-        if (hub && at < (uint32_t)kHubMax) list[at] = (int32_t)x;
+    const int64_t per = 64 * kHubU;   // vertices per wave and step
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64) * per;
+    for (int64_t x0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64 * per; x0 < n; x0 += stride) {
+        int32_t d[kHubU];
+#pragma unroll
+        for (int j = 0; j < kHubU; ++j) {
+            const int64_t x = x0 + j * 64 + lane_id();
+            d[j] = x < n ? deg[x] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kHubU; ++j) {
+            const bool hub = d[j] >= dmin;   // dmin >= 1, so lanes past n never qualify
+            const uint64_t mk = ballot(hub);
+            if (mk == 0) continue;
+            uint32_t base = 0;
+            if (lane_id() == 0) base = atomicAdd(count, (uint32_t)__popcll(mk));
+            base = __shfl(base, 0);
+            const uint32_t at = base + (uint32_t)__popcll(mk & ((1ull << lane_id()) - 1));
+            if (hub && at < (uint32_t)kHubMax) list[at] = (int32_t)(x0 + j * 64 + lane_id());
+        }
     }
 }
 
@@ -523,7 +536,8 @@ hipError_t launch_giant_bits_hubs(const int32_t* parent, int32_t n, const int32_
 hipError_t launch_hub_list(const int32_t* deg, int32_t n, int32_t dmin, int32_t* list, uint32_t* count, int4* ids,
                            hipStream_t s) {
     if (n <= 0) return hipErrorInvalidValue;
-    hub_list_kernel<<<grid_for(n, 4), kBlock, 0, s>>>(deg, n, dmin, list, count);
+    if (dmin < 1) return hipErrorInvalidValue;
+    hub_list_kernel<<<grid_for(n, kHubU), kBlock, 0, s>>>(deg, n, dmin, list, count);
     hub_table_kernel<<<1, kHubTableThreads, 0, s>>>(list, count, ids);
     return hipGetLastError();
 }
