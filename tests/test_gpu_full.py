@@ -35,7 +35,7 @@ def workload(name):
     ("gnm64k", ["sv", "sv-theta", "bfs+sv", "heuristic"]),
     ("rmat24", ["heuristic", "sv", "bfs+sv", "sv-theta"]),
     ("rmat24noisy", ["heuristic", "sv"]),
-    ("grid8192", ["sv", "sv-theta"]),
+    ("grid8192", ["sv", "sv-theta", "heuristic"]),
     ("plcomp200m", ["sv", "heuristic", "bfs+sv", "router"]),
 ])
 def test_full_workload(name, routes):
