@@ -188,3 +188,31 @@ def test_largest_tree_bitmap(route, name, drops):
         assert 0 < st["sv_hubs"] <= 2048
     elif route != "predicted-sv" or name == "grid2048":
         assert st["sv_hubs"] == 0
+
+
+
+def test_hub_table_full_bucket():
+    """R-MAT scale 18 with its twelve highest-degree vertices renamed to ids
+    that share one bucket of the LDS hub table (a bucket holds four ids): the
+    hubs left out of the table are probed in the largest tree's bitmap
+    instead.  The list (2^22 edges) gets a chunked first pass, and the
+    largest tree drops most later edges, so the table is in use.  Labels
+    exact against the oracle."""
+    g0 = gen.workload("rmat18")
+    n = g0.n
+    xs = np.arange(n, dtype=np.uint64)
+    bucket = ((xs * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF)) >> np.uint64(22)
+    same = np.flatnonzero(bucket == 0)[:12]
+    deg = np.bincount(g0.u, minlength=n) + np.bincount(g0.v, minlength=n)
+    top = np.argsort(-deg, kind="stable")[:12]
+    f = np.arange(n, dtype=np.int64)   # a permutation of the ids: swap each top vertex with a shared-bucket id
+    for a, b in zip(top, same):
+        ia, ib = np.flatnonzero(f == a)[0], np.flatnonzero(f == b)[0]
+        f[ia], f[ib] = b, a
+    new_top = f[top]
+    assert int(np.sum(bucket[new_top] == 0)) >= 8
+    g = gen.Graph(f[g0.u].astype(np.int32), f[g0.v].astype(np.int32), n, "rmat18, top hubs in one bucket")
+    lab, st = run(g, "predicted-sv", stats=True)
+    assert st["route"] == ccmi.R1_SV and 12 <= st["sv_hubs"] <= 2048
+    assert st["giant_dropped"] > g.m // 2
+    assert_labels_equal(lab, oracle_labels(g), g.name)
