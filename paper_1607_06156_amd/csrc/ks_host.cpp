@@ -50,6 +50,8 @@ int ks_fit(Workspace& ws, hipStream_t s, const int64_t* histx, const int32_t* ta
     // distinct positive degrees (ascending) and their vertex counts
     std::vector<double> vals;
     std::vector<double> cnts;
+    vals.reserve((size_t)kExactBins + (size_t)std::max<int64_t>(ntail, 0));
+    cnts.reserve(vals.capacity());
     for (int d = 1; d < kExactBins; ++d)
         if (histx[d] > 0) {
             vals.push_back((double)d);
