@@ -197,6 +197,27 @@ int Workspace::pinned(void** out) {
 
 static std::mutex g_ws_mu;
 static std::unordered_map<int, Workspace*> g_ws;
+
+// One more stream per device (default priority, not synchronising with the
+// null stream): the power-law fit runs on it beside a speculative SV launch.
+static std::mutex g_side_mu;
+static std::unordered_map<int, hipStream_t> g_side;
+
+int side_stream(hipStream_t* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_side_mu);
+    auto it = g_side.find(dev);
+    if (it == g_side.end()) {
+        hipStream_t s = nullptr;
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        it = g_side.emplace(dev, s).first;
+    }
+    *out = it->second;
+    return CC_OK;
+}
 static std::unordered_map<int, hipMemPool_t> g_pools;
 
 int acquire_workspace(Workspace** out) {
@@ -386,18 +407,76 @@ static int flatten_all(Call& c, unsigned long long* open, unsigned long long* hp
     }
 }
 
-int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes) {
+// Segments of the first pass over a caller's list of m0 edges: chunks of
+// nseg_chunk segments of cap edges; on dense lists the first chunk runs as
+// [0, cut) and [cut, nseg_chunk) (split = 2).
+struct SvGeom {
+    int chunks = 1, nseg_chunk = 0, nseg = 0, split = 1, cut = 1;
+    int64_t cap = 1;
+};
+
+static SvGeom sv_geometry(int64_t m0, int32_t n) {
+    SvGeom g;
+    g.chunks = pass0_chunks(m0, n);
+    g.nseg_chunk = choose_nseg((m0 + g.chunks - 1) / g.chunks);
+    g.nseg = g.chunks * g.nseg_chunk;
+    g.cap = (m0 + g.nseg - 1) / g.nseg;
+    if (g.cap < 1) g.cap = 1;
+    g.split = g.chunks > 1 && m0 >= kSplitDegree * (int64_t)n && g.nseg_chunk >= 2 ? 2 : 1;
+    g.cut = std::max(1, g.nseg_chunk / kFirstLaunch);
+    return g;
+}
+
+// The first launch of the first pass, enqueued before the route is known
+// (while the host fits the degree distribution).  Only on lists cut into
+// several chunks; run_sv(..., spec) then goes on from it.  It needs no
+// result of the degree pass: every id is range-checked by the pass itself.
+int sv_speculate(Call& c, const SvInput& in0, SvSpec* spec) {
+    spec->launched = false;
+    if (!in0.soa || in0.m <= 0) return CC_OK;
+    const SvGeom g = sv_geometry(in0.m, c.n);
+    if (g.chunks <= 1) return CC_OK;
+    Workspace& ws = *c.ws;
+    const size_t slots = (size_t)g.nseg * (size_t)g.cap;
+    void *pbuf0, *phook, *pcnt, *ptot;
+    int rc;
+    if ((rc = ws.get(WS_EDGES0, slots * sizeof(int2), &pbuf0))) return rc;
+    if ((rc = ws.get(WS_HOOKED, slots * sizeof(int32_t), &phook))) return rc;
+    if ((rc = ws.get(WS_SEGCOUNT, (size_t)g.nseg * 7 * sizeof(uint32_t), &pcnt))) return rc;
+    if ((rc = ws.get(WS_TOTALS, 64 * sizeof(unsigned long long), &ptot))) return rc;
+    unsigned long long* totals = (unsigned long long*)ptot;
+    hipError_t e = hipMemsetAsync(totals, 0, 64 * sizeof(unsigned long long), c.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    // the same arrays and launch as run_sv's first: survivors to segment
+    // buffer 0 with counts in array 1, hooks counted in array 3
+    const int s1 = g.split == 2 ? g.cut : g.nseg_chunk;
+    SegList out{(int2*)pbuf0, g.cap, g.nseg, (uint32_t*)pcnt + (size_t)1 * g.nseg};
+    spec->t0 = c.timer->mark();
+    int k0 = c.kbeg();
+    e = launch_sv_pass_soa(in0.u, in0.v, in0.m, c.n, c.parent, out, 0, s1, 1, 1, (int32_t*)phook,
+                           (uint32_t*)pcnt + (size_t)3 * g.nseg, totals, (uint32_t*)pcnt + (size_t)4 * g.nseg, nullptr,
+                           nullptr, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "sv_pass launch");
+    spec->rec = c.kend(CC_K_SV_PASS, k0, 16.0 * (double)std::min<int64_t>(in0.m, (int64_t)s1 * g.cap));
+    spec->t1 = c.timer->mark();
+    spec->launched = true;
+    return CC_OK;
+}
+
+int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes, const SvSpec* spec) {
     Workspace& ws = *c.ws;
     const int64_t m0 = in0.soa ? in0.m : 0;
+    const bool resume = spec && spec->launched && in0.soa;
     int nseg;
     int64_t cap;
     int chunks = 1, nseg_chunk = 0;
+    SvGeom geom;
     if (in0.soa) {
-        chunks = pass0_chunks(m0, c.n);
-        nseg_chunk = choose_nseg((m0 + chunks - 1) / chunks);
-        nseg = chunks * nseg_chunk;
-        cap = (m0 + nseg - 1) / nseg;
-        if (cap < 1) cap = 1;
+        geom = sv_geometry(m0, c.n);
+        chunks = geom.chunks;
+        nseg_chunk = geom.nseg_chunk;
+        nseg = geom.nseg;
+        cap = geom.cap;
     } else {
         nseg = in0.seg.nseg;
         cap = in0.seg.cap;
@@ -446,7 +525,8 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
     }
     int2* bufs[2] = {(int2*)pbuf0, (int2*)pbuf1};
 
-    hipError_t e = hipMemsetAsync(totals, 0, 64 * sizeof(unsigned long long), c.stream);
+    // (resuming after sv_speculate: its launch's counters are already in totals)
+    hipError_t e = resume ? hipSuccess : hipMemsetAsync(totals, 0, 64 * sizeof(unsigned long long), c.stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
 
     bool in_soa = in0.soa;
@@ -481,8 +561,8 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
         if (in_soa) {
             // chunk k covers segments [k * nseg_chunk, (k + 1) * nseg_chunk);
             // on dense graphs the first chunk is launched as [0, cut), [cut, nseg_chunk)
-            const int split = chunks > 1 && m0 >= kSplitDegree * (int64_t)c.n && nseg_chunk >= 2 ? 2 : 1;
-            const int cut = std::max(1, nseg_chunk / kFirstLaunch);
+            const int split = geom.split;
+            const int cut = geom.cut;
             // On dense lists (more than kMergeAfter + 2 chunks) the chunks from
             // kMergeAfter on run as one launch: by then the largest tree's
             // bitmap drops nearly all of their edges, and the flattens, picks
@@ -498,6 +578,14 @@ int run_sv(Call& c, const SvInput& in0, int policy, double theta, int max_passes
                     const int s1 = k >= merge_at ? chunks * nseg_chunk
                                  : k > 0 ? (k + 1) * nseg_chunk : (split == 1 || part == 1 ? nseg_chunk : cut);
                     const bool filt = s0 > 0 && gbits;
+                    if (resume && pass == 0 && k == 0 && part == 0) {
+                        // this launch was enqueued by sv_speculate, with the same
+                        // segments, arrays and hook rule (R2's later attempts only
+                        // add hooks, so its first launch may use R1's)
+                        rec_pass = spec->rec;
+                        chain = -1;   // the fit's kernels and copies ran after it
+                        continue;
+                    }
                     if (s0 > 0) {
                         int kf = c.kbeg_after(chain);
                         e = launch_sv_finalize(c.parent, c.n, totals + 6, c.stream);
@@ -819,6 +907,14 @@ CC_API int cc_shutdown(void) {
             if ((e = hipMemPoolDestroy(kv.second)) != hipSuccess && rc == CC_OK) rc = hip_fail(e, "hipMemPoolDestroy");
         }
         g_pools.clear();
+    }
+    {
+        std::lock_guard<std::mutex> g(g_side_mu);
+        for (auto& kv : g_side) {
+            if (hipSetDevice(kv.first) != hipSuccess) continue;
+            if ((e = hipStreamDestroy(kv.second)) != hipSuccess && rc == CC_OK) rc = hip_fail(e, "hipStreamDestroy");
+        }
+        g_side.clear();
     }
     {
         std::lock_guard<std::mutex> g(g_stage_mu);

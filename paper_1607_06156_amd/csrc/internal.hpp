@@ -98,6 +98,9 @@ int pool_workspace(Workspace* ws, hipStream_t s);
 
 int acquire_workspace(Workspace** out);
 
+// the device's second stream (created on first use, destroyed by cc_shutdown)
+int side_stream(hipStream_t* out);
+
 // true when a pending cc_debug_fail_alloc countdown makes this allocation fail
 bool alloc_fault();
 
@@ -186,9 +189,18 @@ struct SvInput {
     SegList seg{};       // when !soa: list in WS_EDGES0
 };
 
+// The first pass's first launch, enqueued ahead of the route decision.
+struct SvSpec {
+    bool launched = false;
+    int rec = -1;          // its kernel record (profiling)
+    int t0 = -1, t1 = -1;  // timer marks around it
+};
+
 int choose_nseg(int64_t m);
 int pass0_chunks(int64_t m, int32_t n);
-int run_sv(Call& c, const SvInput& in, int policy, double theta, int max_passes);
+int sv_speculate(Call& c, const SvInput& in, SvSpec* spec);
+// spec: resume after sv_speculate on the same list (its launch is not repeated)
+int run_sv(Call& c, const SvInput& in, int policy, double theta, int max_passes, const SvSpec* spec = nullptr);
 int run_label(Call& c);
 
 // result of the degree pass (prediction step)
@@ -207,6 +219,9 @@ struct DegreeResult {
     int64_t hub_min = 0;               // hub threshold from the power-law fit (0: none)
     bool csr_built = false;
     bool prefetch_tail = false;        // set by the caller: read the tail back with the histograms
+    // set by the caller: enqueue this SV launch before waiting for the
+    // histograms (sv_speculate on the caller's list)
+    SvSpec* spec = nullptr;
     const int32_t* tail_host = nullptr;   // the first tail_host_n tail entries, in pinned host memory
     int64_t tail_host_n = 0;
     int64_t* off = nullptr;

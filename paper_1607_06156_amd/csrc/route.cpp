@@ -152,8 +152,27 @@ int run_degree_pass(Call& c, bool want_csr, DegreeResult* r) {
                            hipMemcpyDeviceToHost, c.stream);
     }
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(hist)");
-    e = hipStreamSynchronize(c.stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (r->spec && !r->spec->launched) {
+        // The SV route's first launch goes in behind the readback, so the GPU
+        // labels while the host fits the degree distribution; only the
+        // readback is waited for.
+        hipEvent_t ev;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        e = hipEventRecord(ev, c.stream);
+        SvInput in;
+        in.soa = true;
+        in.u = c.u;
+        in.v = c.v;
+        in.m = c.m;
+        rc = e == hipSuccess ? sv_speculate(c, in, r->spec) : CC_OK;
+        if (e == hipSuccess) e = hipEventSynchronize(ev);
+        (void)hipEventDestroy(ev);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        if (rc) return rc;
+    } else {
+        e = hipStreamSynchronize(c.stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
     if (host[64 + kExactBins + 3] == 0 || attempt > 0) break;
     }
     if (host[64 + kExactBins + 2])
@@ -197,8 +216,17 @@ int decide_heuristic(Call& c, DegreeResult& r, int* route) {
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
         tail = dst;
     }
+    // With a speculative SV launch in the call's stream, the fit goes to the
+    // second stream and runs beside it.  Its inputs come from the host and its
+    // scratch is WS_KS, which that launch does not touch; a stream-ordered
+    // pool allocation belongs to the call's stream, so that mode keeps it.
+    hipStream_t ks_s = c.stream;
+    if (r.spec && r.spec->launched && c.ws->mode != Workspace::kPool) {
+        hipStream_t side;
+        if (side_stream(&side) == CC_OK) ks_s = side;
+    }
     KsResult k;
-    int rc = ks_fit(*c.ws, c.stream, r.histx.data(), tail, ntail, &k);
+    int rc = ks_fit(*c.ws, ks_s, r.histx.data(), tail, ntail, &k);
     if (rc) return rc;
     if (c.stats) {
         c.stats->ks_statistic = k.ks;
@@ -529,6 +557,7 @@ int run_label(Call& c) {
     const bool can_predict = bucket_plan(c.n, c.m, &probe) == 0 && c.m < (int64_t)1 << 31;
     int route = CC_R1_SV;
     DegreeResult dr;
+    SvSpec spec;
     int rc;
     int tp0 = c.timer->mark();
     if (req == CC_ROUTE_SV) route = CC_R1_SV;
@@ -538,20 +567,34 @@ int run_label(Call& c) {
         if ((rc = run_degree_pass(c, true, &dr))) return rc;
         route = CC_R0_BFS_SV;
     } else {
+        // the SV route's first launch runs while the host decides (sv_speculate)
         dr.prefetch_tail = req == CC_ROUTE_HEURISTIC;
-        if ((rc = run_degree_pass(c, false, &dr))) return rc;
-        if (req == CC_ROUTE_HEURISTIC) rc = decide_heuristic(c, dr, &route);
-        else rc = decide_router(c, dr, &route);
-        if (rc) return rc;
+        dr.spec = &spec;
+        rc = run_degree_pass(c, false, &dr);
+        if (rc == CC_OK) rc = req == CC_ROUTE_HEURISTIC ? decide_heuristic(c, dr, &route) : decide_router(c, dr, &route);
+        if (rc) {
+            if (spec.launched) (void)hipStreamSynchronize(c.stream);   // no kernel outlives the call
+            return rc;
+        }
     }
     int tp1 = c.timer->mark();
+    // the speculative launch counts as SV time, not prediction
+    const double spec_ms = spec.launched ? c.timer->ms(spec.t0, spec.t1) : 0.0;
     if (c.stats) {
         c.stats->route = route;
-        c.stats->ms_predict = c.timer->ms(tp0, tp1);
+        c.stats->ms_predict = c.timer->ms(tp0, tp1) - spec_ms;
     }
     if (route == CC_R0_BFS_SV) {
-        if (dr.argmax < 0) route = CC_R1_SV;   // no edge with a valid endpoint: nothing to traverse
-        else return run_bfs_route(c, dr);
+        if (dr.argmax < 0) {
+            route = CC_R1_SV;   // no edge with a valid endpoint: nothing to traverse
+        } else {
+            if (spec.launched) {
+                // the BFS route starts from single vertices: undo the speculative hooks
+                hipError_t e = launch_sv_init(c.parent, c.n, c.stream);
+                if (e != hipSuccess) return hip_fail(e, "sv_init launch");
+            }
+            return run_bfs_route(c, dr);
+        }
     }
     if (dr.deg && dr.hub_min > 0 && dr.hub_min < INT32_MAX) {
         c.hub_deg = dr.deg;
@@ -563,9 +606,9 @@ int run_label(Call& c) {
     in.v = c.v;
     in.m = c.m;
     int t0 = c.timer->mark();
-    rc = run_sv(c, in, route, c.opt.theta, c.opt.max_passes);
+    rc = run_sv(c, in, route, c.opt.theta, c.opt.max_passes, &spec);
     int t1 = c.timer->mark();
-    if (c.stats) c.stats->ms_sv = c.timer->ms(t0, t1);
+    if (c.stats) c.stats->ms_sv = c.timer->ms(t0, t1) + spec_ms;
     return rc;
 }
 

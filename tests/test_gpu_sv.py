@@ -216,3 +216,28 @@ def test_hub_table_full_bucket():
     assert st["route"] == ccmi.R1_SV and 12 <= st["sv_hubs"] <= 2048
     assert st["giant_dropped"] > g.m // 2
     assert_labels_equal(lab, oracle_labels(g), g.name)
+
+
+@pytest.mark.parametrize("name,tau,taken", [("rmat18", 1e-300, 1), ("rmat18", 1.0, 0), ("grid2048", 1e-300, 1)])
+def test_first_launch_ahead_of_the_decision(name, tau, taken):
+    """On lists cut into several first-pass chunks (m >= 2^22) the SV
+    route's first launch is enqueued behind the degree pass, before the host
+    has fitted the degree distribution (the fit runs on a second stream
+    beside it).  Taking R1 goes on from that launch (not repeating it);
+    taking R0 resets the forest and runs the BFS route.  Labels are exact
+    either way, on a dense list (first launch 1/64 of the edges) and a
+    sparse one (the whole first chunk).  The lattice's degrees leave the
+    power-law fit no candidate cutoff, so no tau sends it to R0."""
+    g = gen.workload(name) if name != "grid2048" else gen.grid(2048, 0.7, seed=5)
+    assert g.m >= 1 << 22
+    say(f"[gpu] {g.name} m={g.m} tau={tau}")
+    for scratch in ("cached", "pool"):
+        lab, st = ccmi.label(to_dev(g.u), to_dev(g.v), g.n, route="heuristic", tau=tau, stats=True, profile=True,
+                             scratch=scratch)
+        assert st["route"] == taken
+        assert_labels_equal(lab, oracle_labels(g), f"{g.name}/tau={tau}/{scratch}")
+        assert st["ms_predict"] > 0 and st["ms_sv"] > 0
+        if taken == 1:
+            # R1's passes each take at least one launch, the first pass several
+            k = ccmi.KERNEL_CLASSES.index("sv_pass")
+            assert st["kernel_launches"][k] >= st["sv_passes"] + 1
