@@ -23,9 +23,14 @@
  *  - The caller owns every array it passes; inputs are never modified; outputs
  *    are written only on success (on CC_ERANGE the labels are undefined).
  *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All device
- *    work is enqueued on it.  Calls return after their results are complete
- *    (they read small device counters to drive their loops), i.e. they are
- *    host-synchronous with respect to `stream`.
+ *    work on the caller's arrays is enqueued on it.  Calls return after their
+ *    results are complete (they read small device counters to drive their
+ *    loops), i.e. they are host-synchronous with respect to `stream`.  One
+ *    exception to the single stream: when the heuristic route fits the degree
+ *    distribution while a first SV launch runs (lists of 2^22 edges or more,
+ *    cached or caller scratch), the fit's kernel runs on a second stream the
+ *    library keeps per device; it reads only the library's own scratch and
+ *    has finished before the call goes on.
  *  - Scratch memory of cc_label / cc_label_ex comes from one of three
  *    places (cc_options.scratch, cc_options.workspace):
  *      the caller's device block of at least cc_workspace_size() bytes
